@@ -1,0 +1,178 @@
+/*
+ * CPU oracle of the Hough-transform track finder -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only tests, the smoke check and the CPU-baseline leg of the benchmark may
+ * load this library.  The product path never calls it and shares no code with
+ * it.  It is deliberately plain: one thread, loops in the order of the
+ * definition, no blocking, no vectorisation tricks.
+ *
+ * What it computes (Section 3, "The Hough transform ..." paragraph): every
+ * track hypothesis starts with zero votes; every hit adds one vote to every
+ * hypothesis it is compatible with; local maxima of the vote array are then
+ * the track candidates.
+ *
+ * Track model (transverse plane, units cm).  A hypothesis (d0, phi0, kappa)
+ * is the circle whose point of closest approach to the origin is
+ * P0 = (-d0 sin phi0, d0 cos phi0), moving along (cos phi0, sin phi0) there,
+ * with signed curvature kappa.  For a fixed (d0, phi0) and a hit h = (x, y)
+ * exactly one kappa puts h on that circle:
+ *     u     = y cos(phi0) - x sin(phi0)       (signed offset of h along the
+ *                                             normal at P0, plus d0)
+ *     kappa = 2 (u - d0) / (r^2 - 2 d0 u + d0^2),   r^2 = x^2 + y^2
+ * i.e. twice the offset of h from the tangent line at P0 over the squared
+ * chord |h - P0|^2.  At d0 = 0 this is 2 sin(phi_h - phi0) / r.
+ *
+ * Binning and arithmetic (the paper fixes neither; this is the reading used):
+ *   - every operation is one IEEE-754 binary32 operation, round to nearest
+ *     even, evaluated in the order C parses the expressions below; no
+ *     contraction into FMA (build with -ffp-contract=off), denormals kept;
+ *   - the phi0 bin-centre cosines/sines and d0 bin centres are inputs;
+ *   - kf = (kappa - kappa_min) * kappa_scale; the vote lands in kappa bin
+ *     (int)kf when 0 <= kf < n_kappa; NaN or infinite kf casts no vote;
+ *   - a 2D grid is the 3D definition with one d0 bin at d0 = +0.
+ *
+ * Peak rule (Section 3: "looking for local maxima in the parameter space"):
+ * a cell with v >= threshold is a candidate when, for every neighbour w at
+ * offset o in {-1,0,1}^3 \ {0} (d0, phi0, kappa order), v > w if o is
+ * lexicographically negative and v >= w otherwise.  phi0 is periodic; d0 and
+ * kappa neighbours outside the grid are ignored.  Candidates are sorted by
+ * votes descending, then cell index ascending, cell = (l*n_phi + j)*n_kappa + k.
+ *
+ * Parity pins live in tests/test_oracle_pins.py.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Vote every hit into the accumulator (Section 3).  acc is int64 [n_d0][n_phi][n_kappa],
+ * overwritten.  d0 == NULL means a 2D grid (n_d0 must be 1, d0 = +0).  Returns the number
+ * of votes cast, or -1 on invalid arguments. */
+int64_t hough_oracle_vote(int64_t n_hits, const float *x, const float *y,
+                          int32_t n_d0, const float *d0,
+                          int32_t n_phi, const float *cos_phi, const float *sin_phi,
+                          int32_t n_kappa, float kappa_min, float kappa_scale,
+                          int64_t *acc)
+{
+    if (n_hits < 0 || n_d0 < 1 || n_phi < 1 || n_kappa < 1 || !acc)
+        return -1;
+    if (d0 == NULL && n_d0 != 1)
+        return -1;
+    int64_t cells = (int64_t)n_d0 * n_phi * n_kappa;
+    memset(acc, 0, (size_t)cells * sizeof(int64_t));
+    const float n_kappa_f = (float)n_kappa;
+    int64_t votes = 0;
+    for (int64_t i = 0; i < n_hits; ++i) {
+        float xi = x[i];
+        float yi = y[i];
+        float r2 = xi * xi + yi * yi;
+        for (int32_t l = 0; l < n_d0; ++l) {
+            float d = d0 ? d0[l] : 0.0f;
+            for (int32_t j = 0; j < n_phi; ++j) {
+                float c = cos_phi[j];
+                float s = sin_phi[j];
+                float u = yi * c - xi * s;
+                float num = 2.0f * (u - d);
+                float den = r2 - 2.0f * d * u + d * d;
+                float kappa = num / den;
+                float kf = (kappa - kappa_min) * kappa_scale;
+                if (kf >= 0.0f && kf < n_kappa_f) {
+                    int32_t k = (int32_t)kf;
+                    acc[((int64_t)l * n_phi + j) * n_kappa + k] += 1;
+                    votes += 1;
+                }
+            }
+        }
+    }
+    return votes;
+}
+
+typedef struct {
+    int64_t votes;
+    int64_t cell;
+} oracle_cand;
+
+static int cand_order(const void *pa, const void *pb)
+{
+    const oracle_cand *a = (const oracle_cand *)pa;
+    const oracle_cand *b = (const oracle_cand *)pb;
+    if (a->votes != b->votes)
+        return a->votes > b->votes ? -1 : 1;
+    if (a->cell != b->cell)
+        return a->cell < b->cell ? -1 : 1;
+    return 0;
+}
+
+/* Is cell (l, j, k) with value v a local maximum under the tie rule above? */
+static int is_local_max(int32_t n_d0, int32_t n_phi, int32_t n_kappa, const int64_t *acc,
+                        int32_t l, int32_t j, int32_t k, int64_t v)
+{
+    for (int od = -1; od <= 1; ++od) {
+        for (int op = -1; op <= 1; ++op) {
+            for (int ok = -1; ok <= 1; ++ok) {
+                if (od == 0 && op == 0 && ok == 0)
+                    continue;
+                int32_t ll = l + od;
+                int32_t kk = k + ok;
+                if (ll < 0 || ll >= n_d0 || kk < 0 || kk >= n_kappa)
+                    continue;
+                int32_t jj = j + op;
+                if (jj < 0)
+                    jj += n_phi;
+                if (jj >= n_phi)
+                    jj -= n_phi;
+                int64_t w = acc[((int64_t)ll * n_phi + jj) * n_kappa + kk];
+                int negative = od != 0 ? od < 0 : (op != 0 ? op < 0 : ok < 0);
+                if (negative ? !(v > w) : !(v >= w))
+                    return 0;
+            }
+        }
+    }
+    return 1;
+}
+
+/* Threshold + local-maximum search + sort (Section 3).  Writes the first min(n_found, cap)
+ * candidates to out_votes/out_cell (either may be NULL when cap == 0).  Returns n_found,
+ * or -1 on invalid arguments / allocation failure. */
+int64_t hough_oracle_peaks(int32_t n_d0, int32_t n_phi, int32_t n_kappa, const int64_t *acc,
+                           int64_t threshold, int64_t cap, int64_t *out_votes, int64_t *out_cell)
+{
+    if (n_d0 < 1 || n_phi < 3 || n_kappa < 1 || !acc || cap < 0)
+        return -1;
+    int64_t n_found = 0;
+    int64_t room = 1024;
+    oracle_cand *list = (oracle_cand *)malloc((size_t)room * sizeof(oracle_cand));
+    if (!list)
+        return -1;
+    for (int32_t l = 0; l < n_d0; ++l) {
+        for (int32_t j = 0; j < n_phi; ++j) {
+            for (int32_t k = 0; k < n_kappa; ++k) {
+                int64_t cell = ((int64_t)l * n_phi + j) * n_kappa + k;
+                int64_t v = acc[cell];
+                if (v < threshold)
+                    continue;
+                if (!is_local_max(n_d0, n_phi, n_kappa, acc, l, j, k, v))
+                    continue;
+                if (n_found == room) {
+                    room *= 2;
+                    oracle_cand *grown = (oracle_cand *)realloc(list, (size_t)room * sizeof(oracle_cand));
+                    if (!grown) {
+                        free(list);
+                        return -1;
+                    }
+                    list = grown;
+                }
+                list[n_found].votes = v;
+                list[n_found].cell = cell;
+                n_found += 1;
+            }
+        }
+    }
+    qsort(list, (size_t)n_found, sizeof(oracle_cand), cand_order);
+    int64_t n_out = n_found < cap ? n_found : cap;
+    for (int64_t i = 0; i < n_out; ++i) {
+        out_votes[i] = list[i].votes;
+        out_cell[i] = list[i].cell;
+    }
+    free(list);
+    return n_found;
+}

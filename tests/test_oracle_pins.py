@@ -1,0 +1,382 @@
+"""Pins of the CPU oracle to facts other than itself (CPU only).
+
+Each test checks the oracle against something fixed by the geometry of the
+track model (Section 3), a closed form, a library routine or a hand-derived
+fixture -- never against a retyped copy of its own formula.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+import synth
+from synth.grids import Grid, make_grid
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tiny_exact.json")
+
+# The library under test.  tests/test_oracle_mutants.py swaps in oracle builds with a
+# planted mistake and checks that these pins catch it.
+LIBRARY = [None]
+
+
+def vote(x, y, grid):
+    return oracle.vote(x, y, grid, library=LIBRARY[0])
+
+
+def peaks(acc, threshold, cap=None):
+    return oracle.peaks(acc, threshold, cap, library=LIBRARY[0])
+
+
+def _grid_from_tables(n_phi, n_kappa, kappa_min, kappa_scale, cos_phi, sin_phi, d0=None, acc="i32"):
+    return Grid(n_d0=1 if d0 is None else len(d0), n_phi=n_phi, n_kappa=n_kappa,
+                kappa_min=np.float32(kappa_min), kappa_scale=np.float32(kappa_scale),
+                cos_phi=np.asarray(cos_phi, np.float32), sin_phi=np.asarray(sin_phi, np.float32),
+                d0=None if d0 is None else np.asarray(d0, np.float32), acc_type=acc)
+
+
+# --------------------------------------------------------------------------------------
+# Hand-derived exact fixture
+# --------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def test_golden_2d_votes_per_hit(golden):
+    g = golden["grid_2d"]
+    grid = _grid_from_tables(g["n_phi"], g["n_kappa"], g["kappa_min"], g["kappa_scale"],
+                             g["cos_phi"], g["sin_phi"])
+    for (x, y), row in zip(golden["hits_2d"], golden["votes_2d"]):
+        acc, n = vote([x], [y], grid)
+        expect = np.zeros(grid.shape, np.int64)
+        for j, k in enumerate(row):
+            if k is not None:
+                expect[0, j, k] = 1
+        np.testing.assert_array_equal(acc, expect, err_msg=f"hit {(x, y)}")
+        assert n == sum(k is not None for k in row)
+
+
+def test_golden_2d_accumulator_and_peaks(golden):
+    g = golden["grid_2d"]
+    grid = _grid_from_tables(g["n_phi"], g["n_kappa"], g["kappa_min"], g["kappa_scale"],
+                             g["cos_phi"], g["sin_phi"])
+    hx, hy = np.array(golden["hits_2d"], np.float32).T
+    acc, n = vote(hx, hy, grid)
+    expect = np.zeros(grid.shape, np.int64)
+    for j, k, v in golden["acc_2d_nonzero"]:
+        expect[0, j, k] = v
+    np.testing.assert_array_equal(acc, expect)
+    assert n == golden["n_votes_2d"]
+    for key, t in (("T2", 2), ("T1", 1)):
+        want = golden["peaks_2d"][key]
+        v, c, nf = peaks(acc, t)
+        assert nf == want["n_found"]
+        assert v.tolist() == want["votes"]
+        assert c.tolist() == want["cells"]
+
+
+def test_golden_3d_votes(golden):
+    g = golden["grid_3d"]
+    grid = _grid_from_tables(g["n_phi"], g["n_kappa"], g["kappa_min"], g["kappa_scale"],
+                             g["cos_phi"], g["sin_phi"], d0=g["d0"], acc="u16")
+    total = np.zeros(grid.shape, np.int64)
+    for (x, y), table in zip(golden["hits_3d"], golden["votes_3d"]):
+        acc, n = vote([x], [y], grid)
+        expect = np.zeros(grid.shape, np.int64)
+        for l, row in enumerate(table):
+            for j, k in enumerate(row):
+                if k is not None:
+                    expect[l, j, k] = 1
+        np.testing.assert_array_equal(acc, expect, err_msg=f"hit {(x, y)}")
+        total += expect
+    hx, hy = np.array(golden["hits_3d"], np.float32).T
+    acc, n = vote(hx, hy, grid)
+    np.testing.assert_array_equal(acc, total)
+    assert n == golden["n_votes_3d"]
+
+
+# --------------------------------------------------------------------------------------
+# Geometry: hits placed on known circles (circle-circle intersection, no Hough formula)
+# --------------------------------------------------------------------------------------
+
+def _edge_distance(kf):
+    return np.abs(kf - np.round(kf))
+
+
+@pytest.mark.parametrize("displaced", [False, True])
+def test_known_circles_vote_their_own_kappa_bin(displaced):
+    """A track's hits, evaluated at the track's own (d0, phi0), all land in the bin of its kappa."""
+    rng = np.random.default_rng(11)
+    n_kappa = 4096
+    checked = 0
+    for _ in range(120):
+        phi0 = rng.uniform(0, 2 * math.pi)
+        kappa = rng.uniform(-1 / 34, 1 / 34)
+        d0 = float(np.float32(rng.uniform(-20, 20))) if displaced else 0.0
+        ev = synth.gen_tracks_event([d0], [phi0], [kappa])
+        r = np.hypot(ev.x.astype(np.float64), ev.y.astype(np.float64))
+        keep = np.abs(r - abs(d0)) > 1.0           # well-conditioned chords only
+        if keep.sum() < 3:
+            continue
+        tab = phi0 + np.array([0.0, 2 * math.pi / 3, 4 * math.pi / 3])
+        grid = make_grid(3, n_kappa, phi_table=tab)
+        if displaced:
+            grid = Grid(**{**grid.__dict__, "d0": np.array([d0], np.float32), "acc_type": "u16"})
+        kf = (kappa - float(grid.kappa_min)) * float(grid.kappa_scale)
+        if _edge_distance(kf) < 0.05:
+            continue
+        acc, n = vote(ev.x[keep], ev.y[keep], grid)
+        assert acc[0, 0, int(math.floor(kf))] == keep.sum(), (phi0, kappa, d0)
+        checked += 1
+    assert checked > 60
+
+
+def _bin_centre_track(grid, l, j, k):
+    phi0 = float(grid.phi_centre(j))
+    kappa = float(grid.kappa_centre(k))
+    d0 = float(grid.d0[l]) if grid.is_3d else 0.0
+    return d0, phi0, kappa
+
+
+@pytest.mark.parametrize("which", ["small2d", "big2d", "3d"])
+def test_bin_centre_tracks_peak_at_their_bin(which):
+    """Noise-free tracks at bin centres give #hits votes at the true cell and at the mirror cell
+    (d0, phi0, kappa) -> (-d0, phi0 + pi, -kappa), and the candidate list holds them."""
+    grid = {"small2d": synth.GRID_2D_SMALL, "big2d": synth.GRID_2D, "3d": synth.GRID_3D}[which]
+    rng = np.random.default_rng(5)
+    done = 0
+    while done < 6:
+        l = int(rng.integers(0, grid.n_d0))
+        j = int(rng.integers(0, grid.n_phi))
+        # |kappa| below 1/60 keeps every layer reachable
+        k = int(rng.integers(int(grid.n_kappa * 0.25), int(grid.n_kappa * 0.75)))
+        d0, phi0, kappa = _bin_centre_track(grid, l, j, k)
+        if grid.is_3d and np.min(np.abs(synth.LAYERS_CM - abs(d0))) < 2.0:
+            continue
+        ev = synth.gen_tracks_event([d0], [phi0], [kappa])
+        if ev.n_hits < 5:
+            continue
+        acc, n = vote(ev.x, ev.y, grid)
+        mirror = (grid.n_d0 - 1 - l, (j + grid.n_phi // 2) % grid.n_phi, grid.n_kappa - 1 - k)
+        assert acc[l, j, k] == ev.n_hits
+        assert acc[mirror] == ev.n_hits
+        assert acc.max() == ev.n_hits
+        v, c, nf = peaks(acc, ev.n_hits)
+        cells = set(c.tolist())
+        for (a, b, cc) in ((l, j, k), mirror):
+            cell = (a * grid.n_phi + b) * grid.n_kappa + cc
+            if grid.is_3d:
+                # a d0 neighbour may tie; the surviving cell is within one bin of the truth
+                near = [x for x in cells
+                        if abs(x // (grid.n_phi * grid.n_kappa) - a) <= 1
+                        and (x // grid.n_kappa) % grid.n_phi == b and x % grid.n_kappa == cc]
+                assert near, (which, l, j, k)
+            else:
+                assert cell in cells, (which, l, j, k)
+        done += 1
+
+
+def test_prompt_closed_form_single_hits():
+    """At d0 = 0 the curvature is 2 sin(phi_h - phi0) / r (evaluated with atan2/sin in fp64):
+    each single hit votes exactly once in each phi0 row where that value is in range."""
+    grid = synth.GRID_2D_SMALL
+    rng = np.random.default_rng(3)
+    phis = grid.phi_centre(np.arange(grid.n_phi))
+    for _ in range(40):
+        r = rng.choice(synth.LAYERS_CM)
+        ph = rng.uniform(0, 2 * math.pi)
+        x, y = np.float32(r * math.cos(ph)), np.float32(r * math.sin(ph))
+        acc, n = vote([x], [y], grid)
+        rh = math.hypot(float(x), float(y))
+        phh = math.atan2(float(y), float(x))
+        kap = 2.0 * np.sin(phh - phis) / rh
+        kf = (kap - float(grid.kappa_min)) * float(grid.kappa_scale)
+        row_sums = acc[0].sum(axis=1)
+        assert set(np.unique(row_sums)) <= {0, 1}
+        sure = (kf > 1e-3) & (kf < grid.n_kappa - 1e-3) & (_edge_distance(kf) > 1e-3)
+        out = (kf < -1e-3) | (kf > grid.n_kappa + 1e-3)
+        for j in np.nonzero(sure)[0]:
+            assert acc[0, j, int(math.floor(kf[j]))] == 1
+        assert np.all(row_sums[out] == 0)
+        assert n == row_sums.sum()
+
+
+# --------------------------------------------------------------------------------------
+# Invariants and special cases
+# --------------------------------------------------------------------------------------
+
+def test_vote_count_and_row_invariants():
+    ev = synth.gen_config_event(1)
+    grid = synth.GRID_2D_SMALL
+    acc, n = vote(ev.x, ev.y, grid)
+    assert acc.sum() == n
+    assert np.all(acc[0].sum(axis=1) <= ev.n_hits)
+    # one hit at a time: every (hit, row) receives at most one vote, and the
+    # per-hit vote counts add up to the event's
+    total = 0
+    for i in range(0, ev.n_hits, 7):
+        a1, n1 = vote(ev.x[i:i + 1], ev.y[i:i + 1], grid)
+        assert np.all(a1[0].sum(axis=1) <= 1)
+        total += n1
+    assert total > 0
+
+
+def test_hit_permutation_leaves_accumulator_unchanged():
+    ev = synth.gen_config_event(1)
+    grid = synth.GRID_2D_SMALL
+    a1, n1 = vote(ev.x, ev.y, grid)
+    p = np.random.default_rng(0).permutation(ev.n_hits)
+    a2, n2 = vote(ev.x[p], ev.y[p], grid)
+    np.testing.assert_array_equal(a1, a2)
+    assert n1 == n2
+
+
+def test_3d_slice_at_zero_d0_equals_2d():
+    ev = synth.gen_config_event(1)
+    g2 = synth.GRID_2D_SMALL
+    g3 = Grid(**{**g2.__dict__, "n_d0": 3, "d0": np.array([-0.5, 0.0, 0.5], np.float32)})
+    a2, _ = vote(ev.x, ev.y, g2)
+    a3, _ = vote(ev.x, ev.y, g3)
+    np.testing.assert_array_equal(a3[1], a2[0])
+    assert not np.array_equal(a3[0], a2[0])
+
+
+def test_nonfinite_and_origin_hits_cast_no_votes():
+    grid = synth.GRID_2D_SMALL
+    bad = np.array([[np.nan, 1.0], [1.0, np.nan], [np.inf, 2.0], [-np.inf, 0.0],
+                    [0.0, 0.0], [np.inf, np.inf]], np.float32)
+    acc, n = vote(bad[:, 0], bad[:, 1], grid)
+    assert n == 0 and acc.sum() == 0
+    acc3, n3 = vote(bad[:4, 0], bad[:4, 1], synth.GRID_3D)
+    assert n3 == 0
+
+
+def test_empty_event():
+    acc, n = vote(np.zeros(0, np.float32), np.zeros(0, np.float32), synth.GRID_2D_SMALL)
+    assert n == 0 and acc.sum() == 0
+    v, c, nf = peaks(acc, 1)
+    assert nf == 0 and len(v) == 0
+
+
+# --------------------------------------------------------------------------------------
+# Peak rule
+# --------------------------------------------------------------------------------------
+
+def _neighbour_max(acc, strict_centre):
+    """Max over the 3x3(x3) neighbourhood (phi periodic, other edges ignored) via scipy."""
+    a = acc.astype(np.int64)
+    fp = np.ones((3, 3, 3), bool)
+    if strict_centre:
+        fp[1, 1, 1] = False
+    big_neg = np.iinfo(np.int64).min // 2
+    a = np.pad(a, ((0, 0), (1, 1), (0, 0)), mode="wrap")
+    a = np.pad(a, ((1, 1), (0, 0), (1, 1)), mode="constant", constant_values=big_neg)
+    m = ndi.maximum_filter(a, footprint=fp, mode="constant", cval=big_neg)
+    return m[1:-1, 1:-1, 1:-1]
+
+
+def _check_peak_bounds(acc, t):
+    v, c, nf = peaks(acc, t)
+    assert nf == len(c)
+    flat = acc.reshape(-1)
+    # sorted by (votes desc, cell asc); votes match the array
+    assert v.tolist() == flat[c].tolist()
+    assert list(zip((-v).tolist(), c.tolist())) == sorted(zip((-v).tolist(), c.tolist()))
+    weak = (acc >= _neighbour_max(acc, False)) & (acc >= t)
+    strict = (acc > _neighbour_max(acc, True)) & (acc >= t)
+    cand = np.zeros(acc.size, bool)
+    cand[c] = True
+    cand = cand.reshape(acc.shape)
+    assert np.all(cand <= weak)
+    assert np.all(strict <= cand)
+    # no two candidates are neighbours
+    n_d0, n_phi, n_kappa = acc.shape
+    idx = np.argwhere(cand)
+    s = set(map(tuple, idx.tolist()))
+    for (l, j, k) in idx.tolist():
+        for od in (-1, 0, 1):
+            for op in (-1, 0, 1):
+                for ok in (-1, 0, 1):
+                    if od == op == ok == 0:
+                        continue
+                    q = (l + od, (j + op) % n_phi, k + ok)
+                    assert q not in s
+    return v, c, nf
+
+
+@pytest.mark.parametrize("shape,hi", [((1, 7, 9), 3), ((1, 16, 12), 6), ((4, 6, 5), 2), ((3, 5, 7), 9)])
+def test_peaks_bounded_by_scipy_maximum_filter(shape, hi):
+    rng = np.random.default_rng(hash(shape) % 2**32)
+    for _ in range(20):
+        acc = rng.integers(0, hi + 1, size=shape).astype(np.int64)
+        _check_peak_bounds(acc, 1)
+        _check_peak_bounds(acc, hi // 2 + 1)
+
+
+def test_peak_special_cases():
+    # delta
+    acc = np.zeros((1, 8, 8), np.int64)
+    acc[0, 3, 5] = 7
+    v, c, n = peaks(acc, 7)
+    assert n == 1 and c.tolist() == [3 * 8 + 5] and v.tolist() == [7]
+    assert peaks(acc, 8)[2] == 0
+    # constant field: every cell ties an earlier neighbour
+    assert peaks(np.full((1, 5, 6), 9, np.int64), 1)[2] == 0
+    assert peaks(np.full((3, 5, 6), 9, np.int64), 1)[2] == 0
+    # two-cell plateaus keep the earlier cell (along kappa, phi0, d0)
+    acc = np.zeros((1, 8, 8), np.int64)
+    acc[0, 2, 3] = acc[0, 2, 4] = 5
+    assert peaks(acc, 1)[1].tolist() == [2 * 8 + 3]
+    acc = np.zeros((1, 8, 8), np.int64)
+    acc[0, 2, 3] = acc[0, 3, 3] = 5
+    assert peaks(acc, 1)[1].tolist() == [2 * 8 + 3]
+    acc = np.zeros((3, 4, 4), np.int64)
+    acc[0, 1, 1] = acc[1, 1, 1] = 5
+    assert peaks(acc, 1)[1].tolist() == [0 * 16 + 1 * 4 + 1]
+    # the phi0 seam: row n_phi - 1 precedes row 0 through the wrap offset +1
+    acc = np.zeros((1, 8, 8), np.int64)
+    acc[0, 0, 3] = acc[0, 7, 3] = 5
+    assert peaks(acc, 1)[1].tolist() == [7 * 8 + 3]
+    # kappa edges are not periodic
+    acc = np.zeros((1, 8, 8), np.int64)
+    acc[0, 4, 0] = 3
+    acc[0, 4, 7] = 4
+    assert sorted(peaks(acc, 1)[1].tolist()) == [4 * 8 + 0, 4 * 8 + 7]
+
+
+def test_peaks_capacity_truncates_a_prefix():
+    ev = synth.gen_config_event(1)
+    acc, _ = vote(ev.x, ev.y, synth.GRID_2D_SMALL)
+    v, c, n = peaks(acc, 3)
+    assert n > 20
+    v2, c2, n2 = peaks(acc, 3, cap=17)
+    assert n2 == n and v2.tolist() == v[:17].tolist() and c2.tolist() == c[:17].tolist()
+    v3, c3, n3 = peaks(acc, 3, cap=0)
+    assert n3 == n and len(c3) == 0
+
+
+def test_config1_tracks_found():
+    """Physics sanity (not parity): with 256 phi0 bins against 128 kappa bins the phi0 bin
+    width smears the small-radius hits over several kappa bins, so only about 60 % of the 40
+    tracks of workload 1 leave a candidate within 1.6 phi0 bins and 6 kappa bins of the truth."""
+    ev = synth.gen_config_event(1)
+    grid = synth.GRID_2D_SMALL
+    acc, n = vote(ev.x, ev.y, grid)
+    v, c, nf = peaks(acc, 7)
+    j = (c // grid.n_kappa) % grid.n_phi
+    k = c % grid.n_kappa
+    found = 0
+    for p0, k0 in zip(ev.phi0, ev.kappa):
+        jt = p0 / (2 * math.pi / grid.n_phi) - 0.5
+        kt = (k0 - float(grid.kappa_min)) * float(grid.kappa_scale) - 0.5
+        dj = (j - jt + grid.n_phi / 2) % grid.n_phi - grid.n_phi / 2
+        if np.any((np.abs(dj) <= 1.6) & (np.abs(k - kt) <= 6)):
+            found += 1
+    assert found >= 20
