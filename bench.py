@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Hough track finder on one MI355X.
+
+One step = one batch of 256 uneven prompt-track events (200-8,000 tracks
+each, about 2k-100k hits, 1024 phi0 x 512 kappa int32 accumulators,
+threshold 7) through the whole path: vote, peak search and sorted candidate
+lists, launched as one captured graph (hough_event_batch).  Hits are resident
+in HBM before the timed region.  The line also carries the per-event-launch
+rate on the same events, the dominant kernel against its roofline and the
+CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs at up to 2.4 GHz, 64 fp32 lanes per CU per clock for
+# one non-fused, non-packed fp32 operation (157.3 TFLOP/s counts a packed
+# FMA as four flops per lane).
+PEAK_FP32_OPS = 256 * 64 * 2.4e9          # 39.3e12 single fp32 operations / s
+PEAK_LDS_ATOMIC = 256 * 32 * 2.4e9        # 19.7e12 dword atomics / s (32 banks per CU, one per clock)
+FLOPS_PER_EVAL_2D = 7                     # u: 2 mul + 1 sub; 2u: 1 mul; divide: 1; kf: 1 sub + 1 mul
+FLOPS_PER_HIT_2D = 3                      # r^2: 2 mul + 1 add
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--latency-events", type=int, default=64)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch, grid, threshold, budget_s):
+    import oracle
+    oracle.lib()
+    t0 = time.perf_counter()
+    n = 0
+    for ev in batch.events:
+        oracle.find(ev.x, ev.y, grid, threshold)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of the {batch.n_events} events of the batch, vote + peaks + sort, "
+                      f"one thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: events are independent and the path has no cross-GPU step; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1311_2769_amd import hough
+
+    hough.load()                                  # fails loudly if libhough.so is missing
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wc = synth.CONFIGS[4]
+    grid, thr = wc.grid, wc.threshold
+    log(f"generating {args.events} events")
+    batch = synth.gen_batch(4, args.events)
+    n_ev = batch.n_events
+    hit_off = batch.hit_off
+    x = torch.from_numpy(batch.x).to(dev)
+    y = torch.from_numpy(batch.y).to(dev)
+    ctx = hough.HoughContext(grid, device=dev, max_events=n_ev, max_hits=batch.n_hits)
+    cap = ctx.spec.max_candidates()
+    cand_off = np.arange(n_ev + 1, dtype=np.int64) * cap
+    cands = torch.empty((n_ev * cap, 2), dtype=torch.int32, device=dev)
+    n_found = torch.empty(n_ev, dtype=torch.int32, device=dev)
+    n_votes = torch.empty(n_ev, dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.event_batch(hit_off, x, y, thr, cand_off=cand_off, cands=cands, n_found=n_found, n_votes=n_votes)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    votes = int(n_votes.sum().item())
+    evals = int(batch.n_hits) * grid.n_phi * grid.n_d0
+    found = int(n_found.sum().item())
+    ms_step = 1e3 * dt / args.steps
+    events_per_s = n_ev * args.steps / dt
+
+    # Dominant kernel: the batched vote, timed alone with HIP events on its stream.
+    log("timing the batched vote kernel")
+    acc = ctx.new_acc(n_ev)
+    nv2 = torch.empty(n_ev, dtype=torch.int64, device=dev)
+    for _ in range(2):
+        ctx.vote_batch(hit_off, x, y, acc=acc, n_votes=nv2)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    k_launch = max(3, args.steps)
+    e0.record(stream)
+    for _ in range(k_launch):
+        ctx.vote_batch(hit_off, x, y, acc=acc, n_votes=nv2)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    vote_ms = e0.elapsed_time(e1) / k_launch
+    assert int(nv2.sum().item()) == votes
+    flops = evals * FLOPS_PER_EVAL_2D + int(batch.n_hits) * FLOPS_PER_HIT_2D
+    achieved = flops / (vote_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": "vote_kernel (batched, persistent)", "achieved": achieved / 1e12,
+                "peak": PEAK_FP32_OPS / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_OPS,
+                "traffic": None, "launch_ms": vote_ms,
+                "work_per_launch": {"evaluations": evals, "fp32_ops": flops, "votes": votes}}
+    lds = {"achieved": votes / (vote_ms * 1e-3) / 1e12, "peak": PEAK_LDS_ATOMIC / 1e12, "unit": "T atomics/s",
+           "frac": votes / (vote_ms * 1e-3) / PEAK_LDS_ATOMIC}
+
+    # Per-event launch on the same resident events: hough_vote + hough_peaks per event.
+    log("per-event launches")
+    single = hough.HoughContext(grid, device=dev, max_hits=int(np.diff(hit_off).max()))
+    acc1 = single.new_acc()
+    out1 = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    nf1 = torch.empty(1, dtype=torch.int32, device=dev)
+    nv1 = torch.empty(1, dtype=torch.int64, device=dev)
+    views = [(x[hit_off[e]:hit_off[e + 1]], y[hit_off[e]:hit_off[e + 1]]) for e in range(n_ev)]
+    for xe, ye in views[:4]:
+        single.vote(xe, ye, acc1, nv1)
+        single.peaks(acc1, thr, cap, out1, nf1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for xe, ye in views:
+        single.vote(xe, ye, acc1, nv1)
+        single.peaks(acc1, thr, cap, out1, nf1)
+    torch.cuda.synchronize()
+    per_event_rate = n_ev / (time.perf_counter() - t0)
+    # closed loop with host round trips: pinned H2D hits -> vote -> peaks -> D2H list -> sync
+    lat = []
+    hx = torch.from_numpy(batch.x).pin_memory()
+    hy = torch.from_numpy(batch.y).pin_memory()
+    host_out = torch.empty((cap, 2), dtype=torch.int32).pin_memory()
+    xd = torch.empty(int(np.diff(hit_off).max()), dtype=torch.float32, device=dev)
+    yd = torch.empty_like(xd)
+    for e in range(min(args.latency_events, n_ev)):
+        a, b = int(hit_off[e]), int(hit_off[e + 1])
+        ts = time.perf_counter()
+        xd[:b - a].copy_(hx[a:b], non_blocking=True)
+        yd[:b - a].copy_(hy[a:b], non_blocking=True)
+        single.vote(xd[:b - a], yd[:b - a], acc1, nv1)
+        single.peaks(acc1, thr, cap, out1, nf1)
+        n = int(nf1.item())
+        host_out[:n].copy_(out1[:n])
+        lat.append(time.perf_counter() - ts)
+    lat_ms = 1e3 * np.array(lat)
+
+    line = {
+        "metric": "events/s (batched vote + peaks + sorted candidates, one graph per 256-event batch)",
+        "value": events_per_s,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wc.name, "events_per_step": n_ev, "hits_per_step": int(batch.n_hits),
+                   "grid": [grid.n_d0, grid.n_phi, grid.n_kappa], "acc": grid.acc_type, "threshold": thr},
+        "votes_per_s": votes * args.steps / dt,
+        "evals_per_s": evals * args.steps / dt,
+        "candidates_per_step": found,
+        "per_event_launch": {"events_per_s": per_event_rate, "batched_speedup": events_per_s / per_event_rate,
+                             "closed_loop_p50_ms": float(np.percentile(lat_ms, 50)),
+                             "closed_loop_p99_ms": float(np.percentile(lat_ms, 99)),
+                             "closed_loop_events": len(lat)},
+        "roofline": roofline,
+        "lds_atomic_roofline": lds,
+    }
+    if not args.no_cpu:
+        log("oracle sample on the host")
+        line["cpu_baseline"] = cpu_baseline(batch, grid, thr, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * hough.h -- C ABI of the MI355X (gfx950) Hough-transform track finder.
+ *
+ * The library computes the data-parallel part of the Hough track finder
+ * (Section 3): every track hypothesis of a binned parameter space starts with
+ * zero votes, every detector hit adds one vote to each hypothesis it is
+ * compatible with, and the local maxima above a threshold become track
+ * candidates.  Section 3 notes that prompt curved tracks need two parameters
+ * (phi0, kappa) and displaced curved tracks three (d0, phi0, kappa); both are
+ * served here.  Section 4 notes the computation for each hit is independent
+ * of all other hits, which is the parallelism the kernels exploit.
+ *
+ * Track model (transverse plane, cm).  Hypothesis (d0, phi0, kappa) is the
+ * circle whose point of closest approach to the origin is
+ * P0 = (-d0 sin phi0, d0 cos phi0), tangent there to (cos phi0, sin phi0),
+ * with signed curvature kappa (> 0: counter-clockwise).  A hit (x, y) votes,
+ * for each d0 bin l and phi0 bin j, the kappa of the circle through it:
+ *     r2 = x*x + y*y;   u = y*cos_phi[j] - x*sin_phi[j];   d = d0[l]
+ *     kappa = 2*(u - d) / ((r2 - (2*d)*u) + d*d)
+ *     kf = (kappa - kappa_min) * kappa_scale
+ *     if (kf >= 0 && kf < n_kappa) acc[l][j][(int)kf] += 1
+ * Every operation is one IEEE binary32 operation rounded to nearest even, in
+ * exactly this order (no FMA contraction, correctly rounded division,
+ * denormals kept).  NaN/Inf kf casts no vote.  A 2D grid is the d0 = +0 case.
+ * Results (accumulators, vote counts, candidate lists) are therefore exact
+ * integers and do not depend on launch shape, tiling or batching.
+ *
+ * Peak rule.  Cell p = (l, j, k) with v = acc[p] >= threshold is a candidate
+ * when for every neighbour w at offset o in {-1,0,1}^3 \ {0} (order d0, phi0,
+ * kappa; phi0 periodic; d0 and kappa neighbours outside the grid ignored)
+ * v > w if o is lexicographically negative and v >= w otherwise.  Candidates
+ * are sorted by votes descending then cell ascending, with
+ * cell = (l*n_phi + j)*n_kappa + k.
+ *
+ * Conventions for every call:
+ *   - [dev] marks device memory (e.g. a torch tensor's data_ptr()); all other
+ *     pointers are host memory read during the call only.
+ *   - The caller owns every buffer; the context owns only its workspace,
+ *     allocated in hough_ctx_create.  No other call allocates device memory.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream) and
+ *     is asynchronous; results are valid once the stream reaches that point.
+ *   - Argument errors are reported synchronously as HOUGH_EINVAL and enqueue
+ *     nothing.  HIP runtime failures return HOUGH_EDEVICE and
+ *     hough_last_error() describes them.  Calls never throw.
+ *   - Device-side conditions are not errors: a candidate list longer than its
+ *     capacity reports its full length in n_found and writes the first `cap`
+ *     entries of the sorted list.
+ *   - A context may be used by one host thread at a time.  Calls on one
+ *     context must not overlap on different streams (they share workspace).
+ */
+#ifndef HOUGH_H
+#define HOUGH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HOUGH_OK = 0,
+    HOUGH_EINVAL = -1,   /* invalid argument; nothing was enqueued */
+    HOUGH_ENOMEM = -2,   /* workspace allocation failed (context creation only) */
+    HOUGH_EDEVICE = -3   /* a HIP runtime call failed; see hough_last_error() */
+} hough_status;
+
+typedef enum {
+    HOUGH_ACC_I32 = 0,   /* int32 cells */
+    HOUGH_ACC_U16 = 1    /* uint16 cells; requires n_hits <= 65535 per event and even n_kappa */
+} hough_acc_type;
+
+/* The binned parameter space.  Bin tables are shared inputs computed once by
+ * the caller (fp32), so no transcendental is evaluated on the device. */
+typedef struct {
+    int32_t n_d0;            /* d0 bins; 1 with d0 == NULL for the 2D grid */
+    int32_t n_phi;           /* phi0 bins (periodic); >= 3 */
+    int32_t n_kappa;         /* kappa bins; >= 1 */
+    float kappa_min;         /* lower edge of the kappa range (cm^-1) */
+    float kappa_scale;       /* bins per unit kappa (cm) */
+    const float *cos_phi;    /* [dev][n_phi] cos of the phi0 bin centres */
+    const float *sin_phi;    /* [dev][n_phi] sin of the phi0 bin centres */
+    const float *d0;         /* [dev][n_d0] d0 bin centres (cm), or NULL for 2D */
+    int32_t acc_type;        /* hough_acc_type */
+} hough_grid;
+
+typedef struct {
+    int32_t votes;           /* votes of the cell */
+    int32_t cell;            /* (l*n_phi + j)*n_kappa + k */
+} hough_cand;
+
+/* Context sizing.  Zero fields take the defaults noted. */
+typedef struct {
+    int32_t max_events;      /* largest n_events of hough_event_batch (default 1) */
+    int64_t max_hits;        /* largest total hit count of one call (default 1<<20) */
+    const char *tune_cache;  /* JSON file of tuned launch shapes, or NULL */
+} hough_ctx_opts;
+
+typedef struct hough_ctx hough_ctx;
+
+/* Create a context for one grid on the current HIP device.  The bin tables
+ * must stay valid for the context's lifetime.  Allocates all workspace.
+ * EINVAL: null pointers, n_phi < 3, n_kappa < 1, n_d0 < 1, n_d0 > 1 without a
+ * d0 table, u16 with odd n_kappa, more than 2^31 - 1 cells. */
+hough_status hough_ctx_create(hough_ctx **ctx, const hough_grid *grid, const hough_ctx_opts *opts);
+void hough_ctx_destroy(hough_ctx *ctx);
+
+/* Vote one event (Section 3: zero the parameter space, then every hit adds its
+ * votes).  x, y: [dev][n_hits] fp32, cm.  acc: [dev] n_d0*n_phi*n_kappa cells
+ * of the grid's type, 4-byte aligned, overwritten.  n_votes: [dev] one
+ * uint64, overwritten with the number of votes cast (sum of acc), or NULL.
+ * EINVAL: null x/y/acc with n_hits > 0, n_hits < 0, n_hits > max_hits, u16
+ * with n_hits > 65535. */
+hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t n_hits,
+                        void *acc, uint64_t *n_votes, void *stream);
+
+/* Find the local maxima of an accumulator (Section 3: "looking for local
+ * maxima in the parameter space").  acc: [dev] as produced by hough_vote
+ * (any values are accepted).  out: [dev][cap] sorted candidates (may be NULL
+ * when cap == 0).  n_found: [dev] one int32, the full number of candidates.
+ * EINVAL: null acc/n_found, cap < 0, threshold < 1 for u16 is allowed. */
+hough_status hough_peaks(hough_ctx *ctx, const void *acc, int32_t threshold,
+                         hough_cand *out, int32_t cap, int32_t *n_found, void *stream);
+
+/* Vote and find peaks for a batch of independent events in one pass
+ * (Section 4: hits, and so events, are independent).  Equivalent, bit for bit,
+ * to hough_vote followed by hough_peaks on each event.
+ *   hit_off:  host [n_events+1] CSR offsets into x, y (hit_off[0] == 0).
+ *   x, y:     [dev][hit_off[n_events]] fp32 hits of all events, packed.
+ *   acc:      [dev][n_events * cells] accumulators, or NULL to skip storing them.
+ *   cands:    [dev] candidate storage; event e owns [cand_off[e], cand_off[e+1]).
+ *   cand_off: host [n_events+1] nondecreasing capacity offsets.
+ *   n_found:  [dev][n_events] int32 full candidate counts.
+ *   n_votes:  [dev][n_events] uint64 vote counts, or NULL.
+ * The launch sequence is captured once as a HIP graph per stream and
+ * replayed; the per-batch descriptors travel inside the graph.
+ * EINVAL: n_events < 1 or > max_events, bad offsets, total hits > max_hits,
+ * u16 with an event of more than 65535 hits, null required pointers. */
+hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off,
+                               const float *x, const float *y, int32_t threshold,
+                               void *acc, hough_cand *cands, const int64_t *cand_off,
+                               int32_t *n_found, uint64_t *n_votes, void *stream);
+
+/* Vote a batch of independent events (the vote half of hough_event_batch,
+ * without the peak search and without a captured graph): acc receives every
+ * event's accumulator back to back, exactly as hough_vote would write it.
+ *   hit_off: host [n_events+1] CSR offsets; x, y: [dev] packed hits;
+ *   acc: [dev][n_events * cells]; n_votes: [dev][n_events] uint64 or NULL.
+ * EINVAL as for hough_event_batch. */
+hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off,
+                              const float *x, const float *y, void *acc, uint64_t *n_votes,
+                              void *stream);
+
+/* Launch-shape controls (used by the autotuner and tests; results never
+ * depend on them).  which: 0 = single-event vote, 1 = batched vote.
+ * rows: phi0 rows per workgroup tile; threads: workgroup size (256/512/1024);
+ * split: hit chunks per tile for the single-event vote (>= 1); pad: extra
+ * dwords per LDS row (0 or 1).  Invalid combinations return EINVAL. */
+hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32_t threads,
+                              int32_t split, int32_t pad);
+hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows, int32_t *threads,
+                              int32_t *split, int32_t *pad);
+
+const char *hough_status_str(hough_status status);
+/* Text of the last HIP failure seen by this thread (empty if none). */
+const char *hough_last_error(void);
+/* Library version string. */
+const char *hough_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOUGH_H */

@@ -1,0 +1,519 @@
+// C ABI of libhough: contexts, argument checking, workspace and launch
+// sequences.  See include/hough.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hough.h"
+#include "hough_impl.h"
+
+using namespace hough;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hough_status device_error(hipError_t e, const char *what) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
+    g_last_error = buf;
+    return HOUGH_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess)                           \
+            return device_error(e_, #expr);             \
+    } while (0)
+
+// Descriptor block uploaded per batch: a header followed by per-event
+// descriptors and the work list.
+struct BatchHeader {
+    int32_t n_events;
+    int32_t n_items;
+    int32_t pad_[2];
+};
+
+struct GraphKey {
+    const void *x, *y, *acc, *cands, *n_found, *n_votes;
+    int32_t threshold;
+    bool operator==(const GraphKey &o) const {
+        return x == o.x && y == o.y && acc == o.acc && cands == o.cands && n_found == o.n_found &&
+               n_votes == o.n_votes && threshold == o.threshold;
+    }
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct hough_ctx {
+    hough_grid grid;
+    GridArgs g;
+    bool u16;
+    int32_t max_events;
+    int64_t max_hits;
+    int device;
+    VoteShape shape_single;
+    VoteShape shape_batch;
+    int32_t persistent_groups;
+
+    // sort workspace
+    int64_t bound;             // max candidates per event (any pass-0 layout)
+    int32_t hist_chunks;
+    int32_t n_chunks0;         // peak blocks per event
+    int32_t cap0;              // peak block capacity
+    EventState *state = nullptr;
+    Cand *stage = nullptr;     // also the second ping-pong buffer
+    int32_t *cnt0 = nullptr;
+    uint32_t *hist = nullptr;
+    Cand *tmp0 = nullptr;
+    uint32_t *acc_ws = nullptr;   // batch accumulators when the caller passes none
+
+    // batch descriptors
+    size_t desc_bytes = 0;
+    char *desc_host = nullptr;    // pinned
+    char *desc_dev = nullptr;
+    int32_t *work_counter = nullptr;
+    int32_t max_items = 0;
+    hipEvent_t desc_done = nullptr;
+    bool desc_in_flight = false;
+    std::vector<int64_t> last_hit_off, last_cand_off;   // what desc_host currently holds
+    hipStream_t capture_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+void free_ctx(hough_ctx *c) {
+    if (!c)
+        return;
+    for (auto &ge : c->graphs)
+        (void)hipGraphExecDestroy(ge.exec);
+    if (c->desc_done)
+        (void)hipEventDestroy(c->desc_done);
+    if (c->capture_stream)
+        (void)hipStreamDestroy(c->capture_stream);
+    if (c->desc_host)
+        (void)hipHostFree(c->desc_host);
+    void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->desc_dev,
+                   c->work_counter};
+    for (void *p : dev)
+        if (p)
+            (void)hipFree(p);
+    delete c;
+}
+
+int32_t tiles_per_event(const hough_ctx *c, const VoteShape &s) {
+    return c->g.n_d0 * ((c->g.n_phi + s.rows - 1) / s.rows);
+}
+
+SortWork make_sort_work(hough_ctx *c) {
+    SortWork w{};
+    w.s0.stage = c->stage;
+    w.s0.cnt0 = c->cnt0;
+    w.s0.n_chunks0 = c->n_chunks0;
+    w.s0.cap0 = c->cap0;
+    w.hist = c->hist;
+    w.hist_chunks = c->hist_chunks;
+    w.tmp0 = c->tmp0;
+    w.tmp1 = c->stage;
+    w.bound = c->bound;
+    w.state = c->state;
+    w.key_mask = c->u16 ? 0xffffu : 0xffffffffu;
+    return w;
+}
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count) {
+    if (count == 0)
+        count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+
+// Write the batch descriptors (header, per-event ranges, largest-first work
+// list) into the pinned staging block, unless it already holds this batch.
+// *changed tells the caller whether the device copy must be refreshed.
+hough_status stage_descriptors(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off,
+                               const int64_t *cand_off, bool *changed) {
+    const size_t n = static_cast<size_t>(n_events) + 1;
+    std::vector<int64_t> co(n, 0);
+    if (cand_off)
+        co.assign(cand_off, cand_off + n);
+    if (ctx->last_hit_off.size() == n && std::equal(hit_off, hit_off + n, ctx->last_hit_off.begin()) &&
+        ctx->last_cand_off == co) {
+        *changed = false;
+        return HOUGH_OK;
+    }
+    // The previous upload must have left the pinned block before it is rewritten.
+    if (ctx->desc_in_flight)
+        HIP_TRY(hipEventSynchronize(ctx->desc_done));
+    ctx->desc_in_flight = false;
+    const int32_t tpe = tiles_per_event(ctx, ctx->shape_batch);
+    auto *hdr = reinterpret_cast<BatchHeader *>(ctx->desc_host);
+    auto *desc = reinterpret_cast<EventDesc *>(ctx->desc_host + sizeof(BatchHeader));
+    auto *items = reinterpret_cast<WorkItem *>(ctx->desc_host + sizeof(BatchHeader) +
+                                               static_cast<size_t>(ctx->max_events) * sizeof(EventDesc));
+    hdr->n_events = n_events;
+    hdr->n_items = n_events * tpe;
+    for (int32_t e = 0; e < n_events; ++e) {
+        desc[e].hit_begin = hit_off[e];
+        desc[e].hit_end = hit_off[e + 1];
+        desc[e].cand_begin = co[e];
+        desc[e].cand_cap = static_cast<int32_t>(co[e + 1] - co[e]);
+        desc[e].pad_ = 0;
+    }
+    // Largest events first so the persistent workgroups finish together.
+    std::vector<int32_t> order(static_cast<size_t>(n_events));
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return hit_off[a + 1] - hit_off[a] > hit_off[b + 1] - hit_off[b];
+    });
+    int32_t n_items = 0;
+    for (int32_t e : order)
+        for (int32_t t = 0; t < tpe; ++t)
+            items[n_items++] = WorkItem{e, t};
+    ctx->last_hit_off.assign(hit_off, hit_off + n);
+    ctx->last_cand_off = co;
+    *changed = true;
+    return HOUGH_OK;
+}
+
+hough_status check_batch(const hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
+                         const float *y) {
+    if (!ctx || !hit_off || n_events < 1 || n_events > ctx->max_events || hit_off[0] != 0)
+        return HOUGH_EINVAL;
+    for (int32_t e = 0; e < n_events; ++e) {
+        const int64_t nh = hit_off[e + 1] - hit_off[e];
+        if (nh < 0 || (ctx->u16 && nh > 65535))
+            return HOUGH_EINVAL;
+    }
+    if (hit_off[n_events] > ctx->max_hits)
+        return HOUGH_EINVAL;
+    if (hit_off[n_events] > 0 && (!x || !y))
+        return HOUGH_EINVAL;
+    return HOUGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hough_version(void) { return "hough-mi355x 0.1"; }
+
+const char *hough_status_str(hough_status s) {
+    switch (s) {
+        case HOUGH_OK: return "ok";
+        case HOUGH_EINVAL: return "invalid argument";
+        case HOUGH_ENOMEM: return "out of device memory";
+        case HOUGH_EDEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *hough_last_error(void) { return g_last_error.c_str(); }
+
+hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hough_ctx_opts *opts) {
+    if (!out || !grid)
+        return HOUGH_EINVAL;
+    *out = nullptr;
+    if (grid->n_phi < 3 || grid->n_kappa < 1 || grid->n_d0 < 1 || !grid->cos_phi || !grid->sin_phi)
+        return HOUGH_EINVAL;
+    if (grid->n_d0 > 1 && !grid->d0)
+        return HOUGH_EINVAL;
+    if (grid->acc_type != HOUGH_ACC_I32 && grid->acc_type != HOUGH_ACC_U16)
+        return HOUGH_EINVAL;
+    const bool u16 = grid->acc_type == HOUGH_ACC_U16;
+    if (u16 && (grid->n_kappa & 1))
+        return HOUGH_EINVAL;
+    const int64_t cells = static_cast<int64_t>(grid->n_d0) * grid->n_phi * grid->n_kappa;
+    if (cells > 0x7fffffffLL)
+        return HOUGH_EINVAL;
+    hough_ctx_opts o{};
+    if (opts)
+        o = *opts;
+    if (o.max_events < 0 || o.max_hits < 0)
+        return HOUGH_EINVAL;
+    if (o.max_events == 0)
+        o.max_events = 1;
+    if (o.max_hits == 0)
+        o.max_hits = 1 << 20;
+
+    hough_ctx *c = new (std::nothrow) hough_ctx();
+    if (!c)
+        return HOUGH_ENOMEM;
+    c->grid = *grid;
+    c->u16 = u16;
+    c->max_events = o.max_events;
+    c->max_hits = o.max_hits;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return device_error(hipErrorNoDevice, "hipGetDevice");
+    }
+    GridArgs &g = c->g;
+    g.cos_phi = grid->cos_phi;
+    g.sin_phi = grid->sin_phi;
+    g.d0 = grid->d0;
+    g.n_d0 = grid->n_d0;
+    g.n_phi = grid->n_phi;
+    g.n_kappa = grid->n_kappa;
+    g.kappa_min = grid->kappa_min;
+    g.kappa_scale = grid->kappa_scale;
+    g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
+    g.cells = cells;
+    g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;
+
+    // Default launch shapes (the autotuner may replace them).
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, c->device);
+    const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->shape_single = VoteShape{u16 ? 64 : 4, 256, 1, 0};
+    if (!vote_shape_supported(c->shape_single, u16, g.row_dwords))
+        c->shape_single = VoteShape{8, 256, 1, 0};
+    c->shape_batch = VoteShape{u16 ? 64 : 32, 512, 1, 0};
+    if (!vote_shape_supported(c->shape_batch, u16, g.row_dwords))
+        c->shape_batch = VoteShape{8, 256, 1, 0};
+    c->persistent_groups = cus * 4;
+
+    // Sort workspace sized for the peak-block layout.
+    c->n_chunks0 = peak_blocks_per_event(g);
+    c->cap0 = peak_chunk_cap(g);
+    c->bound = static_cast<int64_t>(c->n_chunks0) * c->cap0;
+    const int64_t later = (c->bound + kSortChunk - 1) / kSortChunk;
+    c->hist_chunks = static_cast<int32_t>(std::max<int64_t>(c->n_chunks0, later));
+    const size_t E = static_cast<size_t>(c->max_events);
+    // Work list: the largest tile count any shape can produce (8 rows).
+    c->max_items = static_cast<int32_t>(E) * g.n_d0 * ((g.n_phi + 7) / 8);
+    c->desc_bytes = sizeof(BatchHeader) + E * sizeof(EventDesc) + static_cast<size_t>(c->max_items) * sizeof(WorkItem);
+
+    hipError_t e = hipSuccess;
+    e = e ? e : dev_alloc(&c->state, E);
+    e = e ? e : dev_alloc(&c->stage, E * static_cast<size_t>(c->bound));
+    e = e ? e : dev_alloc(&c->cnt0, E * c->n_chunks0);
+    e = e ? e : dev_alloc(&c->hist, E * static_cast<size_t>(c->hist_chunks) * kDigits);
+    e = e ? e : dev_alloc(&c->tmp0, E * static_cast<size_t>(c->bound));
+    e = e ? e : dev_alloc(&c->acc_ws, E * static_cast<size_t>(g.acc_dwords));
+    e = e ? e : dev_alloc(&c->desc_dev, c->desc_bytes);
+    e = e ? e : dev_alloc(&c->work_counter, 1);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&c->desc_host), c->desc_bytes, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        const bool oom = e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation;
+        hough_status st = oom ? HOUGH_ENOMEM : device_error(e, "hough_ctx_create");
+        if (oom)
+            g_last_error = "workspace allocation failed";
+        free_ctx(c);
+        return st;
+    }
+    *out = c;
+    return HOUGH_OK;
+}
+
+void hough_ctx_destroy(hough_ctx *ctx) {
+    if (!ctx)
+        return;
+    (void)hipDeviceSynchronize();
+    free_ctx(ctx);
+}
+
+hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32_t threads, int32_t split,
+                              int32_t pad) {
+    if (!ctx || (which != 0 && which != 1))
+        return HOUGH_EINVAL;
+    VoteShape s{rows, threads, split, pad};
+    if (which == 1 && split != 1)
+        return HOUGH_EINVAL;
+    if (!vote_shape_supported(s, ctx->u16, ctx->g.row_dwords))
+        return HOUGH_EINVAL;
+    if (which == 1 && tiles_per_event(ctx, s) * static_cast<int64_t>(ctx->max_events) > ctx->max_items)
+        return HOUGH_EINVAL;
+    if (which == 0)
+        ctx->shape_single = s;
+    else
+        ctx->shape_batch = s;
+    // Cached graphs embed the old shape.
+    for (auto &ge : ctx->graphs)
+        (void)hipGraphExecDestroy(ge.exec);
+    ctx->graphs.clear();
+    return HOUGH_OK;
+}
+
+hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows, int32_t *threads,
+                              int32_t *split, int32_t *pad) {
+    if (!ctx || (which != 0 && which != 1))
+        return HOUGH_EINVAL;
+    const VoteShape &s = which == 0 ? ctx->shape_single : ctx->shape_batch;
+    if (rows)
+        *rows = s.rows;
+    if (threads)
+        *threads = s.threads;
+    if (split)
+        *split = s.split;
+    if (pad)
+        *pad = s.pad;
+    return HOUGH_OK;
+}
+
+hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t n_hits, void *acc,
+                        uint64_t *n_votes, void *stream) {
+    if (!ctx || !acc || n_hits < 0 || n_hits > ctx->max_hits)
+        return HOUGH_EINVAL;
+    if (n_hits > 0 && (!x || !y))
+        return HOUGH_EINVAL;
+    if (ctx->u16 && n_hits > 65535)
+        return HOUGH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(acc) & 3u)
+        return HOUGH_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
+    if (nv)
+        HIP_TRY(launch_prep(nullptr, 1, nv, s));
+    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, ctx->shape_single, x, y, n_hits, static_cast<uint32_t *>(acc),
+                               nv, s));
+    return HOUGH_OK;
+}
+
+hough_status hough_peaks(hough_ctx *ctx, const void *acc, int32_t threshold, hough_cand *out, int32_t cap,
+                         int32_t *n_found, void *stream) {
+    if (!ctx || !acc || !n_found || cap < 0 || (cap > 0 && !out))
+        return HOUGH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(acc) & 3u)
+        return HOUGH_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SortWork w = make_sort_work(ctx);
+    w.out = out;
+    w.cap = cap;
+    w.n_found = n_found;
+    HIP_TRY(launch_prep(ctx->state, 1, nullptr, s));
+    HIP_TRY(launch_peaks(ctx->g, ctx->u16, static_cast<const uint32_t *>(acc), 1, threshold, w, s));
+    HIP_TRY(launch_sort(w, 1, s));
+    return HOUGH_OK;
+}
+
+hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
+                               const float *y, int32_t threshold, void *acc, hough_cand *cands,
+                               const int64_t *cand_off, int32_t *n_found, uint64_t *n_votes, void *stream) {
+    if (!cand_off || !n_found || check_batch(ctx, n_events, hit_off, x, y) != HOUGH_OK)
+        return HOUGH_EINVAL;
+    if (cand_off[0] != 0)
+        return HOUGH_EINVAL;
+    for (int32_t e = 0; e < n_events; ++e)
+        if (cand_off[e + 1] < cand_off[e] || cand_off[e + 1] - cand_off[e] > 0x7fffffffLL)
+            return HOUGH_EINVAL;
+    if (cand_off[n_events] > 0 && !cands)
+        return HOUGH_EINVAL;
+    if (acc && (reinterpret_cast<uintptr_t>(acc) & 3u))
+        return HOUGH_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    bool changed = false;
+    hough_status st = stage_descriptors(ctx, n_events, hit_off, cand_off, &changed);
+    if (st != HOUGH_OK)
+        return st;
+    const VoteShape &vs = ctx->shape_batch;
+
+    GraphKey key{x, y, acc, cands, n_found, n_votes, threshold};
+    hipGraphExec_t exec = nullptr;
+    for (auto &ge : ctx->graphs)
+        if (ge.key == key)
+            exec = ge.exec;
+    if (!exec) {
+        hipStream_t cs = ctx->capture_stream;
+        char *dd = ctx->desc_dev;
+        auto *d_hdr = reinterpret_cast<BatchHeader *>(dd);
+        auto *d_desc = reinterpret_cast<EventDesc *>(dd + sizeof(BatchHeader));
+        auto *d_items = reinterpret_cast<WorkItem *>(dd + sizeof(BatchHeader) +
+                                                     static_cast<size_t>(ctx->max_events) * sizeof(EventDesc));
+        (void)d_hdr;
+        uint32_t *acc_dw = acc ? static_cast<uint32_t *>(acc) : ctx->acc_ws;
+        SortWork w = make_sort_work(ctx);
+        w.desc = d_desc;
+        w.out = cands;
+        w.n_found = n_found;
+        w.n_events_dev = &d_hdr->n_events;
+        auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipMemcpyAsync(dd, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, cs);
+        if (ce == hipSuccess)
+            ce = launch_prep_batch(ctx->state, ctx->max_events, &d_hdr->n_events, nv, ctx->work_counter, cs);
+        if (ce == hipSuccess)
+            ce = launch_vote_batch(ctx->g, ctx->u16, vs, x, y, d_desc, &d_hdr->n_items, d_items, ctx->max_items,
+                                   ctx->work_counter, ctx->persistent_groups, acc_dw, nv, cs);
+        if (ce == hipSuccess)
+            ce = launch_peaks(ctx->g, ctx->u16, acc_dw, ctx->max_events, threshold, w, cs);
+        if (ce == hipSuccess)
+            ce = launch_sort(w, ctx->max_events, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (ce != hipSuccess) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return device_error(ce, "hough_event_batch capture");
+        }
+        if (ee != hipSuccess)
+            return device_error(ee, "hipStreamEndCapture");
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess)
+            return device_error(ie, "hipGraphInstantiate");
+        if (ctx->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back(GraphEntry{key, exec});
+    }
+    HIP_TRY(hipGraphLaunch(exec, s));
+    if (changed) {
+        // The graph's first node copies the pinned block; it is free once the graph is done.
+        HIP_TRY(hipEventRecord(ctx->desc_done, s));
+        ctx->desc_in_flight = true;
+    }
+    return HOUGH_OK;
+}
+
+hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
+                              const float *y, void *acc, uint64_t *n_votes, void *stream) {
+    if (check_batch(ctx, n_events, hit_off, x, y) != HOUGH_OK || !acc)
+        return HOUGH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(acc) & 3u)
+        return HOUGH_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool changed = false;
+    hough_status st = stage_descriptors(ctx, n_events, hit_off, nullptr, &changed);
+    if (st != HOUGH_OK)
+        return st;
+    char *dd = ctx->desc_dev;
+    auto *d_hdr = reinterpret_cast<BatchHeader *>(dd);
+    auto *d_desc = reinterpret_cast<EventDesc *>(dd + sizeof(BatchHeader));
+    auto *d_items = reinterpret_cast<WorkItem *>(dd + sizeof(BatchHeader) +
+                                                 static_cast<size_t>(ctx->max_events) * sizeof(EventDesc));
+    if (changed) {
+        HIP_TRY(hipMemcpyAsync(dd, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(ctx->desc_done, s));
+        ctx->desc_in_flight = true;
+    }
+    auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
+    HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &d_hdr->n_events, nv, ctx->work_counter, s));
+    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, ctx->shape_batch, x, y, d_desc, &d_hdr->n_items, d_items,
+                              ctx->max_items, ctx->work_counter, ctx->persistent_groups,
+                              static_cast<uint32_t *>(acc), nv, s));
+    return HOUGH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Internal declarations shared by the HIP sources of libhough (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hough.h"
+
+namespace hough {
+
+// ---------------------------------------------------------------------------
+// Sort geometry: candidates are ordered by an LSD radix sort over 8-bit digits
+// of key = 0x7fffffff - votes (so ascending keys = descending votes); the
+// stable passes keep the ascending-cell order in which the peak search emits
+// them.  Only the digits in which the event's keys differ are sorted.
+// ---------------------------------------------------------------------------
+constexpr int kDigits = 256;
+constexpr int kMaxPasses = 4;
+constexpr int kSortChunk = 4096;      // elements per chunk in passes >= 1
+constexpr int kSortThreads = 256;
+constexpr int kScanThreads = 1024;
+
+struct Cand {
+    int32_t votes;
+    int32_t cell;
+};
+static_assert(sizeof(Cand) == sizeof(hough_cand), "candidate layout");
+
+__host__ __device__ inline uint32_t sort_key(int32_t votes) {
+    return static_cast<uint32_t>(static_cast<int64_t>(0x7fffffff) - static_cast<int64_t>(votes));
+}
+
+// Per-event state of one call, reset by the prep kernel.
+struct EventState {
+    uint32_t key_min;
+    uint32_t key_max;
+    int32_t n_found;
+    int32_t passes;       // LSD passes this event needs (>= 1), set by the pass-0 scan
+};
+
+// Per-event descriptor uploaded by hough_event_batch.
+struct EventDesc {
+    int64_t hit_begin;
+    int64_t hit_end;
+    int64_t cand_begin;   // output slice of the caller's candidate array
+    int32_t cand_cap;
+    int32_t pad_;
+};
+
+// A unit of batched vote work: one phi0 tile of one event.
+struct WorkItem {
+    int32_t event;
+    int32_t tile;         // tile index inside the event (d0 slice major)
+};
+
+// Grid in the form the kernels take it.
+struct GridArgs {
+    const float *cos_phi;
+    const float *sin_phi;
+    const float *d0;      // nullptr for 2D
+    int32_t n_d0, n_phi, n_kappa;
+    float kappa_min, kappa_scale;
+    int32_t row_dwords;   // dwords per (d0, phi0) row in global memory
+    int64_t cells;        // cells per event
+    int64_t acc_dwords;   // dwords per event accumulator
+};
+
+// Where the pass-0 candidate lists of every event live.  Chunk c of event e
+// holds cnt0[e*n_chunks0 + c] candidates at stage + (e*n_chunks0 + c)*cap0.
+struct Stage0 {
+    Cand *stage;
+    int32_t *cnt0;
+    int32_t n_chunks0;
+    int32_t cap0;
+};
+
+struct SortWork {
+    Stage0 s0;
+    uint32_t *hist;           // [events][hist_chunks][256], offsets in place after a scan
+    int32_t hist_chunks;
+    Cand *tmp0;               // [events][bound]
+    Cand *tmp1;               // [events][bound] (aliases stage, which is dead after pass 0)
+    int64_t bound;            // max candidates per event
+    EventState *state;
+    const EventDesc *desc;    // per-event output slices, or nullptr
+    hough_cand *out;          // caller's candidate array
+    int32_t cap;              // used when desc == nullptr (one event)
+    int32_t *n_found;         // caller's [events]
+    uint32_t key_mask;        // 0xffffffff (i32) or 0xffff (u16): digits that can differ
+    const int32_t *n_events_dev;  // batch: live event count on the device, or nullptr
+};
+
+// Launch shape of a vote kernel.
+struct VoteShape {
+    int32_t rows;     // phi0 rows per tile
+    int32_t threads;  // workgroup size
+    int32_t split;    // hit chunks per tile (single-event vote only)
+    int32_t pad;      // extra dwords per LDS row
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (return hipSuccess or the first launch error).
+// ---------------------------------------------------------------------------
+bool vote_shape_supported(const VoteShape &s, bool u16, int32_t row_dwords);
+size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords);
+
+hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *n_votes,
+                       hipStream_t stream);
+// Batch form: state of all max_events slots, n_votes of the live events, work counter.
+hipError_t launch_prep_batch(EventState *state, int32_t max_events, const int32_t *n_events_dev,
+                             unsigned long long *n_votes, int32_t *work_counter, hipStream_t stream);
+hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
+
+// One event: hits [0, n_hits).
+hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const float *x,
+                              const float *y, int32_t n_hits, uint32_t *acc,
+                              unsigned long long *n_votes, hipStream_t stream);
+// Many events: tile work items over events described by desc; the live item
+// count is read on the device.  With a work counter (reset beforehand) the
+// launch is persistent: persistent_groups workgroups pull items in order.
+hipError_t launch_vote_batch(const GridArgs &g, bool u16, const VoteShape &s, const float *x,
+                             const float *y, const EventDesc *desc, const int32_t *n_items_dev,
+                             const WorkItem *items, int32_t max_items, int32_t *work_counter,
+                             int32_t persistent_groups, uint32_t *acc,
+                             unsigned long long *n_votes, hipStream_t stream);
+
+constexpr int kPeakRows = 16;         // phi0 rows per peak-search block
+int32_t peak_blocks_per_event(const GridArgs &g);
+int32_t peak_chunk_cap(const GridArgs &g);
+hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_t n_events,
+                        int32_t threshold, const SortWork &w, hipStream_t stream);
+hipError_t launch_sort(const SortWork &w, int32_t n_events, hipStream_t stream);
+
+}  // namespace hough

@@ -1,0 +1,270 @@
+"""Python binding of libhough (argument marshalling only).
+
+Every step of the vote and peak search runs in the HIP kernels of
+``libhough.so``; this module loads the library, checks shapes and passes
+device pointers.  PyTorch supplies device memory and streams.  There is no
+fallback: if the library is missing, importing this module's entry points
+raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhough.so")
+
+HOUGH_OK, HOUGH_EINVAL, HOUGH_ENOMEM, HOUGH_EDEVICE = 0, -1, -2, -3
+ACC_I32, ACC_U16 = 0, 1
+
+SYMBOLS = (
+    "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
+    "hough_vote_batch",
+    "hough_set_launch", "hough_get_launch", "hough_status_str", "hough_last_error", "hough_version",
+)
+
+
+class HoughError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        lib = _lib_or_none()
+        msg = lib.hough_status_str(status).decode() if lib else str(status)
+        detail = lib.hough_last_error().decode() if lib else ""
+        super().__init__(f"{what}: {msg}" + (f" ({detail})" if detail else ""))
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_d0", ctypes.c_int32), ("n_phi", ctypes.c_int32), ("n_kappa", ctypes.c_int32),
+                ("kappa_min", ctypes.c_float), ("kappa_scale", ctypes.c_float),
+                ("cos_phi", ctypes.c_void_p), ("sin_phi", ctypes.c_void_p), ("d0", ctypes.c_void_p),
+                ("acc_type", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("max_events", ctypes.c_int32), ("max_hits", ctypes.c_int64), ("tune_cache", ctypes.c_char_p)]
+
+
+_LIB = None
+
+
+def _lib_or_none():
+    return _LIB
+
+
+def load(path: str = LIB_PATH):
+    """Load libhough.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1311_2769_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.hough_ctx_create.restype = i32
+    lib.hough_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Grid), ctypes.POINTER(_Opts)]
+    lib.hough_ctx_destroy.restype = None
+    lib.hough_ctx_destroy.argtypes = [vp]
+    lib.hough_vote.restype = i32
+    lib.hough_vote.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.hough_peaks.restype = i32
+    lib.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+    lib.hough_event_batch.restype = i32
+    lib.hough_event_batch.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hough_vote_batch.restype = i32
+    lib.hough_vote_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hough_set_launch.restype = i32
+    lib.hough_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
+    lib.hough_get_launch.restype = i32
+    lib.hough_get_launch.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
+    lib.hough_status_str.restype = ctypes.c_char_p
+    lib.hough_status_str.argtypes = [i32]
+    lib.hough_last_error.restype = ctypes.c_char_p
+    lib.hough_last_error.argtypes = []
+    lib.hough_version.restype = ctypes.c_char_p
+    lib.hough_version.argtypes = []
+    _LIB = lib
+    return lib
+
+
+def _check(status, what):
+    if status != HOUGH_OK:
+        raise HoughError(status, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclasses.dataclass
+class GridSpec:
+    """The binned parameter space, with fp32 bin tables (host arrays)."""
+    n_d0: int
+    n_phi: int
+    n_kappa: int
+    kappa_min: float
+    kappa_scale: float
+    cos_phi: np.ndarray
+    sin_phi: np.ndarray
+    d0: np.ndarray | None
+    acc_u16: bool
+
+    @classmethod
+    def from_grid(cls, g):
+        """From any object with the fields of a grid (n_d0, n_phi, ..., acc_type "i32"/"u16")."""
+        return cls(int(g.n_d0), int(g.n_phi), int(g.n_kappa), float(g.kappa_min), float(g.kappa_scale),
+                   np.asarray(g.cos_phi, np.float32), np.asarray(g.sin_phi, np.float32),
+                   None if g.d0 is None else np.asarray(g.d0, np.float32), g.acc_type == "u16")
+
+    @property
+    def cells(self):
+        return self.n_d0 * self.n_phi * self.n_kappa
+
+    @property
+    def acc_dtype(self):
+        return torch.int16 if self.acc_u16 else torch.int32
+
+    def max_candidates(self):
+        """Upper bound on candidates of one event: no two candidates are neighbours."""
+        return ((self.n_d0 + 1) // 2 if self.n_d0 > 1 else 1) * (self.n_phi // 2) * ((self.n_kappa + 1) // 2)
+
+
+class HoughContext:
+    """One grid on one device: owns the library context and the device bin tables."""
+
+    def __init__(self, grid, *, device="cuda", max_events: int = 1, max_hits: int = 1 << 20,
+                 tune_cache: str | None = None):
+        self.lib = load()
+        self.spec = grid if isinstance(grid, GridSpec) else GridSpec.from_grid(grid)
+        self.device = torch.device(device)
+        s = self.spec
+        self.cos_phi = torch.from_numpy(s.cos_phi.copy()).to(self.device)
+        self.sin_phi = torch.from_numpy(s.sin_phi.copy()).to(self.device)
+        self.d0 = None if s.d0 is None else torch.from_numpy(s.d0.copy()).to(self.device)
+        g = _Grid(s.n_d0, s.n_phi, s.n_kappa, s.kappa_min, s.kappa_scale, self.cos_phi.data_ptr(),
+                  self.sin_phi.data_ptr(), None if self.d0 is None else self.d0.data_ptr(),
+                  ACC_U16 if s.acc_u16 else ACC_I32)
+        opts = _Opts(int(max_events), int(max_hits), tune_cache.encode() if tune_cache else None)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.hough_ctx_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(opts)),
+                   "hough_ctx_create")
+        self.handle = h
+        self.max_events = int(max_events)
+        self.max_hits = int(max_hits)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.hough_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- allocation helpers ------------------------------------------------------------
+    def new_acc(self, n_events=None):
+        shape = (self.spec.n_d0, self.spec.n_phi, self.spec.n_kappa)
+        if n_events is not None:
+            shape = (n_events,) + shape
+        return torch.empty(shape, dtype=self.spec.acc_dtype, device=self.device)
+
+    # -- entry points -------------------------------------------------------------------
+    def vote(self, x, y, acc=None, n_votes=None, stream=None):
+        n = int(x.numel())
+        if y.numel() != n or x.dtype != torch.float32 or y.dtype != torch.float32:
+            raise ValueError("x, y must be fp32 tensors of equal length")
+        if not (x.is_contiguous() and y.is_contiguous()):
+            raise ValueError("x, y must be contiguous")
+        if acc is None:
+            acc = self.new_acc()
+        if acc.numel() != self.spec.cells or acc.element_size() != (2 if self.spec.acc_u16 else 4):
+            raise ValueError("accumulator has the wrong size or type")
+        if n_votes is None:
+            n_votes = torch.empty(1, dtype=torch.int64, device=self.device)
+        _check(self.lib.hough_vote(self.handle, _ptr(x), _ptr(y), n, _ptr(acc), _ptr(n_votes),
+                                   _stream_handle(stream)), "hough_vote")
+        return acc, n_votes
+
+    def peaks(self, acc, threshold, cap=None, out=None, n_found=None, stream=None):
+        if cap is None:
+            cap = self.spec.max_candidates() if out is None else out.shape[0]
+        if out is None:
+            out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
+        if n_found is None:
+            n_found = torch.empty(1, dtype=torch.int32, device=self.device)
+        if acc.numel() != self.spec.cells:
+            raise ValueError("accumulator has the wrong size")
+        _check(self.lib.hough_peaks(self.handle, _ptr(acc), int(threshold), _ptr(out) if cap else None,
+                                    int(cap), _ptr(n_found), _stream_handle(stream)), "hough_peaks")
+        return out, n_found
+
+    def event_batch(self, hit_off, x, y, threshold, cand_off=None, cands=None, n_found=None,
+                    n_votes=None, acc=None, want_votes=True, stream=None):
+        hit_off = np.ascontiguousarray(hit_off, dtype=np.int64)
+        n_events = hit_off.shape[0] - 1
+        if cand_off is None:
+            cap = self.spec.max_candidates()
+            cand_off = np.arange(n_events + 1, dtype=np.int64) * cap
+        cand_off = np.ascontiguousarray(cand_off, dtype=np.int64)
+        if cands is None:
+            cands = torch.empty((max(int(cand_off[-1]), 1), 2), dtype=torch.int32, device=self.device)
+        if n_found is None:
+            n_found = torch.empty(n_events, dtype=torch.int32, device=self.device)
+        if n_votes is None and want_votes:
+            n_votes = torch.empty(n_events, dtype=torch.int64, device=self.device)
+        _check(self.lib.hough_event_batch(
+            self.handle, n_events, hit_off.ctypes.data_as(ctypes.c_void_p), _ptr(x), _ptr(y), int(threshold),
+            _ptr(acc), _ptr(cands), cand_off.ctypes.data_as(ctypes.c_void_p), _ptr(n_found), _ptr(n_votes),
+            _stream_handle(stream)), "hough_event_batch")
+        return cands, cand_off, n_found, n_votes
+
+    def vote_batch(self, hit_off, x, y, acc=None, n_votes=None, stream=None):
+        hit_off = np.ascontiguousarray(hit_off, dtype=np.int64)
+        n_events = hit_off.shape[0] - 1
+        if acc is None:
+            acc = self.new_acc(n_events)
+        if acc.numel() != n_events * self.spec.cells:
+            raise ValueError("accumulator has the wrong size")
+        if n_votes is None:
+            n_votes = torch.empty(n_events, dtype=torch.int64, device=self.device)
+        _check(self.lib.hough_vote_batch(self.handle, n_events, hit_off.ctypes.data_as(ctypes.c_void_p),
+                                         _ptr(x), _ptr(y), _ptr(acc), _ptr(n_votes), _stream_handle(stream)),
+               "hough_vote_batch")
+        return acc, n_votes
+
+    def set_launch(self, which, rows, threads, split=1, pad=0):
+        _check(self.lib.hough_set_launch(self.handle, which, rows, threads, split, pad), "hough_set_launch")
+
+    def get_launch(self, which):
+        vals = [ctypes.c_int32() for _ in range(4)]
+        _check(self.lib.hough_get_launch(self.handle, which, *[ctypes.byref(v) for v in vals]),
+               "hough_get_launch")
+        return tuple(v.value for v in vals)
+
+
+def acc_to_numpy(acc, spec: GridSpec):
+    """Accumulator tensor to an int64 numpy array (uint16 cells widened without sign)."""
+    a = acc.detach().cpu()
+    if spec.acc_u16:
+        return a.numpy().view(np.uint16).astype(np.int64).reshape(acc.shape)
+    return a.numpy().astype(np.int64)
+
+
+def cands_to_numpy(out, n_found, cap=None):
+    n = int(n_found)
+    m = n if cap is None else min(n, cap)
+    c = out[:m].detach().cpu().numpy()
+    return c[:, 0].astype(np.int64), c[:, 1].astype(np.int64), n

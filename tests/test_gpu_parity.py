@@ -1,0 +1,325 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integers all the way: accumulators, vote counts and candidate lists must be
+bit-exact, at every launch shape, for single events and for batches.
+"""
+
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.grids import Grid, make_grid
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1311_2769_amd import hough  # noqa: E402
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(_dev())
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle(key, x, y, grid, thr):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle.find(x, y, grid, thr)
+    return _ORACLE_CACHE[key]
+
+
+def _gpu_find(ctx, x, y, thr, cap=None):
+    acc, nv = ctx.vote(_t(x), _t(y))
+    out, nf = ctx.peaks(acc, thr, cap)
+    torch.cuda.synchronize()
+    a = hough.acc_to_numpy(acc, ctx.spec)
+    v, c, n = hough.cands_to_numpy(out, nf.item(), cap)
+    return a, int(nv.item()), v, c, n
+
+
+def _assert_same(gpu, ref, what):
+    a, nv, v, c, n = gpu
+    ra, rnv, rv, rc, rn = ref
+    assert a.shape == ra.reshape(a.shape).shape
+    np.testing.assert_array_equal(a.reshape(-1), ra.reshape(-1), err_msg=f"{what}: accumulator")
+    assert nv == rnv, f"{what}: vote count"
+    assert n == rn, f"{what}: n_found"
+    np.testing.assert_array_equal(v, rv[:len(v)], err_msg=f"{what}: votes")
+    np.testing.assert_array_equal(c, rc[:len(c)], err_msg=f"{what}: cells")
+
+
+# --------------------------------------------------------------------------------------
+# Single events at the workload sizes
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_workload_event_matches_oracle(cfg):
+    print(f"[parity] workload {cfg}", flush=True)
+    wc = synth.CONFIGS[cfg]
+    ev = synth.gen_config_event(cfg)
+    ref = _oracle(("cfg", cfg), ev.x, ev.y, wc.grid, wc.threshold)
+    ctx = hough.HoughContext(wc.grid, max_hits=ev.n_hits)
+    _assert_same(_gpu_find(ctx, ev.x, ev.y, wc.threshold), ref, f"workload {cfg}")
+
+
+@pytest.mark.parametrize("shape", [(4, 256, 1, 0), (8, 256, 2, 1), (16, 512, 1, 0), (32, 1024, 3, 1),
+                                   (64, 256, 1, 0), (64, 1024, 4, 1)])
+def test_vote_launch_shapes_agree_2d(shape):
+    print(f"[parity] 2D shape {shape}", flush=True)
+    wc = synth.CONFIGS[2]
+    ev = synth.gen_config_event(2)
+    ref = _oracle(("cfg", 2), ev.x, ev.y, wc.grid, wc.threshold)
+    ctx = hough.HoughContext(wc.grid, max_hits=ev.n_hits)
+    rows, threads, split, pad = shape
+    ctx.set_launch(0, rows, threads, split, pad)
+    acc, nv = ctx.vote(_t(ev.x), _t(ev.y))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(hough.acc_to_numpy(acc, ctx.spec).reshape(-1), ref[0].reshape(-1))
+    assert int(nv.item()) == ref[1]
+
+
+@pytest.mark.parametrize("shape", [(8, 256, 1, 0), (32, 512, 2, 1), (64, 1024, 1, 0), (128, 256, 1, 1)])
+def test_vote_launch_shapes_agree_3d(shape):
+    print(f"[parity] 3D shape {shape}", flush=True)
+    wc = synth.CONFIGS[3]
+    ev = synth.gen_config_event(3)
+    ref = _oracle(("cfg", 3), ev.x, ev.y, wc.grid, wc.threshold)
+    ctx = hough.HoughContext(wc.grid, max_hits=ev.n_hits)
+    ctx.set_launch(0, *shape)
+    acc, nv = ctx.vote(_t(ev.x), _t(ev.y))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(hough.acc_to_numpy(acc, ctx.spec).reshape(-1), ref[0].reshape(-1))
+    assert int(nv.item()) == ref[1]
+
+
+# --------------------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------------------
+
+def test_empty_event():
+    ctx = hough.HoughContext(synth.GRID_2D_SMALL)
+    x = torch.zeros(0, dtype=torch.float32, device=_dev())
+    acc, nv = ctx.vote(x, x)
+    out, nf = ctx.peaks(acc, 1)
+    torch.cuda.synchronize()
+    assert int(acc.abs().sum().item()) == 0 and int(nv.item()) == 0 and int(nf.item()) == 0
+
+
+def test_nonfinite_origin_and_huge_hits():
+    pts = np.array([[np.nan, 1], [1, np.nan], [np.inf, 2], [-np.inf, 0], [0, 0], [np.inf, np.inf],
+                    [3e19, 1.0], [1e-30, 2e-30], [-1e-42, 1e-42], [4.0, 0.0], [0.0, -7.0]], np.float32)
+    for grid in (synth.GRID_2D_SMALL, synth.GRID_3D):
+        ref = oracle.find(pts[:, 0], pts[:, 1], grid, 1)
+        ctx = hough.HoughContext(grid)
+        _assert_same(_gpu_find(ctx, pts[:, 0], pts[:, 1], 1), ref, f"special hits {grid.shape}")
+
+
+@pytest.mark.parametrize("dims", [(1, 3, 1), (1, 37, 13), (1, 5, 2), (3, 11, 6), (5, 33, 10), (2, 200, 64)])
+def test_odd_small_grids(dims):
+    n_d0, n_phi, n_kappa = dims
+    print(f"[parity] grid {dims}", flush=True)
+    if n_d0 == 1:
+        grid = make_grid(n_phi, n_kappa, kappa_half_range_inv_cm=20.0)
+    else:
+        grid = make_grid(n_phi, n_kappa, n_d0=n_d0, d0_range=(-9.0, 9.0), kappa_half_range_inv_cm=20.0,
+                         acc_type="u16")
+    ev = synth.gen_config_event(1)
+    ref = oracle.find(ev.x, ev.y, grid, 2)
+    ctx = hough.HoughContext(grid)
+    for rows in (4, 8, 64):
+        ctx.set_launch(0, rows, 256, 1, 0)
+        _assert_same(_gpu_find(ctx, ev.x, ev.y, 2), ref, f"grid {dims} rows {rows}")
+
+
+def test_u16_at_the_hit_limit_and_beyond():
+    grid = make_grid(16, 8, n_d0=2, d0_range=(-1.0, 1.0), kappa_half_range_inv_cm=0.5, acc_type="u16")
+    rng = np.random.default_rng(1)
+    # 65535 hits on one spot: every vote lands in the same few cells (max count 65535)
+    x = np.full(65535, 50.0, np.float32)
+    y = np.full(65535, 0.0, np.float32)
+    x[:100] = rng.uniform(-50, 50, 100).astype(np.float32)
+    ref = oracle.find(x, y, grid, 1)
+    assert ref[0].max() > 65000
+    ctx = hough.HoughContext(grid, max_hits=70000)
+    _assert_same(_gpu_find(ctx, x, y, 1), ref, "u16 limit")
+    big = _t(np.zeros(65536))
+    with pytest.raises(hough.HoughError):
+        ctx.vote(big, big)
+
+
+def test_capacity_truncates_to_a_prefix():
+    wc = synth.CONFIGS[2]
+    ev = synth.gen_config_event(2)
+    ref = _oracle(("cfg", 2), ev.x, ev.y, wc.grid, wc.threshold)
+    ctx = hough.HoughContext(wc.grid, max_hits=ev.n_hits)
+    for cap in (0, 1, 777, ref[4] - 1, ref[4], ref[4] + 5):
+        acc, _ = ctx.vote(_t(ev.x), _t(ev.y))
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=_dev())
+        out, nf = ctx.peaks(acc, wc.threshold, cap=cap, out=out)
+        torch.cuda.synchronize()
+        v, c, n = hough.cands_to_numpy(out, nf.item(), cap)
+        assert n == ref[4]
+        np.testing.assert_array_equal(c, ref[3][:cap])
+        np.testing.assert_array_equal(v, ref[2][:cap])
+
+
+@pytest.mark.parametrize("shape,hi,signed", [((1, 64, 40), 5, True), ((4, 24, 18), 3, False),
+                                             ((1, 256, 128), 2000000, True), ((6, 10, 8), 70000, False)])
+def test_peaks_on_arbitrary_accumulators(shape, hi, signed):
+    """The peak search takes any accumulator: random fields with many ties, negative and
+    large values (multi-pass sorts)."""
+    n_d0, n_phi, n_kappa = shape
+    u16 = n_d0 > 1
+    if u16:
+        hi = min(hi, 65535)
+        grid = make_grid(n_phi, n_kappa, n_d0=n_d0, d0_range=(-1.0, 1.0), acc_type="u16")
+    else:
+        grid = make_grid(n_phi, n_kappa)
+    ctx = hough.HoughContext(grid)
+    rng = np.random.default_rng(sum(shape))
+    for t in (1, 2, hi // 2):
+        lo = -hi if (signed and not u16) else 0
+        a = rng.integers(lo, hi + 1, size=shape).astype(np.int64)
+        dev = torch.from_numpy(a.astype(np.uint16).view(np.int16) if u16 else a.astype(np.int32)).to(_dev())
+        out, nf = ctx.peaks(dev, t)
+        torch.cuda.synchronize()
+        v, c, n = hough.cands_to_numpy(out, nf.item())
+        rv, rc, rn = oracle.peaks(a, t)
+        assert n == rn
+        np.testing.assert_array_equal(c, rc)
+        np.testing.assert_array_equal(v, rv)
+
+
+def test_invalid_arguments_raise():
+    ctx = hough.HoughContext(synth.GRID_2D_SMALL, max_hits=100)
+    x = _t(np.zeros(101))
+    with pytest.raises(hough.HoughError):
+        ctx.vote(x, x)                                     # more than max_hits
+    with pytest.raises(hough.HoughError):
+        ctx.set_launch(0, 24, 256, 1, 0)                   # unsupported tile height
+    big = hough.HoughContext(synth.GRID_2D)
+    with pytest.raises(hough.HoughError):
+        big.set_launch(0, 128, 512, 1, 0)                  # 256 KiB of LDS
+    with pytest.raises(hough.HoughError):
+        ctx.set_launch(1, 64, 256, 2, 0)                   # batch tiles are never split
+    with pytest.raises(hough.HoughError):
+        ctx.event_batch(np.array([0, 5, 3]), x, x, 7)      # decreasing offsets
+
+
+# --------------------------------------------------------------------------------------
+# Batches
+# --------------------------------------------------------------------------------------
+
+def _batch_results(ctx, b, thr, acc=None):
+    x, y = _t(b.x), _t(b.y)
+    cands, cand_off, nf, nv = ctx.event_batch(b.hit_off, x, y, thr, acc=acc)
+    torch.cuda.synchronize()
+    out = []
+    nf = nf.cpu().numpy()
+    nv = nv.cpu().numpy()
+    cc = cands.cpu().numpy()
+    for e in range(b.n_events):
+        s = cc[cand_off[e]:cand_off[e] + min(nf[e], cand_off[e + 1] - cand_off[e])]
+        out.append((int(nv[e]), int(nf[e]), s[:, 0].astype(np.int64), s[:, 1].astype(np.int64)))
+    return out
+
+
+def test_batch_matches_oracle_per_event():
+    print("[parity] batch of 24 workload-4 events vs oracle", flush=True)
+    b = synth.gen_batch(4, 24)
+    g = synth.GRID_2D
+    ctx = hough.HoughContext(g, max_events=24, max_hits=b.n_hits)
+    acc = ctx.new_acc(24)
+    res = _batch_results(ctx, b, 7, acc=acc)
+    acc_np = hough.acc_to_numpy(acc, ctx.spec)
+    for e, ev in enumerate(b.events):
+        ra, rnv, rv, rc, rn = oracle.find(ev.x, ev.y, g, 7)
+        np.testing.assert_array_equal(acc_np[e].reshape(-1), ra.reshape(-1), err_msg=f"event {e}")
+        nv, nf, v, c = res[e]
+        assert (nv, nf) == (rnv, rn), e
+        np.testing.assert_array_equal(c, rc)
+        np.testing.assert_array_equal(v, rv)
+
+
+def test_batch_3d_matches_single_event_path():
+    print("[parity] batch of 3 displaced events", flush=True)
+    evs = [synth.gen_config_event(3, i) for i in range(3)]
+    b = synth.events.pack_events(evs)
+    ctx = hough.HoughContext(synth.GRID_3D, max_events=3, max_hits=b.n_hits)
+    res = _batch_results(ctx, b, 5)
+    single = hough.HoughContext(synth.GRID_3D, max_hits=40000)
+    for e, ev in enumerate(evs):
+        a, nv, v, c, n = _gpu_find(single, ev.x, ev.y, 5)
+        assert res[e][0] == nv and res[e][1] == n
+        np.testing.assert_array_equal(res[e][3], c)
+        np.testing.assert_array_equal(res[e][2], v)
+    ra, rnv, rv, rc, rn = _oracle(("cfg", 3), evs[0].x, evs[0].y, synth.GRID_3D, 5)
+    assert res[0][1] == rn and res[0][0] == rnv
+    np.testing.assert_array_equal(res[0][3], rc)
+
+
+def test_full_batch_equals_single_event_launches_and_is_repeatable():
+    """All 256 events of workload 4 in one batch give, bit for bit, what one-event launches
+    give; replaying the captured batch ten times changes nothing."""
+    print("[parity] full 256-event batch vs single-event launches", flush=True)
+    b = synth.gen_batch(4, 256)
+    g = synth.GRID_2D
+    ctx = hough.HoughContext(g, max_events=256, max_hits=b.n_hits)
+    first = _batch_results(ctx, b, 7)
+    single = hough.HoughContext(g, max_hits=int(np.diff(b.hit_off).max()))
+    for e in range(0, 256, 1):
+        ev = b.events[e]
+        a, nv, v, c, n = _gpu_find(single, ev.x, ev.y, 7)
+        assert first[e][0] == nv and first[e][1] == n, e
+        np.testing.assert_array_equal(first[e][3], c)
+        np.testing.assert_array_equal(first[e][2], v)
+    for rep in range(10):
+        again = _batch_results(ctx, b, 7)
+        for e in range(256):
+            assert again[e][0] == first[e][0] and again[e][1] == first[e][1]
+            np.testing.assert_array_equal(again[e][3], first[e][3])
+    # sampled events of the full batch against the oracle
+    for e in (0, 77, 255):
+        ev = b.events[e]
+        ra, rnv, rv, rc, rn = oracle.find(ev.x, ev.y, g, 7)
+        assert first[e][0] == rnv and first[e][1] == rn
+        np.testing.assert_array_equal(first[e][3], rc)
+
+
+def test_batch_graph_replay_with_changing_descriptors():
+    """The same buffers with different event counts and hit offsets reuse one captured graph;
+    every replay must match a fresh single-event computation."""
+    g = synth.GRID_2D_SMALL
+    evs = [synth.gen_config_event(1, i) for i in range(12)]
+    ctx = hough.HoughContext(g, max_events=12, max_hits=20000)
+    single = hough.HoughContext(g)
+    x = torch.empty(20000, dtype=torch.float32, device=_dev())
+    y = torch.empty(20000, dtype=torch.float32, device=_dev())
+    cap = 4096
+    cands = torch.empty((12 * cap, 2), dtype=torch.int32, device=_dev())
+    nf = torch.empty(12, dtype=torch.int32, device=_dev())
+    nv = torch.empty(12, dtype=torch.int64, device=_dev())
+    for sel in ([0, 1, 2], list(range(12)), [5], [3, 9, 11, 4, 7], [0, 1, 2]):
+        b = synth.events.pack_events([evs[i] for i in sel])
+        x[:b.n_hits] = _t(b.x)
+        y[:b.n_hits] = _t(b.y)
+        cand_off = np.arange(len(sel) + 1, dtype=np.int64) * cap
+        ctx.event_batch(b.hit_off, x, y, 7, cand_off=cand_off, cands=cands, n_found=nf[:len(sel)],
+                        n_votes=nv[:len(sel)])
+        torch.cuda.synchronize()
+        for k, i in enumerate(sel):
+            a, v1, v, c, n = _gpu_find(single, evs[i].x, evs[i].y, 7)
+            assert int(nv[k]) == v1 and int(nf[k]) == n
+            got = cands[k * cap:k * cap + n].cpu().numpy()
+            np.testing.assert_array_equal(got[:, 1], c)
