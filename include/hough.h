@@ -160,6 +160,15 @@ hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32
 hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows, int32_t *threads,
                               int32_t *split, int32_t *pad);
 
+/* Timing mode (for benchmarks and profiling; results are unchanged).  When
+ * enabled, hough_event_batch enqueues its kernels directly on the stream
+ * instead of replaying a graph and records HIP events around the whole batch
+ * and around its vote kernel.  hough_get_timing waits for the last timed batch
+ * and returns the two durations in milliseconds (EINVAL before any timed
+ * batch). */
+hough_status hough_set_timing(hough_ctx *ctx, int32_t enable);
+hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms);
+
 const char *hough_status_str(hough_status status);
 /* Text of the last HIP failure seen by this thread (empty if none). */
 const char *hough_last_error(void);

@@ -3,9 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -39,15 +39,16 @@ hough_status device_error(hipError_t e, const char *what) {
 struct BatchHeader {
     int32_t n_events;
     int32_t n_items;
-    int32_t pad_[2];
+    int64_t n_hits;
 };
 
 struct GraphKey {
     const void *x, *y, *acc, *cands, *n_found, *n_votes;
     int32_t threshold;
+    int64_t hit_bucket;
     bool operator==(const GraphKey &o) const {
         return x == o.x && y == o.y && acc == o.acc && cands == o.cands && n_found == o.n_found &&
-               n_votes == o.n_votes && threshold == o.threshold;
+               n_votes == o.n_votes && threshold == o.threshold && hit_bucket == o.hit_bucket;
     }
 };
 
@@ -56,12 +57,17 @@ struct GraphEntry {
     hipGraphExec_t exec;
 };
 
+// Tile heights a batched vote can use; workspace is sized for all of them.
+constexpr int32_t kBatchRows[] = {64, 128};
+
 }  // namespace
 
 struct hough_ctx {
     hough_grid grid;
     GridArgs g;
     bool u16;
+    bool fused_batch;          // 2D int32: peaks searched inside the vote tiles
+    bool cull_ok;              // phi0 table holds the bin centres: tile masks allowed
     int32_t max_events;
     int64_t max_hits;
     int device;
@@ -70,16 +76,17 @@ struct hough_ctx {
     int32_t persistent_groups;
 
     // sort workspace
-    int64_t bound;             // max candidates per event (any pass-0 layout)
+    int64_t bound;             // max candidates per event (any first-pass layout)
     int32_t hist_chunks;
-    int32_t n_chunks0;         // peak blocks per event
-    int32_t cap0;              // peak block capacity
+    int32_t max_blocks0;
     EventState *state = nullptr;
     Cand *stage = nullptr;     // also the second ping-pong buffer
     int32_t *cnt0 = nullptr;
     uint32_t *hist = nullptr;
     Cand *tmp0 = nullptr;
     uint32_t *acc_ws = nullptr;   // batch accumulators when the caller passes none
+    uint32_t *mask = nullptr;     // [n_d0][max_hits], when cull_ok
+    uint32_t *ones = nullptr;     // one all-ones mask word: culling off
 
     // batch descriptors
     size_t desc_bytes = 0;
@@ -90,24 +97,36 @@ struct hough_ctx {
     hipEvent_t desc_done = nullptr;
     bool desc_in_flight = false;
     std::vector<int64_t> last_hit_off, last_cand_off;   // what desc_host currently holds
+    bool last_fused = false;                             // ... and for which tile layout
     hipStream_t capture_stream = nullptr;
     std::vector<GraphEntry> graphs;
+
+    // timing mode: batches run without a graph, with events around the vote
+    bool timing = false;
+    bool timed_once = false;
+    hipEvent_t ev_start = nullptr, ev_vote0 = nullptr, ev_vote1 = nullptr, ev_end = nullptr;
 };
 
 namespace {
 
+void drop_graphs(hough_ctx *c) {
+    for (auto &ge : c->graphs)
+        (void)hipGraphExecDestroy(ge.exec);
+    c->graphs.clear();
+}
+
 void free_ctx(hough_ctx *c) {
     if (!c)
         return;
-    for (auto &ge : c->graphs)
-        (void)hipGraphExecDestroy(ge.exec);
-    if (c->desc_done)
-        (void)hipEventDestroy(c->desc_done);
+    drop_graphs(c);
+    for (hipEvent_t ev : {c->desc_done, c->ev_start, c->ev_vote0, c->ev_vote1, c->ev_end})
+        if (ev)
+            (void)hipEventDestroy(ev);
     if (c->capture_stream)
         (void)hipStreamDestroy(c->capture_stream);
     if (c->desc_host)
         (void)hipHostFree(c->desc_host);
-    void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->desc_dev,
+    void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->mask, c->ones, c->desc_dev,
                    c->work_counter};
     for (void *p : dev)
         if (p)
@@ -115,16 +134,37 @@ void free_ctx(hough_ctx *c) {
     delete c;
 }
 
-int32_t tiles_per_event(const hough_ctx *c, const VoteShape &s) {
-    return c->g.n_d0 * ((c->g.n_phi + s.rows - 1) / s.rows);
+int32_t batch_tiles_per_event(const hough_ctx *c, const VoteShape &s, bool fused) {
+    return c->g.n_d0 * vote_tiles_per_slice(c->g, s, fused);
 }
 
-SortWork make_sort_work(hough_ctx *c) {
+bool use_mask(const hough_ctx *c, const VoteShape &s, bool fused) {
+    return c->cull_ok && vote_tiles_per_slice(c->g, s, fused) <= 32;
+}
+
+VoteInputs vote_inputs(const hough_ctx *c, const float *x, const float *y, bool masked) {
+    VoteInputs in{};
+    in.x = x;
+    in.y = y;
+    in.mask = masked ? c->mask : c->ones;
+    in.mask_stride = masked ? c->max_hits : 0;
+    in.mask_step = masked ? 1 : 0;
+    return in;
+}
+
+SortWork sort_work(const hough_ctx *c, bool fused_layout) {
     SortWork w{};
     w.s0.stage = c->stage;
     w.s0.cnt0 = c->cnt0;
-    w.s0.n_chunks0 = c->n_chunks0;
-    w.s0.cap0 = c->cap0;
+    if (fused_layout) {
+        w.s0.n_blocks0 = vote_tiles_per_slice(c->g, c->shape_batch, true);
+        w.s0.cap0 = fused_chunk_cap(c->g, c->shape_batch);
+        w.s0.cb = 1;
+    } else {
+        w.s0.n_blocks0 = peak_blocks_per_event(c->g);
+        w.s0.cap0 = peak_block_cap(c->g);
+        w.s0.cb = peak_blocks_per_chunk(c->g);
+    }
     w.hist = c->hist;
     w.hist_chunks = c->hist_chunks;
     w.tmp0 = c->tmp0;
@@ -142,18 +182,41 @@ hipError_t dev_alloc(T **p, size_t count) {
     return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
 }
 
+// Does the phi0 table hold the bin centres (j + 1/2) 2 pi / n_phi?  The tile
+// masks assume it; any other table just turns culling off.
+bool table_is_bin_centres(const hough_grid *grid) {
+    const size_t n = static_cast<size_t>(grid->n_phi);
+    std::vector<float> c(n), s(n);
+    if (hipMemcpy(c.data(), grid->cos_phi, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(s.data(), grid->sin_phi, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return false;
+    const double two_pi = 6.283185307179586;
+    for (size_t j = 0; j < n; ++j) {
+        const double want = (static_cast<double>(j) + 0.5) * two_pi / static_cast<double>(n);
+        const double got = std::atan2(static_cast<double>(s[j]), static_cast<double>(c[j]));
+        double diff = std::fmod(got - want, two_pi);
+        if (diff > two_pi / 2)
+            diff -= two_pi;
+        if (diff < -two_pi / 2)
+            diff += two_pi;
+        const double norm = std::hypot(static_cast<double>(c[j]), static_cast<double>(s[j]));
+        if (!(std::fabs(diff) < 1e-6) || !(std::fabs(norm - 1.0) < 1e-6))
+            return false;
+    }
+    return true;
+}
 
 // Write the batch descriptors (header, per-event ranges, largest-first work
 // list) into the pinned staging block, unless it already holds this batch.
 // *changed tells the caller whether the device copy must be refreshed.
 hough_status stage_descriptors(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off,
-                               const int64_t *cand_off, bool *changed) {
+                               const int64_t *cand_off, bool fused, bool *changed) {
     const size_t n = static_cast<size_t>(n_events) + 1;
     std::vector<int64_t> co(n, 0);
     if (cand_off)
         co.assign(cand_off, cand_off + n);
     if (ctx->last_hit_off.size() == n && std::equal(hit_off, hit_off + n, ctx->last_hit_off.begin()) &&
-        ctx->last_cand_off == co) {
+        ctx->last_cand_off == co && ctx->last_fused == fused) {
         *changed = false;
         return HOUGH_OK;
     }
@@ -161,13 +224,14 @@ hough_status stage_descriptors(hough_ctx *ctx, int32_t n_events, const int64_t *
     if (ctx->desc_in_flight)
         HIP_TRY(hipEventSynchronize(ctx->desc_done));
     ctx->desc_in_flight = false;
-    const int32_t tpe = tiles_per_event(ctx, ctx->shape_batch);
+    const int32_t tpe = batch_tiles_per_event(ctx, ctx->shape_batch, fused);
     auto *hdr = reinterpret_cast<BatchHeader *>(ctx->desc_host);
     auto *desc = reinterpret_cast<EventDesc *>(ctx->desc_host + sizeof(BatchHeader));
     auto *items = reinterpret_cast<WorkItem *>(ctx->desc_host + sizeof(BatchHeader) +
                                                static_cast<size_t>(ctx->max_events) * sizeof(EventDesc));
     hdr->n_events = n_events;
     hdr->n_items = n_events * tpe;
+    hdr->n_hits = hit_off[n_events];
     for (int32_t e = 0; e < n_events; ++e) {
         desc[e].hit_begin = hit_off[e];
         desc[e].hit_end = hit_off[e + 1];
@@ -187,6 +251,7 @@ hough_status stage_descriptors(hough_ctx *ctx, int32_t n_events, const int64_t *
             items[n_items++] = WorkItem{e, t};
     ctx->last_hit_off.assign(hit_off, hit_off + n);
     ctx->last_cand_off = co;
+    ctx->last_fused = fused;
     *changed = true;
     return HOUGH_OK;
 }
@@ -207,11 +272,74 @@ hough_status check_batch(const hough_ctx *ctx, int32_t n_events, const int64_t *
     return HOUGH_OK;
 }
 
+struct DevDesc {
+    BatchHeader *hdr;
+    EventDesc *desc;
+    WorkItem *items;
+};
+
+DevDesc device_descriptors(const hough_ctx *ctx) {
+    char *dd = ctx->desc_dev;
+    DevDesc d;
+    d.hdr = reinterpret_cast<BatchHeader *>(dd);
+    d.desc = reinterpret_cast<EventDesc *>(dd + sizeof(BatchHeader));
+    d.items = reinterpret_cast<WorkItem *>(dd + sizeof(BatchHeader) +
+                                           static_cast<size_t>(ctx->max_events) * sizeof(EventDesc));
+    return d;
+}
+
+// Hit counts are rounded up to this granularity in the captured graphs (the
+// exact count is read on the device).
+constexpr int64_t kHitBucket = 1 << 16;
+
+
+// The launch sequence of one batch (after the descriptor upload): reset,
+// tile masks, vote (fused with the peak search for 2D int32), sort.  With
+// `timed`, events bracket the whole sequence and the vote kernel.
+hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const float *y, int32_t threshold,
+                         void *acc, hough_cand *cands, int32_t *n_found, uint64_t *n_votes, int64_t bucket,
+                         bool timed) {
+    DevDesc dd = device_descriptors(ctx);
+    const VoteShape &vs = ctx->shape_batch;
+    const bool fused = ctx->fused_batch;
+    const bool masked = use_mask(ctx, vs, fused);
+    SortWork w = sort_work(ctx, fused);
+    w.desc = dd.desc;
+    w.out = cands;
+    w.n_found = n_found;
+    w.n_events_dev = &dd.hdr->n_events;
+    auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
+    uint32_t *acc_dw = static_cast<uint32_t *>(acc);
+    hipError_t ce = hipSuccess;
+    if (timed)
+        ce = hipEventRecord(ctx->ev_start, cs);
+    if (ce == hipSuccess)
+        ce = launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, cs);
+    if (ce == hipSuccess && masked)
+        ce = launch_hit_prep(ctx->g, vs, fused, x, y, bucket, &dd.hdr->n_hits, ctx->mask, ctx->max_hits, cs);
+    if (ce == hipSuccess && timed)
+        ce = hipEventRecord(ctx->ev_vote0, cs);
+    uint32_t *a = (fused || acc_dw) ? acc_dw : ctx->acc_ws;
+    if (ce == hipSuccess)
+        ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, x, y, masked), dd.desc,
+                               &dd.hdr->n_items, dd.items, ctx->max_items, ctx->work_counter,
+                               ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs);
+    if (ce == hipSuccess && timed)
+        ce = hipEventRecord(ctx->ev_vote1, cs);
+    if (ce == hipSuccess && !fused)
+        ce = launch_peaks(ctx->g, ctx->u16, a, ctx->max_events, threshold, w, cs);
+    if (ce == hipSuccess)
+        ce = launch_sort(w, ctx->max_events, cs);
+    if (ce == hipSuccess && timed)
+        ce = hipEventRecord(ctx->ev_end, cs);
+    return ce;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *hough_version(void) { return "hough-mi355x 0.1"; }
+const char *hough_version(void) { return "hough-mi355x 0.2"; }
 
 const char *hough_status_str(hough_status s) {
     switch (s) {
@@ -249,7 +377,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     if (o.max_events == 0)
         o.max_events = 1;
     if (o.max_hits == 0)
-        o.max_hits = 1 << 20;
+        o.max_hits = 1 << 18;
 
     hough_ctx *c = new (std::nothrow) hough_ctx();
     if (!c)
@@ -274,37 +402,60 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
     g.cells = cells;
     g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;
+    c->fused_batch = !u16 && grid->d0 == nullptr;
 
     // Default launch shapes (the autotuner may replace them).
     hipDeviceProp_t prop{};
     (void)hipGetDeviceProperties(&prop, c->device);
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    c->shape_single = VoteShape{u16 ? 64 : 4, 256, 1, 0};
-    if (!vote_shape_supported(c->shape_single, u16, g.row_dwords))
-        c->shape_single = VoteShape{8, 256, 1, 0};
-    c->shape_batch = VoteShape{u16 ? 64 : 32, 512, 1, 0};
-    if (!vote_shape_supported(c->shape_batch, u16, g.row_dwords))
-        c->shape_batch = VoteShape{8, 256, 1, 0};
-    c->persistent_groups = cus * 4;
+    c->shape_single = VoteShape{64, 512, u16 ? 1 : 4, 0};
+    c->shape_batch = VoteShape{64, 512, 1, 0};
+    if (!vote_shape_supported(c->shape_single, u16, g.row_dwords) ||
+        !vote_shape_supported(c->shape_batch, u16, g.row_dwords)) {
+        delete c;
+        return HOUGH_EINVAL;   // a kappa row too long for a 64-row LDS tile
+    }
+    c->persistent_groups = cus * 2;
+    c->cull_ok = table_is_bin_centres(grid);
 
-    // Sort workspace sized for the peak-block layout.
-    c->n_chunks0 = peak_blocks_per_event(g);
-    c->cap0 = peak_chunk_cap(g);
-    c->bound = static_cast<int64_t>(c->n_chunks0) * c->cap0;
+    // Sort workspace sized for every first-pass layout: peak blocks, and
+    // fused tiles of each batched tile height.
+    const int32_t pb = peak_blocks_per_event(g);
+    int64_t bound = static_cast<int64_t>(pb) * peak_block_cap(g);
+    int32_t first_chunks = (pb + peak_blocks_per_chunk(g) - 1) / peak_blocks_per_chunk(g);
+    int32_t max_blocks = pb;
+    if (c->fused_batch) {
+        for (int32_t rows : kBatchRows) {
+            VoteShape s{rows, 256, 1, 0};
+            const int32_t tiles = vote_tiles_per_slice(g, s, true);
+            bound = std::max<int64_t>(bound, static_cast<int64_t>(tiles) * fused_chunk_cap(g, s));
+            first_chunks = std::max(first_chunks, tiles);
+            max_blocks = std::max(max_blocks, tiles);
+        }
+    }
+    c->bound = bound;
+    c->max_blocks0 = max_blocks;
     const int64_t later = (c->bound + kSortChunk - 1) / kSortChunk;
-    c->hist_chunks = static_cast<int32_t>(std::max<int64_t>(c->n_chunks0, later));
+    c->hist_chunks = static_cast<int32_t>(std::max<int64_t>(first_chunks, later));
     const size_t E = static_cast<size_t>(c->max_events);
-    // Work list: the largest tile count any shape can produce (8 rows).
-    c->max_items = static_cast<int32_t>(E) * g.n_d0 * ((g.n_phi + 7) / 8);
+    int32_t max_tpe = 0;
+    for (int32_t rows : kBatchRows)
+        max_tpe = std::max(max_tpe, g.n_d0 * vote_tiles_per_slice(g, VoteShape{rows, 256, 1, 0}, c->fused_batch));
+    c->max_items = static_cast<int32_t>(E) * max_tpe;
     c->desc_bytes = sizeof(BatchHeader) + E * sizeof(EventDesc) + static_cast<size_t>(c->max_items) * sizeof(WorkItem);
 
     hipError_t e = hipSuccess;
     e = e ? e : dev_alloc(&c->state, E);
     e = e ? e : dev_alloc(&c->stage, E * static_cast<size_t>(c->bound));
-    e = e ? e : dev_alloc(&c->cnt0, E * c->n_chunks0);
+    e = e ? e : dev_alloc(&c->cnt0, E * static_cast<size_t>(c->max_blocks0));
     e = e ? e : dev_alloc(&c->hist, E * static_cast<size_t>(c->hist_chunks) * kDigits);
     e = e ? e : dev_alloc(&c->tmp0, E * static_cast<size_t>(c->bound));
     e = e ? e : dev_alloc(&c->acc_ws, E * static_cast<size_t>(g.acc_dwords));
+    if (c->cull_ok)
+        e = e ? e : dev_alloc(&c->mask, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
+    e = e ? e : dev_alloc(&c->ones, 1);
+    if (e == hipSuccess)
+        e = hipMemset(c->ones, 0xff, sizeof(uint32_t));
     e = e ? e : dev_alloc(&c->desc_dev, c->desc_bytes);
     e = e ? e : dev_alloc(&c->work_counter, 1);
     if (e == hipSuccess)
@@ -313,6 +464,9 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         e = hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    for (hipEvent_t *ev : {&c->ev_start, &c->ev_vote0, &c->ev_vote1, &c->ev_end})
+        if (e == hipSuccess)
+            e = hipEventCreate(ev);
     if (e != hipSuccess) {
         const bool oom = e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation;
         hough_status st = oom ? HOUGH_ENOMEM : device_error(e, "hough_ctx_create");
@@ -341,16 +495,39 @@ hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32
         return HOUGH_EINVAL;
     if (!vote_shape_supported(s, ctx->u16, ctx->g.row_dwords))
         return HOUGH_EINVAL;
-    if (which == 1 && tiles_per_event(ctx, s) * static_cast<int64_t>(ctx->max_events) > ctx->max_items)
+    if (which == 1 && std::max(batch_tiles_per_event(ctx, s, true), batch_tiles_per_event(ctx, s, false)) *
+                              static_cast<int64_t>(ctx->max_events) > ctx->max_items)
         return HOUGH_EINVAL;
+    if (ctx->desc_in_flight)
+        HIP_TRY(hipEventSynchronize(ctx->desc_done));
     if (which == 0)
         ctx->shape_single = s;
     else
         ctx->shape_batch = s;
-    // Cached graphs embed the old shape.
-    for (auto &ge : ctx->graphs)
-        (void)hipGraphExecDestroy(ge.exec);
-    ctx->graphs.clear();
+    drop_graphs(ctx);               // cached graphs embed the old shape
+    ctx->last_hit_off.clear();      // the work list depends on the tile shape
+    return HOUGH_OK;
+}
+
+hough_status hough_set_timing(hough_ctx *ctx, int32_t enable) {
+    if (!ctx)
+        return HOUGH_EINVAL;
+    ctx->timing = enable != 0;
+    ctx->timed_once = false;
+    return HOUGH_OK;
+}
+
+hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms) {
+    if (!ctx || !ctx->timed_once)
+        return HOUGH_EINVAL;
+    HIP_TRY(hipEventSynchronize(ctx->ev_end));
+    float v = 0.0f, t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&v, ctx->ev_vote0, ctx->ev_vote1));
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev_start, ctx->ev_end));
+    if (vote_ms)
+        *vote_ms = v;
+    if (total_ms)
+        *total_ms = t;
     return HOUGH_OK;
 }
 
@@ -382,10 +559,14 @@ hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t 
         return HOUGH_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
+    const VoteShape &vs = ctx->shape_single;
+    const bool masked = use_mask(ctx, vs, false);
     if (nv)
         HIP_TRY(launch_prep(nullptr, 1, nv, s));
-    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, ctx->shape_single, x, y, n_hits, static_cast<uint32_t *>(acc),
-                               nv, s));
+    if (masked)
+        HIP_TRY(launch_hit_prep(ctx->g, vs, false, x, y, n_hits, nullptr, ctx->mask, ctx->max_hits, s));
+    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, vs, vote_inputs(ctx, x, y, masked), n_hits,
+                               static_cast<uint32_t *>(acc), nv, s));
     return HOUGH_OK;
 }
 
@@ -396,13 +577,42 @@ hough_status hough_peaks(hough_ctx *ctx, const void *acc, int32_t threshold, hou
     if (reinterpret_cast<uintptr_t>(acc) & 3u)
         return HOUGH_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SortWork w = make_sort_work(ctx);
+    SortWork w = sort_work(ctx, false);
     w.out = out;
     w.cap = cap;
     w.n_found = n_found;
     HIP_TRY(launch_prep(ctx->state, 1, nullptr, s));
     HIP_TRY(launch_peaks(ctx->g, ctx->u16, static_cast<const uint32_t *>(acc), 1, threshold, w, s));
     HIP_TRY(launch_sort(w, 1, s));
+    return HOUGH_OK;
+}
+
+hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
+                              const float *y, void *acc, uint64_t *n_votes, void *stream) {
+    if (check_batch(ctx, n_events, hit_off, x, y) != HOUGH_OK || !acc)
+        return HOUGH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(acc) & 3u)
+        return HOUGH_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool changed = false;
+    hough_status st = stage_descriptors(ctx, n_events, hit_off, nullptr, false, &changed);
+    if (st != HOUGH_OK)
+        return st;
+    DevDesc dd = device_descriptors(ctx);
+    if (changed) {
+        HIP_TRY(hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(ctx->desc_done, s));
+        ctx->desc_in_flight = true;
+    }
+    const VoteShape &vs = ctx->shape_batch;
+    const bool masked = use_mask(ctx, vs, false);
+    auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
+    HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, s));
+    if (masked)
+        HIP_TRY(launch_hit_prep(ctx->g, vs, false, x, y, hit_off[n_events], nullptr, ctx->mask, ctx->max_hits, s));
+    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, x, y, masked), dd.desc, &dd.hdr->n_items,
+                              dd.items, ctx->max_items, ctx->work_counter, ctx->persistent_groups,
+                              static_cast<uint32_t *>(acc), nv, nullptr, 0, s));
     return HOUGH_OK;
 }
 
@@ -423,42 +633,34 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     bool changed = false;
-    hough_status st = stage_descriptors(ctx, n_events, hit_off, cand_off, &changed);
+    hough_status st = stage_descriptors(ctx, n_events, hit_off, cand_off, ctx->fused_batch, &changed);
     if (st != HOUGH_OK)
         return st;
-    const VoteShape &vs = ctx->shape_batch;
 
-    GraphKey key{x, y, acc, cands, n_found, n_votes, threshold};
+    const int64_t bucket = (hit_off[n_events] + kHitBucket - 1) / kHitBucket * kHitBucket;
+    GraphKey key{x, y, acc, cands, n_found, n_votes, threshold, bucket};
     hipGraphExec_t exec = nullptr;
     for (auto &ge : ctx->graphs)
         if (ge.key == key)
             exec = ge.exec;
+    if (ctx->timing) {
+        // Direct launches with events around the vote (no graph).
+        if (changed)
+            HIP_TRY(hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(enqueue_batch(ctx, s, x, y, threshold, acc, cands, n_found, n_votes, bucket, true));
+        ctx->timed_once = true;
+        if (changed) {
+            HIP_TRY(hipEventRecord(ctx->desc_done, s));
+            ctx->desc_in_flight = true;
+        }
+        return HOUGH_OK;
+    }
     if (!exec) {
         hipStream_t cs = ctx->capture_stream;
-        char *dd = ctx->desc_dev;
-        auto *d_hdr = reinterpret_cast<BatchHeader *>(dd);
-        auto *d_desc = reinterpret_cast<EventDesc *>(dd + sizeof(BatchHeader));
-        auto *d_items = reinterpret_cast<WorkItem *>(dd + sizeof(BatchHeader) +
-                                                     static_cast<size_t>(ctx->max_events) * sizeof(EventDesc));
-        (void)d_hdr;
-        uint32_t *acc_dw = acc ? static_cast<uint32_t *>(acc) : ctx->acc_ws;
-        SortWork w = make_sort_work(ctx);
-        w.desc = d_desc;
-        w.out = cands;
-        w.n_found = n_found;
-        w.n_events_dev = &d_hdr->n_events;
-        auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        hipError_t ce = hipMemcpyAsync(dd, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, cs);
+        hipError_t ce = hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, cs);
         if (ce == hipSuccess)
-            ce = launch_prep_batch(ctx->state, ctx->max_events, &d_hdr->n_events, nv, ctx->work_counter, cs);
-        if (ce == hipSuccess)
-            ce = launch_vote_batch(ctx->g, ctx->u16, vs, x, y, d_desc, &d_hdr->n_items, d_items, ctx->max_items,
-                                   ctx->work_counter, ctx->persistent_groups, acc_dw, nv, cs);
-        if (ce == hipSuccess)
-            ce = launch_peaks(ctx->g, ctx->u16, acc_dw, ctx->max_events, threshold, w, cs);
-        if (ce == hipSuccess)
-            ce = launch_sort(w, ctx->max_events, cs);
+            ce = enqueue_batch(ctx, cs, x, y, threshold, acc, cands, n_found, n_votes, bucket, false);
         hipGraph_t graph = nullptr;
         hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (ce != hipSuccess) {
@@ -484,35 +686,6 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
         HIP_TRY(hipEventRecord(ctx->desc_done, s));
         ctx->desc_in_flight = true;
     }
-    return HOUGH_OK;
-}
-
-hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
-                              const float *y, void *acc, uint64_t *n_votes, void *stream) {
-    if (check_batch(ctx, n_events, hit_off, x, y) != HOUGH_OK || !acc)
-        return HOUGH_EINVAL;
-    if (reinterpret_cast<uintptr_t>(acc) & 3u)
-        return HOUGH_EINVAL;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    bool changed = false;
-    hough_status st = stage_descriptors(ctx, n_events, hit_off, nullptr, &changed);
-    if (st != HOUGH_OK)
-        return st;
-    char *dd = ctx->desc_dev;
-    auto *d_hdr = reinterpret_cast<BatchHeader *>(dd);
-    auto *d_desc = reinterpret_cast<EventDesc *>(dd + sizeof(BatchHeader));
-    auto *d_items = reinterpret_cast<WorkItem *>(dd + sizeof(BatchHeader) +
-                                                 static_cast<size_t>(ctx->max_events) * sizeof(EventDesc));
-    if (changed) {
-        HIP_TRY(hipMemcpyAsync(dd, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipEventRecord(ctx->desc_done, s));
-        ctx->desc_in_flight = true;
-    }
-    auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
-    HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &d_hdr->n_events, nv, ctx->work_counter, s));
-    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, ctx->shape_batch, x, y, d_desc, &d_hdr->n_items, d_items,
-                              ctx->max_items, ctx->work_counter, ctx->persistent_groups,
-                              static_cast<uint32_t *>(acc), nv, s));
     return HOUGH_OK;
 }
 

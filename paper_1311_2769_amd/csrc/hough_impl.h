@@ -66,13 +66,16 @@ struct GridArgs {
     int64_t acc_dwords;   // dwords per event accumulator
 };
 
-// Where the pass-0 candidate lists of every event live.  Chunk c of event e
-// holds cnt0[e*n_chunks0 + c] candidates at stage + (e*n_chunks0 + c)*cap0.
+// Where the first-pass candidate lists of every event live.  List (block) b
+// of event e holds cnt0[e*n_blocks0 + b] candidates at
+// stage + (e*n_blocks0 + b)*cap0; first-pass chunk c is blocks
+// [c*cb, (c+1)*cb).
 struct Stage0 {
     Cand *stage;
     int32_t *cnt0;
-    int32_t n_chunks0;
+    int32_t n_blocks0;
     int32_t cap0;
+    int32_t cb;
 };
 
 struct SortWork {
@@ -91,6 +94,15 @@ struct SortWork {
     const int32_t *n_events_dev;  // batch: live event count on the device, or nullptr
 };
 
+// Hit inputs of a vote launch: coordinates and optional tile masks.
+struct VoteInputs {
+    const float *x;
+    const float *y;
+    const uint32_t *mask;      // [n_d0][mask_stride] tile masks, or one all-ones word
+    int64_t mask_stride;       // 0 with the all-ones word
+    int32_t mask_step;         // 1 with masks, 0 with the all-ones word
+};
+
 // Launch shape of a vote kernel.
 struct VoteShape {
     int32_t rows;     // phi0 rows per tile
@@ -104,6 +116,8 @@ struct VoteShape {
 // ---------------------------------------------------------------------------
 bool vote_shape_supported(const VoteShape &s, bool u16, int32_t row_dwords);
 size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords);
+int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
+int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);
 
 hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *n_votes,
                        hipStream_t stream);
@@ -111,23 +125,30 @@ hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *
 hipError_t launch_prep_batch(EventState *state, int32_t max_events, const int32_t *n_events_dev,
                              unsigned long long *n_votes, int32_t *work_counter, hipStream_t stream);
 hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
+// Tile masks of every hit (for the given tile shape): bit t of
+// mask[l*mask_stride + h] is set when hit h may vote in tile t of d0 slice l.
+hipError_t launch_hit_prep(const GridArgs &g, const VoteShape &s, bool fused, const float *x, const float *y,
+                           int64_t n_hits, const int64_t *n_hits_dev, uint32_t *mask, int64_t mask_stride,
+                           hipStream_t stream);
 
 // One event: hits [0, n_hits).
-hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const float *x,
-                              const float *y, int32_t n_hits, uint32_t *acc,
-                              unsigned long long *n_votes, hipStream_t stream);
+hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,
+                              int32_t n_hits, uint32_t *acc, unsigned long long *n_votes, hipStream_t stream);
 // Many events: tile work items over events described by desc; the live item
 // count is read on the device.  With a work counter (reset beforehand) the
 // launch is persistent: persistent_groups workgroups pull items in order.
-hipError_t launch_vote_batch(const GridArgs &g, bool u16, const VoteShape &s, const float *x,
-                             const float *y, const EventDesc *desc, const int32_t *n_items_dev,
-                             const WorkItem *items, int32_t max_items, int32_t *work_counter,
-                             int32_t persistent_groups, uint32_t *acc,
-                             unsigned long long *n_votes, hipStream_t stream);
+// fused (2D int32 only): tiles also search their interior rows for peaks into
+// the staging lists of *w; acc may then be nullptr.
+hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const VoteShape &s, const VoteInputs &in,
+                             const EventDesc *desc, const int32_t *n_items_dev, const WorkItem *items,
+                             int32_t max_items, int32_t *work_counter, int32_t persistent_groups, uint32_t *acc,
+                             unsigned long long *n_votes, const SortWork *w, int32_t threshold,
+                             hipStream_t stream);
 
-constexpr int kPeakRows = 16;         // phi0 rows per peak-search block
+constexpr int kPeakRows = 8;          // phi0 rows per peak-search block
 int32_t peak_blocks_per_event(const GridArgs &g);
-int32_t peak_chunk_cap(const GridArgs &g);
+int32_t peak_block_cap(const GridArgs &g);
+int32_t peak_blocks_per_chunk(const GridArgs &g);
 hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_t n_events,
                         int32_t threshold, const SortWork &w, hipStream_t stream);
 hipError_t launch_sort(const SortWork &w, int32_t n_events, hipStream_t stream);

@@ -25,7 +25,8 @@ ACC_I32, ACC_U16 = 0, 1
 SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
     "hough_vote_batch",
-    "hough_set_launch", "hough_get_launch", "hough_status_str", "hough_last_error", "hough_version",
+    "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
+    "hough_status_str", "hough_last_error", "hough_version",
 )
 
 
@@ -81,6 +82,10 @@ def load(path: str = LIB_PATH):
     lib.hough_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
     lib.hough_get_launch.restype = i32
     lib.hough_get_launch.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
+    lib.hough_set_timing.restype = i32
+    lib.hough_set_timing.argtypes = [vp, i32]
+    lib.hough_get_timing.restype = i32
+    lib.hough_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     lib.hough_status_str.restype = ctypes.c_char_p
     lib.hough_status_str.argtypes = [i32]
     lib.hough_last_error.restype = ctypes.c_char_p
@@ -247,6 +252,15 @@ class HoughContext:
 
     def set_launch(self, which, rows, threads, split=1, pad=0):
         _check(self.lib.hough_set_launch(self.handle, which, rows, threads, split, pad), "hough_set_launch")
+
+    def set_timing(self, enable: bool):
+        _check(self.lib.hough_set_timing(self.handle, 1 if enable else 0), "hough_set_timing")
+
+    def get_timing(self):
+        """(vote_ms, total_ms) of the last timed batch (waits for it)."""
+        v, t = ctypes.c_float(), ctypes.c_float()
+        _check(self.lib.hough_get_timing(self.handle, ctypes.byref(v), ctypes.byref(t)), "hough_get_timing")
+        return v.value, t.value
 
     def get_launch(self, which):
         vals = [ctypes.c_int32() for _ in range(4)]

@@ -73,8 +73,8 @@ def test_workload_event_matches_oracle(cfg):
     _assert_same(_gpu_find(ctx, ev.x, ev.y, wc.threshold), ref, f"workload {cfg}")
 
 
-@pytest.mark.parametrize("shape", [(4, 256, 1, 0), (8, 256, 2, 1), (16, 512, 1, 0), (32, 1024, 3, 1),
-                                   (64, 256, 1, 0), (64, 1024, 4, 1)])
+@pytest.mark.parametrize("shape", [(64, 256, 1, 0), (64, 512, 4, 1), (64, 1024, 2, 0), (64, 512, 16, 0),
+                                   (64, 256, 64, 1)])
 def test_vote_launch_shapes_agree_2d(shape):
     print(f"[parity] 2D shape {shape}", flush=True)
     wc = synth.CONFIGS[2]
@@ -89,7 +89,7 @@ def test_vote_launch_shapes_agree_2d(shape):
     assert int(nv.item()) == ref[1]
 
 
-@pytest.mark.parametrize("shape", [(8, 256, 1, 0), (32, 512, 2, 1), (64, 1024, 1, 0), (128, 256, 1, 1)])
+@pytest.mark.parametrize("shape", [(64, 256, 1, 0), (64, 512, 2, 1), (128, 1024, 1, 0), (128, 256, 3, 1)])
 def test_vote_launch_shapes_agree_3d(shape):
     print(f"[parity] 3D shape {shape}", flush=True)
     wc = synth.CONFIGS[3]
@@ -137,8 +137,12 @@ def test_odd_small_grids(dims):
     ev = synth.gen_config_event(1)
     ref = oracle.find(ev.x, ev.y, grid, 2)
     ctx = hough.HoughContext(grid)
-    for rows in (4, 8, 64):
-        ctx.set_launch(0, rows, 256, 1, 0)
+    for rows, threads, split in ((64, 256, 1), (64, 512, 3), (128, 256, 1)):
+        try:
+            ctx.set_launch(0, rows, threads, split, 0)
+        except hough.HoughError:
+            assert rows * (ctx.spec.n_kappa // (2 if ctx.spec.acc_u16 else 1)) * 4 > 120000
+            continue
         _assert_same(_gpu_find(ctx, ev.x, ev.y, 2), ref, f"grid {dims} rows {rows}")
 
 
@@ -208,6 +212,8 @@ def test_invalid_arguments_raise():
         ctx.vote(x, x)                                     # more than max_hits
     with pytest.raises(hough.HoughError):
         ctx.set_launch(0, 24, 256, 1, 0)                   # unsupported tile height
+    with pytest.raises(hough.HoughError):
+        ctx.set_launch(0, 64, 384, 1, 0)                   # unsupported workgroup size
     big = hough.HoughContext(synth.GRID_2D)
     with pytest.raises(hough.HoughError):
         big.set_launch(0, 128, 512, 1, 0)                  # 256 KiB of LDS
@@ -323,3 +329,107 @@ def test_batch_graph_replay_with_changing_descriptors():
             assert int(nv[k]) == v1 and int(nf[k]) == n
             got = cands[k * cap:k * cap + n].cpu().numpy()
             np.testing.assert_array_equal(got[:, 1], c)
+
+
+# --------------------------------------------------------------------------------------
+# Culling: the tile masks must never drop a vote
+# --------------------------------------------------------------------------------------
+
+def test_culling_stress_displaced_hits_near_the_d0_circles():
+    """Hits whose radius is close to a d0 bin centre (ill-conditioned chords), tiny and huge
+    coordinates, hits on the axes and at bin-edge angles, all against the oracle."""
+    rng = np.random.default_rng(77)
+    grid = synth.GRID_3D
+    d0 = np.abs(grid.d0.astype(np.float64))
+    r = np.concatenate([rng.choice(d0, 3000) + rng.normal(0, 0.05, 3000),
+                        rng.uniform(0.01, 120, 3000), rng.choice(d0, 500) * (1 + rng.normal(0, 1e-4, 500)),
+                        10.0 ** rng.uniform(-20, 20, 200)])
+    phi = np.concatenate([rng.uniform(0, 2 * math.pi, r.size - 400),
+                          (np.arange(400) % 512 + rng.choice([0.0, 0.5], 400)) * 2 * math.pi / 512])
+    x = (r * np.cos(phi)).astype(np.float32)
+    y = (r * np.sin(phi)).astype(np.float32)
+    x[:8] = [0, 0, 5, -5, 1e-39, 3e38, 0, 30]
+    y[:8] = [5, -5, 0, 0, 1e-39, 1, 0, 0]
+    ref = oracle.find(x, y, grid, 3)
+    ctx = hough.HoughContext(grid, max_hits=x.size)
+    for shape in ((64, 512, 1, 0), (128, 256, 1, 0)):
+        ctx.set_launch(0, *shape)
+        _assert_same(_gpu_find(ctx, x, y, 3), ref, f"3D stress {shape}")
+
+
+def test_culling_stress_prompt_hits():
+    rng = np.random.default_rng(78)
+    grid = synth.GRID_2D
+    r = np.concatenate([rng.uniform(0.001, 200, 20000), 10.0 ** rng.uniform(-30, 30, 500)])
+    phi = rng.uniform(-4, 10, r.size)
+    x = (r * np.cos(phi)).astype(np.float32)
+    y = (r * np.sin(phi)).astype(np.float32)
+    ref = oracle.find(x, y, grid, 3)
+    ctx = hough.HoughContext(grid, max_hits=x.size)
+    _assert_same(_gpu_find(ctx, x, y, 3), ref, "2D stress")
+    # the same hits through the fused batch path
+    b = synth.events.pack_events([synth.Event(x=x, y=y, label=np.zeros(x.size, np.int32),
+                                              d0=np.zeros(0), phi0=np.zeros(0), kappa=np.zeros(0))])
+    bctx = hough.HoughContext(grid, max_events=1, max_hits=x.size)
+    res = _batch_results(bctx, b, 3)
+    assert res[0][0] == ref[1] and res[0][1] == ref[4]
+    np.testing.assert_array_equal(res[0][3], ref[3])
+
+
+def test_non_centre_phi_table_turns_culling_off():
+    """A phi0 table that is not the bin centres (here: shifted by a third of a bin) is voted
+    without tile masks and still matches the oracle."""
+    n_phi, n_kappa = 512, 128
+    tab = (np.arange(n_phi) + 0.5 + 1.0 / 3.0) * 2 * math.pi / n_phi
+    grid = make_grid(n_phi, n_kappa, phi_table=tab)
+    ev = synth.gen_config_event(4, 3)
+    ref = oracle.find(ev.x, ev.y, grid, 5)
+    ctx = hough.HoughContext(grid, max_hits=ev.n_hits)
+    _assert_same(_gpu_find(ctx, ev.x, ev.y, 5), ref, "shifted table")
+
+
+def test_more_tiles_than_mask_bits():
+    """4096 phi0 rows make 64 tiles per slice: the masks (32 bits) are not used."""
+    grid = make_grid(4096, 64)
+    ev = synth.gen_config_event(1)
+    ref = oracle.find(ev.x, ev.y, grid, 4)
+    ctx = hough.HoughContext(grid, max_hits=ev.n_hits)
+    _assert_same(_gpu_find(ctx, ev.x, ev.y, 4), ref, "64 tiles")
+    b = synth.events.pack_events([ev, synth.gen_config_event(1, 1)])
+    bctx = hough.HoughContext(grid, max_events=2, max_hits=b.n_hits)
+    res = _batch_results(bctx, b, 4)
+    assert res[0][1] == ref[4]
+    np.testing.assert_array_equal(res[0][3], ref[3])
+
+
+def test_batch_tile_shapes_agree():
+    b = synth.gen_batch(4, 6)
+    g = synth.GRID_2D
+    base = None
+    ctx = hough.HoughContext(g, max_events=6, max_hits=b.n_hits)
+    for shape in ((64, 512), (64, 1024), (64, 256)):
+        ctx.set_launch(1, shape[0], shape[1], 1, 0)
+        res = _batch_results(ctx, b, 7)
+        if base is None:
+            base = res
+        for e in range(6):
+            assert res[e][:2] == base[e][:2]
+            np.testing.assert_array_equal(res[e][3], base[e][3])
+    ev = b.events[2]
+    ra, rnv, rv, rc, rn = oracle.find(ev.x, ev.y, g, 7)
+    assert base[2][0] == rnv and base[2][1] == rn
+    np.testing.assert_array_equal(base[2][3], rc)
+
+
+def test_timing_mode_gives_the_same_results():
+    b = synth.gen_batch(4, 5)
+    ctx = hough.HoughContext(synth.GRID_2D, max_events=5, max_hits=b.n_hits)
+    base = _batch_results(ctx, b, 7)
+    ctx.set_timing(True)
+    timed = _batch_results(ctx, b, 7)
+    v_ms, t_ms = ctx.get_timing()
+    assert 0 < v_ms <= t_ms
+    ctx.set_timing(False)
+    for e in range(5):
+        assert timed[e][:2] == base[e][:2]
+        np.testing.assert_array_equal(timed[e][3], base[e][3])
