@@ -169,6 +169,14 @@ hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows
 hough_status hough_set_timing(hough_ctx *ctx, int32_t enable);
 hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms);
 
+/* Diagnostic: on the current device, compare the vote's division fast path
+ * (the correctly rounded fp32 quotient with its reciprocal refinement done
+ * once per hit) with the division operator, bit for bit, over n pseudo-random
+ * operand pairs of the range where the fast path is used.  Writes the number
+ * of mismatches (must be 0) and of pairs checked.  Allocates and frees a
+ * 16-byte device buffer; synchronous. */
+hough_status hough_selftest_divide(int64_t n, uint64_t seed, uint64_t *mismatches, uint64_t *checked);
+
 const char *hough_status_str(hough_status status);
 /* Text of the last HIP failure seen by this thread (empty if none). */
 const char *hough_last_error(void);

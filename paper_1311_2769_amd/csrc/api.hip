@@ -58,7 +58,7 @@ struct GraphEntry {
 };
 
 // Tile heights a batched vote can use; workspace is sized for all of them.
-constexpr int32_t kBatchRows[] = {64, 128};
+constexpr int32_t kBatchRows[] = {32, 64, 128};
 
 }  // namespace
 
@@ -67,7 +67,7 @@ struct hough_ctx {
     GridArgs g;
     bool u16;
     bool fused_batch;          // 2D int32: peaks searched inside the vote tiles
-    bool cull_ok;              // phi0 table holds the bin centres: tile masks allowed
+    bool cull_ok;              // phi0 table holds the bin centres (n_phi <= 32768): arcs allowed
     int32_t max_events;
     int64_t max_hits;
     int device;
@@ -85,8 +85,8 @@ struct hough_ctx {
     uint32_t *hist = nullptr;
     Cand *tmp0 = nullptr;
     uint32_t *acc_ws = nullptr;   // batch accumulators when the caller passes none
-    uint32_t *mask = nullptr;     // [n_d0][max_hits], when cull_ok
-    uint32_t *ones = nullptr;     // one all-ones mask word: culling off
+    uint2 *arcs = nullptr;        // [n_d0][max_hits], when cull_ok
+    uint2 *full = nullptr;        // one full-circle arc entry: culling off
 
     // batch descriptors
     size_t desc_bytes = 0;
@@ -126,7 +126,7 @@ void free_ctx(hough_ctx *c) {
         (void)hipStreamDestroy(c->capture_stream);
     if (c->desc_host)
         (void)hipHostFree(c->desc_host);
-    void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->mask, c->ones, c->desc_dev,
+    void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->arcs, c->full, c->desc_dev,
                    c->work_counter};
     for (void *p : dev)
         if (p)
@@ -138,17 +138,14 @@ int32_t batch_tiles_per_event(const hough_ctx *c, const VoteShape &s, bool fused
     return c->g.n_d0 * vote_tiles_per_slice(c->g, s, fused);
 }
 
-bool use_mask(const hough_ctx *c, const VoteShape &s, bool fused) {
-    return c->cull_ok && vote_tiles_per_slice(c->g, s, fused) <= 32;
-}
-
-VoteInputs vote_inputs(const hough_ctx *c, const float *x, const float *y, bool masked) {
+VoteInputs vote_inputs(const hough_ctx *c, const float *x, const float *y) {
     VoteInputs in{};
     in.x = x;
     in.y = y;
-    in.mask = masked ? c->mask : c->ones;
-    in.mask_stride = masked ? c->max_hits : 0;
-    in.mask_step = masked ? 1 : 0;
+    in.arcs = c->cull_ok ? c->arcs : c->full;
+    in.arc_stride = c->cull_ok ? c->max_hits : 0;
+    in.arc_step = c->cull_ok ? 1 : 0;
+    in.div_fast = c->cull_ok ? 1 : 0;
     return in;
 }
 
@@ -302,7 +299,6 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
     DevDesc dd = device_descriptors(ctx);
     const VoteShape &vs = ctx->shape_batch;
     const bool fused = ctx->fused_batch;
-    const bool masked = use_mask(ctx, vs, fused);
     SortWork w = sort_work(ctx, fused);
     w.desc = dd.desc;
     w.out = cands;
@@ -315,13 +311,13 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
         ce = hipEventRecord(ctx->ev_start, cs);
     if (ce == hipSuccess)
         ce = launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, cs);
-    if (ce == hipSuccess && masked)
-        ce = launch_hit_prep(ctx->g, vs, fused, x, y, bucket, &dd.hdr->n_hits, ctx->mask, ctx->max_hits, cs);
+    if (ce == hipSuccess && ctx->cull_ok)
+        ce = launch_hit_prep(ctx->g, x, y, bucket, &dd.hdr->n_hits, ctx->arcs, ctx->max_hits, cs);
     if (ce == hipSuccess && timed)
         ce = hipEventRecord(ctx->ev_vote0, cs);
     uint32_t *a = (fused || acc_dw) ? acc_dw : ctx->acc_ws;
     if (ce == hipSuccess)
-        ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, x, y, masked), dd.desc,
+        ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, x, y), dd.desc,
                                &dd.hdr->n_items, dd.items, ctx->max_items, ctx->work_counter,
                                ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs);
     if (ce == hipSuccess && timed)
@@ -416,7 +412,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         return HOUGH_EINVAL;   // a kappa row too long for a 64-row LDS tile
     }
     c->persistent_groups = cus * 2;
-    c->cull_ok = table_is_bin_centres(grid);
+    c->cull_ok = grid->n_phi <= 32768 && table_is_bin_centres(grid);
 
     // Sort workspace sized for every first-pass layout: peak blocks, and
     // fused tiles of each batched tile height.
@@ -452,10 +448,12 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     e = e ? e : dev_alloc(&c->tmp0, E * static_cast<size_t>(c->bound));
     e = e ? e : dev_alloc(&c->acc_ws, E * static_cast<size_t>(g.acc_dwords));
     if (c->cull_ok)
-        e = e ? e : dev_alloc(&c->mask, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
-    e = e ? e : dev_alloc(&c->ones, 1);
-    if (e == hipSuccess)
-        e = hipMemset(c->ones, 0xff, sizeof(uint32_t));
+        e = e ? e : dev_alloc(&c->arcs, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
+    e = e ? e : dev_alloc(&c->full, 1);
+    if (e == hipSuccess) {
+        const uint2 full_circle = make_uint2(static_cast<uint32_t>(g.n_phi) << 16, 0u);
+        e = hipMemcpy(c->full, &full_circle, sizeof(uint2), hipMemcpyHostToDevice);
+    }
     e = e ? e : dev_alloc(&c->desc_dev, c->desc_bytes);
     e = e ? e : dev_alloc(&c->work_counter, 1);
     if (e == hipSuccess)
@@ -560,12 +558,11 @@ hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
     const VoteShape &vs = ctx->shape_single;
-    const bool masked = use_mask(ctx, vs, false);
     if (nv)
         HIP_TRY(launch_prep(nullptr, 1, nv, s));
-    if (masked)
-        HIP_TRY(launch_hit_prep(ctx->g, vs, false, x, y, n_hits, nullptr, ctx->mask, ctx->max_hits, s));
-    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, vs, vote_inputs(ctx, x, y, masked), n_hits,
+    if (ctx->cull_ok)
+        HIP_TRY(launch_hit_prep(ctx->g, x, y, n_hits, nullptr, ctx->arcs, ctx->max_hits, s));
+    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, vs, vote_inputs(ctx, x, y), n_hits,
                                static_cast<uint32_t *>(acc), nv, s));
     return HOUGH_OK;
 }
@@ -605,12 +602,11 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
         ctx->desc_in_flight = true;
     }
     const VoteShape &vs = ctx->shape_batch;
-    const bool masked = use_mask(ctx, vs, false);
     auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
     HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, s));
-    if (masked)
-        HIP_TRY(launch_hit_prep(ctx->g, vs, false, x, y, hit_off[n_events], nullptr, ctx->mask, ctx->max_hits, s));
-    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, x, y, masked), dd.desc, &dd.hdr->n_items,
+    if (ctx->cull_ok)
+        HIP_TRY(launch_hit_prep(ctx->g, x, y, hit_off[n_events], nullptr, ctx->arcs, ctx->max_hits, s));
+    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, x, y), dd.desc, &dd.hdr->n_items,
                               dd.items, ctx->max_items, ctx->work_counter, ctx->persistent_groups,
                               static_cast<uint32_t *>(acc), nv, nullptr, 0, s));
     return HOUGH_OK;

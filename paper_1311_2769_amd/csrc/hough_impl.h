@@ -94,13 +94,14 @@ struct SortWork {
     const int32_t *n_events_dev;  // batch: live event count on the device, or nullptr
 };
 
-// Hit inputs of a vote launch: coordinates and optional tile masks.
+// Hit inputs of a vote launch: coordinates and optional phi0 arcs.
 struct VoteInputs {
     const float *x;
     const float *y;
-    const uint32_t *mask;      // [n_d0][mask_stride] tile masks, or one all-ones word
-    int64_t mask_stride;       // 0 with the all-ones word
-    int32_t mask_step;         // 1 with masks, 0 with the all-ones word
+    const uint2 *arcs;         // [n_d0][arc_stride] arcs per hit, or one full-circle entry
+    int64_t arc_stride;        // 0 with the full-circle entry
+    int32_t arc_step;          // 1 with arcs, 0 with the full-circle entry
+    int32_t div_fast;          // 2D hoisted-reciprocal division allowed (bin-centre phi0 table)
 };
 
 // Launch shape of a vote kernel.
@@ -125,11 +126,10 @@ hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *
 hipError_t launch_prep_batch(EventState *state, int32_t max_events, const int32_t *n_events_dev,
                              unsigned long long *n_votes, int32_t *work_counter, hipStream_t stream);
 hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
-// Tile masks of every hit (for the given tile shape): bit t of
-// mask[l*mask_stride + h] is set when hit h may vote in tile t of d0 slice l.
-hipError_t launch_hit_prep(const GridArgs &g, const VoteShape &s, bool fused, const float *x, const float *y,
-                           int64_t n_hits, const int64_t *n_hits_dev, uint32_t *mask, int64_t mask_stride,
-                           hipStream_t stream);
+// The two phi0 arcs, per hit and d0 slice, outside which a hit cannot vote
+// (arcs[l*arc_stride + h]; each arc packed as start | length << 16, in rows).
+hipError_t launch_hit_prep(const GridArgs &g, const float *x, const float *y, int64_t n_hits,
+                           const int64_t *n_hits_dev, uint2 *arcs, int64_t arc_stride, hipStream_t stream);
 
 // One event: hits [0, n_hits).
 hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,

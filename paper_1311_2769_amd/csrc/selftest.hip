@@ -1,0 +1,84 @@
+// Device self-test of the vote's division fast path (vote_math.h): over n
+// pseudo-random operand pairs drawn across the whole range where the fast
+// path is used, the hoisted-reciprocal sequence must equal the division
+// operator bit for bit.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hough.h"
+#include "vote_math.h"
+
+namespace {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    // SplitMix64 finaliser (Steele, Lea and Flood, 2014).
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// A float with a random mantissa (sometimes all ones or zero) and an
+// exponent uniform in [lo, hi].
+__device__ __forceinline__ float draw(uint64_t bits, int lo, int hi) {
+    uint32_t mant = static_cast<uint32_t>(bits) & 0x7fffffu;
+    const uint32_t kind = static_cast<uint32_t>(bits >> 23) & 15u;
+    if (kind == 0)
+        mant = 0x7fffffu;
+    else if (kind == 1)
+        mant = 0u;
+    else if (kind == 2)
+        mant &= 0x7f0000u;
+    const int e = lo + static_cast<int>((bits >> 32) % static_cast<uint64_t>(hi - lo + 1));
+    const uint32_t sign = static_cast<uint32_t>(bits >> 63) << 31;
+    return __uint_as_float(sign | (static_cast<uint32_t>(e + 127) << 23) | mant);
+}
+
+__global__ void divide_check_kernel(int64_t n, uint64_t seed, unsigned long long *bad, unsigned long long *used) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    unsigned long long nbad = 0, nused = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t h1 = mix64(seed + 2 * static_cast<uint64_t>(i));
+        const uint64_t h2 = mix64(seed + 2 * static_cast<uint64_t>(i) + 1);
+        const float b = fabsf(draw(h1, -31, 31));     // denominators are positive squares
+        const float a = draw(h2, -62, 32);
+        if (!hough::quot_den_ok(b) || !hough::quot_num_ok(a))
+            continue;
+        ++nused;
+        const float fast = hough::quot_apply(a, b, hough::quot_recip(b));
+        const float ref = a / b;
+        if (__float_as_uint(fast) != __float_as_uint(ref))
+            ++nbad;
+    }
+    if (nbad)
+        atomicAdd(bad, nbad);
+    if (nused)
+        atomicAdd(used, nused);
+}
+
+}  // namespace
+
+extern "C" hough_status hough_selftest_divide(int64_t n, uint64_t seed, uint64_t *mismatches, uint64_t *checked) {
+    if (n < 0 || !mismatches)
+        return HOUGH_EINVAL;
+    unsigned long long *d = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&d), 2 * sizeof(unsigned long long)) != hipSuccess)
+        return HOUGH_ENOMEM;
+    hough_status st = HOUGH_OK;
+    unsigned long long h[2] = {0, 0};
+    if (hipMemset(d, 0, 2 * sizeof(unsigned long long)) != hipSuccess)
+        st = HOUGH_EDEVICE;
+    if (st == HOUGH_OK) {
+        hipLaunchKernelGGL(divide_check_kernel, dim3(4096), dim3(256), 0, 0, n, seed, d, d + 1);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+            st = HOUGH_EDEVICE;
+    }
+    (void)hipFree(d);
+    *mismatches = h[0];
+    if (checked)
+        *checked = h[1];
+    return st;
+}

@@ -4,29 +4,34 @@
 // vote to each hypothesis it lies on; Section 4: the work for each hit is
 // independent of the others.
 //
-// Layout.  The accumulator of one d0 slice is cut into tiles of 64 (or 128)
+// Layout.  The accumulator of one d0 slice is cut into tiles of 32, 64 or 128
 // consecutive phi0 rows.  A workgroup owns one tile as a private LDS
-// accumulator; each lane owns one phi0 row (two for 128-row tiles) and keeps
-// that row's cos/sin and the slice's d0 in registers; each wavefront takes
-// one hit at a time (hit data are wave-uniform), so a wavefront evaluates 64
-// rows of a hit per instruction.  The finished tile is flushed to HBM with
-// coalesced stores -- no global atomics on the accumulator -- and the vote
-// count is reduced per wavefront and added once per workgroup.
+// accumulator.  Each lane owns one phi0 row (two for 128-row tiles) and keeps
+// that row's cos/sin and the slice's d0 in registers; a wavefront evaluates
+// 64 rows of one hit, or 32 rows of two hits, per instruction.  The finished
+// tile is flushed to HBM with coalesced stores -- no global atomics on the
+// accumulator -- and the vote count is reduced per wavefront and added once
+// per workgroup.
+//
+// Hits stream through LDS in blocks: each thread loads its share of the next
+// block while the current one is evaluated, and only the hits that may vote
+// in the tile are packed, with r2 and (2D) their refined reciprocal, for
+// wave-uniform LDS reads.
 //
 // Culling.  A hit can only vote in the phi0 rows where its curvature lies in
-// the kappa range, which is two arcs of phi0 per d0 slice.  hit_prep_kernel
-// computes, per hit and d0 slice, a conservative bit mask of the tiles those
-// arcs touch (widened by bounds on every fp32 rounding of the vote
-// arithmetic, see below); the vote loop skips a hit for a tile whose bit is
-// clear.  Which votes are cast is still decided only by the exact fp32 test,
-// so culling changes no result.
+// the kappa range: two arcs of phi0 per d0 slice.  hit_prep_kernel computes
+// both arcs per hit and slice, widened by bounds on every fp32 rounding of the
+// vote arithmetic (see below); a hit is staged for a tile only if an arc meets
+// the tile's rows.  Which votes are cast is still decided only by the exact
+// fp32 test, so culling changes no result.
 //
 // Arithmetic is the fp32 definition in hough.h, op for op; this file is
-// compiled with -ffp-contract=off and the default correctly rounded divide.
-// r2 = x*x + y*y is computed with the same operations when a hit is staged.  For the 2D grid (d0 == +0) the numerator 2*(u - 0) equals 2*u
-// and the denominator (r2 - 0*u) + 0*0 equals r2 for every finite u, and both
-// forms give NaN or an out-of-range kf otherwise, so the 2D kernels use
-// 2*u / r2.
+// compiled with -ffp-contract=off.  r2 = x*x + y*y is computed with the same
+// operations when a hit is staged.  For the 2D grid (d0 == +0) the numerator
+// 2*(u - 0) equals 2*u and the denominator (r2 - 0*u) + 0*0 equals r2 for every
+// finite u, and both forms give NaN or an out-of-range kf otherwise, so the 2D
+// kernels use 2*u / r2, with the division's reciprocal refinement done once
+// per hit (vote_math.h).
 //
 // uint16 accumulators are packed two cells per dword in LDS (even kappa bin in
 // the low half): a vote adds 1 or 0x10000 with one 32-bit LDS atomic.  The low
@@ -41,6 +46,7 @@
 
 #include "hough_impl.h"
 #include "peak_tile.h"
+#include "vote_math.h"
 
 namespace hough {
 namespace {
@@ -49,9 +55,10 @@ struct VoteArgs {
     GridArgs g;
     const float *x;
     const float *y;
-    const uint32_t *mask;       // [n_d0][mask_stride] tile masks; or one all-ones word (step 0)
-    int64_t mask_stride;
-    int32_t mask_step;          // 1 with masks, 0 without
+    const uint2 *arcs;          // [n_d0][arc_stride] phi0 arcs per hit; or one full-circle entry (step 0)
+    int64_t arc_stride;
+    int32_t arc_step;           // 1 with arcs, 0 without
+    int32_t div_fast;           // 2D: hoisted-reciprocal division allowed (bin-centre phi0 table)
     int32_t n_hits;             // single event
     int32_t split;              // single event: hit chunks per tile
     int32_t tiles_per_slice;
@@ -68,11 +75,11 @@ struct VoteArgs {
     int32_t threshold;          // fused
 };
 
-constexpr int kHitBlock = 1024;   // hits staged in LDS per round
+constexpr int kHitBlock = 512;   // hits staged in LDS per round
 
 template <int NT>
 struct TileScratch {
-    float4 hits[kHitBlock];         // kept hits of the current block: x, y, r2
+    float4 hits[kHitBlock];          // kept hits of the current block: x, y, r2, 1/r2 (2D)
     CompactScratch<NT> sc;
     unsigned long long red[NT / 64];
     int32_t n_kept[2];
@@ -88,13 +95,27 @@ __device__ __forceinline__ uint32_t cell_sum(uint32_t v) {
     return U16 ? (v & 0xffffu) + (v >> 16) : v;
 }
 
+// Does the arc (start, length) of phi0 rows meet rows [a, a + rows) (all
+// modulo n, a in [0, n))?
+__device__ __forceinline__ bool arc_meets(uint32_t arc, int a, int rows, int n) {
+    const int start = static_cast<int>(arc & 0xffffu);
+    const int len = static_cast<int>(arc >> 16);
+    int da = a - start;
+    da += da < 0 ? n : 0;
+    int ds = start - a;
+    ds += ds < 0 ? n : 0;
+    return len > 0 && (da < len || ds < rows);
+}
+
 // Vote hits [h_begin, h_end) of event e into tile t of d0 slice l, then either
 // flush it (unfused) or search its interior rows for peaks (fused).
-template <bool U16, bool D3, int RPT, int NT, bool FUSED>
+template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
 __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begin, int64_t h_end,
                           uint32_t *__restrict__ acc_event, bool atomic_flush, unsigned long long *n_votes,
                           uint32_t *lds, TileScratch<NT> &ts) {
-    constexpr int R = 64 * RPT;
+    constexpr int RL = ROWS < 64 ? ROWS : 64;   // lanes across rows
+    constexpr int HPW = 64 / RL;                // hits per wavefront instruction
+    constexpr int RPT = ROWS / RL;              // rows per lane
     constexpr int NW = NT / 64;
     const GridArgs &g = a.g;
     const int tid = threadIdx.x;
@@ -106,7 +127,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         s_here = min(a.tile_stride, n_phi - t * a.tile_stride);
         len = s_here + 2;
     } else {
-        len = min(R, n_phi - first);
+        len = min(ROWS, n_phi - first);
     }
 
     for (int i = tid; i < len * stride; i += NT)
@@ -115,16 +136,21 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         for (int i = tid; i < kDigits; i += NT)
             ts.sc.hist[i] = 0u;
     }
-    __syncthreads();
+    if (tid == 0) {
+        ts.n_kept[0] = 0;
+        ts.n_kept[1] = 0;
+    }
 
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rlane = lane % RL;
+    const int hsub = lane / RL;
     float c[RPT], s[RPT];
     int rowoff[RPT];
     bool live[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-        const int r = lane + 64 * i;
+        const int r = rlane + RL * i;
         live[i] = r < len;
         int j = first + r;
         if (j < 0)
@@ -146,51 +172,54 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const float kmin = g.kappa_min;
     const float kscale = g.kappa_scale;
     const float nkf = static_cast<float>(g.n_kappa);
+    const bool div_fast = a.div_fast != 0;
     const float *__restrict__ xs = a.x;
     const float *__restrict__ ys = a.y;
-    const uint32_t *__restrict__ mrow = a.mask + static_cast<int64_t>(l) * a.mask_stride;
-    const int64_t mstep = a.mask_step;
-    const uint32_t tbit = 1u << (t & 31);
+    const uint2 *__restrict__ arow = a.arcs + static_cast<int64_t>(l) * a.arc_stride;
+    const int64_t astep = a.arc_step;
+    const int tile_first = first < 0 ? first + n_phi : first;   // rows [tile_first, +len) mod n_phi
 
-    // One evaluation: hit (xh, yh, r2) at this lane's row i.
-    auto eval = [&](float xh, float yh, float r2) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const float u = yh * c[i] - xh * s[i];
-            float kappa;
-            if constexpr (D3) {
-                const float num = 2.0f * (u - d);
-                const float den = (r2 - d2 * u) + dd;
-                kappa = num / den;
+    // Kappa bin of one hit at row i of this lane; *ok tells whether it votes.
+    auto bin = [&](const float4 &h, int i, bool *ok) -> int {
+        const float u = h.y * c[i] - h.x * s[i];
+        float kappa;
+        if constexpr (D3) {
+            const float num = 2.0f * (u - d);
+            const float den = (h.z - d2 * u) + dd;
+            kappa = num / den;
+        } else {
+            float num = 2.0f * u;
+            if (h.w != 0.0f) {
+                kappa = quot_apply(num, h.z, h.w);
             } else {
-                kappa = (2.0f * u) / r2;
-            }
-            const float kf = (kappa - kmin) * kscale;
-            if (live[i] && kf >= 0.0f && kf < nkf) {
-                const int k = static_cast<int>(kf);
-                if constexpr (U16)
-                    lds_add(&lds[rowoff[i] + (k >> 1)], (k & 1) ? 0x10000u : 1u);
-                else
-                    lds_add(&lds[rowoff[i] + k], 1u);
+                // Rare: keep the operator's division out of the common path.
+                asm volatile("" : "+v"(num));
+                kappa = num / h.z;
             }
         }
+        const float kf = (kappa - kmin) * kscale;
+        *ok = live[i] && kf >= 0.0f && kf < nkf;
+        return static_cast<int>(kf);
+    };
+    auto vote = [&](int k, int i) {
+        if constexpr (U16)
+            lds_add(&lds[rowoff[i] + (k >> 1)], (k & 1) ? 0x10000u : 1u);
+        else
+            lds_add(&lds[rowoff[i] + k], 1u);
     };
 
-    // Hits stream through LDS in blocks of kHitBlock: every thread loads
-    // kHitBlock/NT hits (the loads for the next block are in flight while the
-    // current one is evaluated), keeps those whose tile bit is set, and the
-    // kept hits are packed as (x, y, r2) for wave-uniform LDS reads.
-    constexpr int PER = kHitBlock / NT;
+    // Hit blocks: every thread loads kHitBlock/NT hits of the next block
+    // (loads issued unconditionally, index clamped) while the current block is
+    // evaluated; whether a hit is kept is decided when it is staged.
+    constexpr int PER = kHitBlock / NT > 0 ? kHitBlock / NT : 1;
+    constexpr int STAGERS = kHitBlock / PER;    // threads that stage
     float px[PER], py[PER];
-    uint32_t pm[PER];
-    // All loads of a block are issued back to back and unconditionally (the
-    // index is clamped), so they stay in flight during the previous block's
-    // evaluation; whether a hit is kept is decided when it is staged.
+    uint2 pa[PER];
     auto fetch = [&](int64_t b0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int64_t h = min(b0 + q * NT + tid, h_end - 1);
-            pm[q] = mrow[h * mstep];
+            const int64_t h = min(b0 + q * STAGERS + tid, h_end - 1);
+            pa[q] = arow[h * astep];
             px[q] = xs[h];
             py[q] = ys[h];
         }
@@ -198,39 +227,53 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     if (h_begin < h_end)
         fetch(h_begin);
     int parity = 0;
-    if (tid == 0) {
-        ts.n_kept[0] = 0;
-        ts.n_kept[1] = 0;
-    }
     for (int64_t b0 = h_begin; b0 < h_end; b0 += kHitBlock, parity ^= 1) {
         __syncthreads();                         // the previous block is fully evaluated
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const bool keep = b0 + q * NT + tid < h_end && (pm[q] & tbit);
+            const bool mine = tid < STAGERS;
+            const bool keep = mine && b0 + q * STAGERS + tid < h_end &&
+                              (arc_meets(pa[q].x, tile_first, len, n_phi) ||
+                               arc_meets(pa[q].y, tile_first, len, n_phi));
             const uint64_t m = __ballot(keep);
             int base = 0;
             if (lane == 0 && m)
                 base = atomicAdd(&ts.n_kept[parity], __popcll(m));
             base = __shfl(base, 0, 64);
-            if (keep)
-                ts.hits[base + rank_below(m)] = make_float4(px[q], py[q], px[q] * px[q] + py[q] * py[q], 0.0f);
+            if (keep) {
+                const float r2 = px[q] * px[q] + py[q] * py[q];
+                float rec = 0.0f;
+                if constexpr (!D3)
+                    rec = (div_fast && quot_den_ok(r2)) ? quot_recip(r2) : 0.0f;
+                ts.hits[base + rank_below(m)] = make_float4(px[q], py[q], r2, rec);
+            }
         }
         __syncthreads();
         const int n = ts.n_kept[parity];
         if (tid == 0)
-            ts.n_kept[parity ^ 1] = 0;           // free since every thread passed the last barrier
+            ts.n_kept[parity ^ 1] = 0;           // free: every thread passed the last barrier
         if (b0 + kHitBlock < h_end)
             fetch(b0 + kHitBlock);
-        int i = wave;
-        for (; i + NW < n; i += 2 * NW) {
-            const float4 h0 = ts.hits[i];
-            const float4 h1 = ts.hits[i + NW];
-            eval(h0.x, h0.y, h0.z);
-            eval(h1.x, h1.y, h1.z);
-        }
-        if (i < n) {
-            const float4 h0 = ts.hits[i];
-            eval(h0.x, h0.y, h0.z);
+        // Two groups of HPW hits per iteration: all bins first, then the votes.
+        for (int i0 = wave * HPW; i0 < n; i0 += 2 * NW * HPW) {
+            const int ia = i0 + hsub;
+            const int ib = i0 + NW * HPW + hsub;
+            const float4 ha = ts.hits[ia < n ? ia : 0];
+            const float4 hb = ts.hits[ib < n ? ib : 0];
+            int ka[RPT], kb[RPT];
+            bool oa[RPT], ob[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                ka[i] = bin(ha, i, &oa[i]);
+                kb[i] = bin(hb, i, &ob[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                if (ia < n && oa[i])
+                    vote(ka[i], i);
+                if (ib < n && ob[i])
+                    vote(kb[i], i);
+            }
         }
     }
     __syncthreads();
@@ -296,7 +339,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     __syncthreads();   // the LDS tile and scratch are reused by the next item
 }
 
-template <bool U16, bool D3, int RPT, int NT, bool FUSED>
+template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
 __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ TileScratch<NT> ts;
@@ -310,7 +353,7 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
         const int64_t per = (n + a.split - 1) / a.split;
         const int64_t hb = static_cast<int64_t>(blockIdx.y) * per;
         const int64_t he = min(n, hb + per);
-        vote_tile<U16, D3, RPT, NT, FUSED>(a, 0, l, t, hb, he, a.acc, a.split > 1, a.n_votes, lds, ts);
+        vote_tile<U16, D3, ROWS, NT, FUSED>(a, 0, l, t, hb, he, a.acc, a.split > 1, a.n_votes, lds, ts);
         return;
     }
     const int32_t n_items = *a.n_items;
@@ -330,32 +373,35 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
         const int l = wi.tile / T;
         const int t = wi.tile - l * T;
         uint32_t *acc_e = a.acc ? a.acc + static_cast<int64_t>(wi.event) * a.g.acc_dwords : nullptr;
-        vote_tile<U16, D3, RPT, NT, FUSED>(a, wi.event, l, t, ev.hit_begin, ev.hit_end, acc_e, false,
-                                           a.n_votes ? a.n_votes + wi.event : nullptr, lds, ts);
+        vote_tile<U16, D3, ROWS, NT, FUSED>(a, wi.event, l, t, ev.hit_begin, ev.hit_end, acc_e, false,
+                                            a.n_votes ? a.n_votes + wi.event : nullptr, lds, ts);
         if (!a.work_counter)
             return;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Per-hit preparation: r2 and conservative tile masks.
+// Per-hit preparation: the two phi0 arcs per d0 slice where a hit may vote.
 //
-// Bound used for the masks (all angles in radians, K = max |kappa edge|).
-// If a vote is cast, the fp32 curvature kappa_c lies within K(1 + 2^-19).
-// kappa_c rounds num_c / den_c, where num_c = 2(u_c - d) to 2^-24 relative,
-// u_c = y c - x s to r 2^-20 absolute (fp32 products, and fp32 cos/sin of the
-// bin centre), and den_c equals r^2 - 2 d u_c + d^2 to 2^-21 (r + |d|)^2
-// absolute.  When |r - |d|| >= 0.1 (r + |d|) the exact denominator is at least
-// (r - |d|)^2, so kappa(u_c) = 2(u_c - d)/(r^2 + d^2 - 2 d u_c) is within
-// relative 5e-5 of kappa_c and |kappa(u_c)| <= K' = K (1 + 1e-3).  kappa(u) is
-// monotone in u, so u_c lies between u(-K') and u(K') with
-// u(k) = (k (r^2 + d^2) + 2 d) / (2 (1 + k d)), and r sin(phi_h - phi0) lies
-// in that interval widened by r 1e-5.  The two phi0 arcs that satisfy this,
-// widened by 1e-5 rad and one row on each side, give the rows (and tiles)
-// that can receive the hit's votes.  Hits that are not finite, sit within
-// 1e-15 of the origin or beyond 1e15, or fail the conditioning test keep
-// every tile.  The phi0 table must hold the bin centres (j + 1/2) 2 pi / n_phi
-// (checked when the context is created; otherwise culling stays off).
+// Bound used (angles in radians, K = max |kappa edge|).  If a vote is cast,
+// the fp32 curvature kappa_c lies within K(1 + 2^-19).  kappa_c rounds
+// num_c / den_c, where num_c = 2(u_c - d) to 2^-24 relative, u_c = y c - x s to
+// r 2^-20 absolute (fp32 products, and fp32 cos/sin of the bin centre), and
+// den_c equals r^2 - 2 d u_c + d^2 to 2^-21 (r + |d|)^2 absolute.  When
+// |r - |d|| >= 0.1 (r + |d|) the exact denominator is at least (r - |d|)^2, so
+// kappa(u_c) = 2(u_c - d)/(r^2 + d^2 - 2 d u_c) is within relative 5e-5 of
+// kappa_c and |kappa(u_c)| <= K' = K (1 + 1e-3).  kappa(u) is monotone in u, so
+// u_c lies between u(-K') and u(K') with u(k) = (k (r^2 + d^2) + 2 d) /
+// (2 (1 + k d)), and r sin(phi_h - phi0) lies in that interval widened by
+// r 1e-5.  The two phi0 arcs that satisfy this, widened by 1e-5 rad and one
+// row on each side, hold every row that can receive the hit's votes.  Hits
+// that are not finite, sit within 1e-15 of the origin or beyond 1e15, or fail
+// the conditioning test get the full circle.  The phi0 table must hold the bin
+// centres (j + 1/2) 2 pi / n_phi (checked when the context is created;
+// otherwise no arcs are used).
+//
+// An arc is packed as start | length << 16 in rows (length 0: empty; length
+// n_phi: the full circle), so n_phi is limited to 32768.
 // ---------------------------------------------------------------------------
 
 struct PrepArgs {
@@ -363,64 +409,27 @@ struct PrepArgs {
     const float *y;
     int64_t n_hits;
     const int64_t *n_hits_dev;  // batch: live hit count (overrides n_hits), or nullptr
-    uint32_t *mask;
-    int64_t mask_stride;
+    uint2 *arcs;
+    int64_t arc_stride;
     const float *d0;            // nullptr for 2D
     int32_t n_phi;
     double kabs;
-    int32_t tiles;
-    int32_t tile_stride;
-    int32_t tile_off;
-    int32_t tile_rows;          // rows a tile votes, halo included
 };
 
-__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
-    const int64_t q = a / b;
-    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
-}
-
-__device__ __forceinline__ uint32_t bit_range(int64_t lo, int64_t hi) {
-    const int64_t n = hi - lo + 1;
-    const uint32_t ones = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
-    return ones << lo;
-}
-
-// Tiles whose rows meet the unwrapped row range [jlo, jhi].
-__device__ uint32_t tiles_meeting(const PrepArgs &p, int64_t jlo, int64_t jhi, uint32_t all) {
-    const int64_t n = p.n_phi;
-    if (jhi < jlo)
-        return 0u;
-    if (jhi - jlo + 1 >= n)
-        return all;
-    const int64_t sh = floor_div(jlo, n) * n;
-    jlo -= sh;
-    jhi -= sh;
-    const int64_t pieces[2][2] = {{jlo, jhi < n ? jhi : n - 1}, {0, jhi - n}};
-    const int n_pieces = jhi >= n ? 2 : 1;
-    uint32_t m = 0u;
-    for (int q = 0; q < n_pieces; ++q) {
-        for (int img = -1; img <= 1; ++img) {
-            const int64_t lo = pieces[q][0] - img * n - p.tile_off;
-            const int64_t hi = pieces[q][1] - img * n - p.tile_off;
-            int64_t tlo = -floor_div(-(lo - p.tile_rows + 1), p.tile_stride);   // ceil
-            int64_t thi = floor_div(hi, p.tile_stride);
-            if (tlo < 0)
-                tlo = 0;
-            if (thi > p.tiles - 1)
-                thi = p.tiles - 1;
-            if (tlo <= thi)
-                m |= bit_range(tlo, thi);
-        }
-    }
-    return m & all;
-}
-
-__device__ uint32_t arc_tiles(const PrepArgs &p, double phi_a, double phi_b, uint32_t all) {
-    const double dphi = 6.283185307179586 / p.n_phi;
+__device__ __forceinline__ uint32_t pack_arc(double phi_a, double phi_b, int n) {
+    const double dphi = 6.283185307179586 / n;
     const double tol = 1e-5;
-    const int64_t jlo = static_cast<int64_t>(ceil((phi_a - tol) / dphi - 0.5)) - 1;
-    const int64_t jhi = static_cast<int64_t>(floor((phi_b + tol) / dphi - 0.5)) + 1;
-    return tiles_meeting(p, jlo, jhi, all);
+    const double lo = ceil((phi_a - tol) / dphi - 0.5) - 1.0;
+    const double hi = floor((phi_b + tol) / dphi - 0.5) + 1.0;
+    if (hi < lo)
+        return 0u;
+    const double rows = hi - lo + 1.0;
+    if (rows >= n)
+        return static_cast<uint32_t>(n) << 16;
+    double start = fmod(lo, static_cast<double>(n));
+    if (start < 0)
+        start += n;
+    return static_cast<uint32_t>(start) | (static_cast<uint32_t>(rows) << 16);
 }
 
 __global__ void hit_prep_kernel(PrepArgs p) {
@@ -429,11 +438,10 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     const int64_t n = p.n_hits_dev ? *p.n_hits_dev : p.n_hits;
     if (i >= n)
         return;
-    const float x = p.x[i];
-    const float y = p.y[i];
-    const uint32_t all = p.tiles >= 32 ? 0xffffffffu : ((1u << p.tiles) - 1u);
-    uint32_t m = all;
-    const double X = x, Y = y;
+    const double X = p.x[i];
+    const double Y = p.y[i];
+    const uint32_t full = static_cast<uint32_t>(p.n_phi) << 16;
+    uint2 out = make_uint2(full, 0u);
     const double r = sqrt(X * X + Y * Y);
     const double d = p.d0 ? static_cast<double>(p.d0[l]) : 0.0;
     const double ad = fabs(d);
@@ -446,16 +454,16 @@ __global__ void hit_prep_kernel(PrepArgs p) {
         const double slo = (fmin(u1, u2) - r * 1e-5) / r;
         const double shi = (fmax(u1, u2) + r * 1e-5) / r;
         if (slo > 1.0 || shi < -1.0) {
-            m = 0u;
+            out = make_uint2(0u, 0u);
         } else if (!(slo <= -1.0 && shi >= 1.0)) {
             const double alo = asin(fmax(slo, -1.0));
             const double ahi = asin(fmin(shi, 1.0));
             const double ph = atan2(Y, X);
             const double pi = 3.141592653589793;
-            m = arc_tiles(p, ph - ahi, ph - alo, all) | arc_tiles(p, ph - pi + alo, ph - pi + ahi, all);
+            out = make_uint2(pack_arc(ph - ahi, ph - alo, p.n_phi), pack_arc(ph - pi + alo, ph - pi + ahi, p.n_phi));
         }
     }
-    p.mask[static_cast<int64_t>(l) * p.mask_stride + i] = m;
+    p.arcs[static_cast<int64_t>(l) * p.arc_stride + i] = out;
 }
 
 __global__ void prep_kernel(EventState *state, int32_t n_events, unsigned long long *n_votes) {
@@ -499,12 +507,15 @@ template <bool U16, bool D3, bool FUSED>
 VoteFn pick_shape(int rows, int threads) {
     const int key = rows * 10000 + threads;
     switch (key) {
-        case 64 * 10000 + 256: return vote_kernel<U16, D3, 1, 256, FUSED>;
-        case 64 * 10000 + 512: return vote_kernel<U16, D3, 1, 512, FUSED>;
-        case 64 * 10000 + 1024: return vote_kernel<U16, D3, 1, 1024, FUSED>;
-        case 128 * 10000 + 256: return vote_kernel<U16, D3, 2, 256, FUSED>;
-        case 128 * 10000 + 512: return vote_kernel<U16, D3, 2, 512, FUSED>;
-        case 128 * 10000 + 1024: return vote_kernel<U16, D3, 2, 1024, FUSED>;
+        case 32 * 10000 + 256: return vote_kernel<U16, D3, 32, 256, FUSED>;
+        case 32 * 10000 + 512: return vote_kernel<U16, D3, 32, 512, FUSED>;
+        case 32 * 10000 + 1024: return vote_kernel<U16, D3, 32, 1024, FUSED>;
+        case 64 * 10000 + 256: return vote_kernel<U16, D3, 64, 256, FUSED>;
+        case 64 * 10000 + 512: return vote_kernel<U16, D3, 64, 512, FUSED>;
+        case 64 * 10000 + 1024: return vote_kernel<U16, D3, 64, 1024, FUSED>;
+        case 128 * 10000 + 256: return vote_kernel<U16, D3, 128, 256, FUSED>;
+        case 128 * 10000 + 512: return vote_kernel<U16, D3, 128, 512, FUSED>;
+        case 128 * 10000 + 1024: return vote_kernel<U16, D3, 128, 1024, FUSED>;
         default: return nullptr;
     }
 }
@@ -543,6 +554,15 @@ void tile_geometry(const GridArgs &g, const VoteShape &s, bool fused, int32_t *t
     *tiles = (g.n_phi + *stride - 1) / *stride;
 }
 
+void fill_inputs(VoteArgs &a, const VoteInputs &in) {
+    a.x = in.x;
+    a.y = in.y;
+    a.arcs = in.arcs;
+    a.arc_stride = in.arc_stride;
+    a.arc_step = in.arc_step;
+    a.div_fast = in.div_fast;
+}
+
 }  // namespace
 
 size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords) {
@@ -570,9 +590,8 @@ int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s) {
     return ((S + 1) / 2) * ((g.n_kappa + 1) / 2);
 }
 
-hipError_t launch_hit_prep(const GridArgs &g, const VoteShape &s, bool fused, const float *x, const float *y,
-                           int64_t n_hits, const int64_t *n_hits_dev, uint32_t *mask, int64_t mask_stride,
-                           hipStream_t stream) {
+hipError_t launch_hit_prep(const GridArgs &g, const float *x, const float *y, int64_t n_hits,
+                           const int64_t *n_hits_dev, uint2 *arcs, int64_t arc_stride, hipStream_t stream) {
     if (n_hits <= 0)
         return hipSuccess;
     PrepArgs p{};
@@ -580,15 +599,13 @@ hipError_t launch_hit_prep(const GridArgs &g, const VoteShape &s, bool fused, co
     p.y = y;
     p.n_hits = n_hits;
     p.n_hits_dev = n_hits_dev;
-    p.mask = mask;
-    p.mask_stride = mask_stride;
+    p.arcs = arcs;
+    p.arc_stride = arc_stride;
     p.d0 = g.d0;
     p.n_phi = g.n_phi;
     const double kmin = g.kappa_min;
     const double kmax = static_cast<double>(g.kappa_min) + static_cast<double>(g.n_kappa) / g.kappa_scale;
     p.kabs = fmax(fabs(kmin), fabs(kmax));
-    tile_geometry(g, s, fused, &p.tiles, &p.tile_stride, &p.tile_off);
-    p.tile_rows = fused ? p.tile_stride + 2 : s.rows;
     const unsigned blocks = static_cast<unsigned>((n_hits + 255) / 256);
     hipLaunchKernelGGL(hit_prep_kernel, dim3(blocks, g.n_d0), dim3(256), 0, stream, p);
     return hipGetLastError();
@@ -623,11 +640,7 @@ hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, c
                               int32_t n_hits, uint32_t *acc, unsigned long long *n_votes, hipStream_t stream) {
     VoteArgs a{};
     a.g = g;
-    a.x = in.x;
-    a.y = in.y;
-    a.mask = in.mask;
-    a.mask_stride = in.mask_stride;
-    a.mask_step = in.mask_step;
+    fill_inputs(a, in);
     a.n_hits = n_hits;
     a.split = s.split;
     tile_geometry(g, s, false, &a.tiles_per_slice, &a.tile_stride, &a.tile_off);
@@ -650,11 +663,7 @@ hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const Vote
                              hipStream_t stream) {
     VoteArgs a{};
     a.g = g;
-    a.x = in.x;
-    a.y = in.y;
-    a.mask = in.mask;
-    a.mask_stride = in.mask_stride;
-    a.mask_step = in.mask_step;
+    fill_inputs(a, in);
     a.split = 1;
     tile_geometry(g, s, fused, &a.tiles_per_slice, &a.tile_stride, &a.tile_off);
     a.lds_stride = g.row_dwords + s.pad;

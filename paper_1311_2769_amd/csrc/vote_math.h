@@ -1,0 +1,61 @@
+// fp32 quotient of the vote with the reciprocal refinement hoisted out of the
+// row loop.
+//
+// The correctly rounded fp32 division used for the curvature (the compiler's
+// default for a / b on gfx950) is Markstein's method: a reciprocal estimate
+// y0 = rcp(b) is refined once with FMA (e = 1 - b y0, y = y0 + e y0), and the
+// quotient is refined twice from exact FMA remainders (q0 = a y,
+// r0 = a - b q0, q1 = q0 + r0 y, r1 = a - b q1, q = q1 + r1 y).  Operand
+// scaling (div_scale / div_fmas) and special-value handling (div_fixup) are
+// no-ops when both operands and the quotient are normal and far from the
+// overflow and underflow thresholds.  Inside that range the sequence below
+// performs the same operations, so its result is bit-identical to a / b;
+// outside it the caller divides with the operator.
+//
+// In 2D the denominator r2 is the same for all phi0 rows of a hit, so y is
+// computed once per hit and each evaluation costs five FMA-pipe operations
+// instead of eleven.
+//
+// Range of the 2D numerator.  With a phi0 table of bin centres
+// (|cos|, |sin| <= 1 + 1e-6, and neither closer to 0 than sin(pi / n_phi),
+// n_phi <= 32768) and r2 = x*x + y*y in [2^-30, 2^30]: |2u| <= 2^17, and a
+// nonzero u = RN(RN(y c) - RN(x s)) is at least 2^-25 max(|y c|, |x s|) >=
+// 2^-54 in magnitude, so every nonzero numerator is in the range below.  A
+// zero numerator may come out as +0 instead of -0, which moves no vote:
+// (+-0 - kappa_min) is the same number, or +-0 when kappa_min is 0, and both
+// zeros pass the range test into bin 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hough {
+
+// Denominators in [2^-30, 2^30] and numerators of magnitude in [2^-60, 2^30]
+// keep every operand, remainder and quotient of the sequence normal.  (Zero
+// numerators take the operator too: the FMA sequence could return +0 for -0.)
+__device__ __forceinline__ bool quot_den_ok(float b) {
+    return b >= 0x1.0p-30f && b <= 0x1.0p30f;
+}
+
+__device__ __forceinline__ bool quot_num_ok(float a) {
+    const float m = fabsf(a);
+    return m >= 0x1.0p-60f && m <= 0x1.0p30f;
+}
+
+// Refined reciprocal of b (the hoistable part).
+__device__ __forceinline__ float quot_recip(float b) {
+    const float y0 = __builtin_amdgcn_rcpf(b);
+    const float e = __builtin_fmaf(-b, y0, 1.0f);
+    return __builtin_fmaf(e, y0, y0);
+}
+
+// a / b given y = quot_recip(b), valid when quot_den_ok(b) && quot_num_ok(a).
+__device__ __forceinline__ float quot_apply(float a, float b, float y) {
+    const float q0 = a * y;
+    const float r0 = __builtin_fmaf(-b, q0, a);
+    const float q1 = __builtin_fmaf(r0, y, q0);
+    const float r1 = __builtin_fmaf(-b, q1, a);
+    return __builtin_fmaf(r1, y, q1);
+}
+
+}  // namespace hough

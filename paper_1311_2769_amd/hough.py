@@ -26,7 +26,7 @@ SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
     "hough_vote_batch",
     "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
-    "hough_status_str", "hough_last_error", "hough_version",
+    "hough_selftest_divide", "hough_status_str", "hough_last_error", "hough_version",
 )
 
 
@@ -86,6 +86,9 @@ def load(path: str = LIB_PATH):
     lib.hough_set_timing.argtypes = [vp, i32]
     lib.hough_get_timing.restype = i32
     lib.hough_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+    lib.hough_selftest_divide.restype = i32
+    lib.hough_selftest_divide.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                                          ctypes.POINTER(ctypes.c_uint64)]
     lib.hough_status_str.restype = ctypes.c_char_p
     lib.hough_status_str.argtypes = [i32]
     lib.hough_last_error.restype = ctypes.c_char_p
@@ -267,6 +270,15 @@ class HoughContext:
         _check(self.lib.hough_get_launch(self.handle, which, *[ctypes.byref(v) for v in vals]),
                "hough_get_launch")
         return tuple(v.value for v in vals)
+
+
+def selftest_divide(n: int, seed: int = 1):
+    """(mismatches, checked) of the device division self-test."""
+    lib = load()
+    bad, used = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib.hough_selftest_divide(int(n), int(seed), ctypes.byref(bad), ctypes.byref(used)),
+           "hough_selftest_divide")
+    return bad.value, used.value
 
 
 def acc_to_numpy(acc, spec: GridSpec):

@@ -433,3 +433,14 @@ def test_timing_mode_gives_the_same_results():
     for e in range(5):
         assert timed[e][:2] == base[e][:2]
         np.testing.assert_array_equal(timed[e][3], base[e][3])
+
+
+def test_division_fast_path_equals_the_operator():
+    """The hoisted-reciprocal quotient equals fp32 division bit for bit (device self-test)."""
+    _dev()
+    total = 0
+    for seed in (1, 2, 3):
+        bad, used = hough.selftest_divide(100_000_000, seed)
+        assert bad == 0, f"{bad} mismatches of {used}"
+        total += used
+    assert total > 100_000_000
