@@ -153,12 +153,13 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
 /* Launch-shape controls (used by the autotuner and tests; results never
  * depend on them).  which: 0 = single-event vote, 1 = batched vote.
  * rows: phi0 rows per workgroup tile; threads: workgroup size (256/512/1024);
- * split: hit chunks per tile for the single-event vote (>= 1); pad: extra
- * dwords per LDS row (0 or 1).  Invalid combinations return EINVAL. */
+ * split: hit chunks per tile for the single-event vote (>= 1; 1 for the
+ * batch).  Invalid combinations (a shape whose tile does not fit in LDS, a
+ * batch work list longer than the context holds) return EINVAL. */
 hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32_t threads,
-                              int32_t split, int32_t pad);
+                              int32_t split);
 hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows, int32_t *threads,
-                              int32_t *split, int32_t *pad);
+                              int32_t *split);
 
 /* Timing mode (for benchmarks and profiling; results are unchanged).  When
  * enabled, hough_event_batch enqueues its kernels directly on the stream

@@ -404,12 +404,12 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     hipDeviceProp_t prop{};
     (void)hipGetDeviceProperties(&prop, c->device);
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    c->shape_single = VoteShape{64, 512, u16 ? 1 : 4, 0};
-    c->shape_batch = VoteShape{64, 512, 1, 0};
+    c->shape_single = VoteShape{32, 512, u16 ? 1 : 4};
+    c->shape_batch = VoteShape{32, 512, 1};
     if (!vote_shape_supported(c->shape_single, u16, g.row_dwords) ||
         !vote_shape_supported(c->shape_batch, u16, g.row_dwords)) {
         delete c;
-        return HOUGH_EINVAL;   // a kappa row too long for a 64-row LDS tile
+        return HOUGH_EINVAL;   // a kappa row too long for a 32-row LDS tile
     }
     c->persistent_groups = cus * 2;
     c->cull_ok = grid->n_phi <= 32768 && table_is_bin_centres(grid);
@@ -422,7 +422,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     int32_t max_blocks = pb;
     if (c->fused_batch) {
         for (int32_t rows : kBatchRows) {
-            VoteShape s{rows, 256, 1, 0};
+            VoteShape s{rows, 256, 1};
             const int32_t tiles = vote_tiles_per_slice(g, s, true);
             bound = std::max<int64_t>(bound, static_cast<int64_t>(tiles) * fused_chunk_cap(g, s));
             first_chunks = std::max(first_chunks, tiles);
@@ -436,7 +436,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     const size_t E = static_cast<size_t>(c->max_events);
     int32_t max_tpe = 0;
     for (int32_t rows : kBatchRows)
-        max_tpe = std::max(max_tpe, g.n_d0 * vote_tiles_per_slice(g, VoteShape{rows, 256, 1, 0}, c->fused_batch));
+        max_tpe = std::max(max_tpe, g.n_d0 * vote_tiles_per_slice(g, VoteShape{rows, 256, 1}, c->fused_batch));
     c->max_items = static_cast<int32_t>(E) * max_tpe;
     c->desc_bytes = sizeof(BatchHeader) + E * sizeof(EventDesc) + static_cast<size_t>(c->max_items) * sizeof(WorkItem);
 
@@ -484,11 +484,10 @@ void hough_ctx_destroy(hough_ctx *ctx) {
     free_ctx(ctx);
 }
 
-hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32_t threads, int32_t split,
-                              int32_t pad) {
+hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32_t threads, int32_t split) {
     if (!ctx || (which != 0 && which != 1))
         return HOUGH_EINVAL;
-    VoteShape s{rows, threads, split, pad};
+    VoteShape s{rows, threads, split};
     if (which == 1 && split != 1)
         return HOUGH_EINVAL;
     if (!vote_shape_supported(s, ctx->u16, ctx->g.row_dwords))
@@ -530,7 +529,7 @@ hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms) {
 }
 
 hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows, int32_t *threads,
-                              int32_t *split, int32_t *pad) {
+                              int32_t *split) {
     if (!ctx || (which != 0 && which != 1))
         return HOUGH_EINVAL;
     const VoteShape &s = which == 0 ? ctx->shape_single : ctx->shape_batch;
@@ -540,8 +539,6 @@ hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows
         *threads = s.threads;
     if (split)
         *split = s.split;
-    if (pad)
-        *pad = s.pad;
     return HOUGH_OK;
 }
 

@@ -109,7 +109,6 @@ struct VoteShape {
     int32_t rows;     // phi0 rows per tile
     int32_t threads;  // workgroup size
     int32_t split;    // hit chunks per tile (single-event vote only)
-    int32_t pad;      // extra dwords per LDS row
 };
 
 // ---------------------------------------------------------------------------

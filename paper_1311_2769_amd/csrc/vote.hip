@@ -8,15 +8,20 @@
 // consecutive phi0 rows.  A workgroup owns one tile as a private LDS
 // accumulator.  Each lane owns one phi0 row (two for 128-row tiles) and keeps
 // that row's cos/sin and the slice's d0 in registers; a wavefront evaluates
-// 64 rows of one hit, or 32 rows of two hits, per instruction.  The finished
-// tile is flushed to HBM with coalesced stores -- no global atomics on the
+// 64 rows of one hit, or 32 rows of two hits, per instruction.  The LDS tile
+// is kappa-major (dword (kappa, row) at kappa*rows + row): lanes are rows, so
+// the LDS atomics of one instruction fall in distinct banks whatever kappa
+// bins the hit produces.  Every lane adds on every evaluation: a lane whose
+// hit casts no vote in its row adds into one spare kappa column past the
+// grid, which keeps the loop free of branches and selects.  The finished tile
+// is flushed to HBM, lanes again across rows -- no global atomics on the
 // accumulator -- and the vote count is reduced per wavefront and added once
 // per workgroup.
 //
 // Hits stream through LDS in blocks: each thread loads its share of the next
 // block while the current one is evaluated, and only the hits that may vote
-// in the tile are packed, with r2 and (2D) their refined reciprocal, for
-// wave-uniform LDS reads.
+// in the tile are staged, with r2, for LDS reads that each lane group issues
+// one iteration ahead of its votes.
 //
 // Culling.  A hit can only vote in the phi0 rows where its curvature lies in
 // the kappa range: two arcs of phi0 per d0 slice.  hit_prep_kernel computes
@@ -30,8 +35,11 @@
 // operations when a hit is staged.  For the 2D grid (d0 == +0) the numerator
 // 2*(u - 0) equals 2*u and the denominator (r2 - 0*u) + 0*0 equals r2 for every
 // finite u, and both forms give NaN or an out-of-range kf otherwise, so the 2D
-// kernels use 2*u / r2, with the division's reciprocal refinement done once
-// per hit (vote_math.h).
+// kernels divide 2*u by r2.  Hits whose r2/2 lies in the range of vote_math.h
+// are staged at the front of the block as (x, y, r2/2, refined 1/(r2/2)) and
+// evaluated as u / (r2/2) with the hoisted division: the same real quotient as
+// 2u / r2, so the same correctly rounded result.  The others (and every 3D
+// hit) are staged at the back and divide with the operator.
 //
 // uint16 accumulators are packed two cells per dword in LDS (even kappa bin in
 // the low half): a vote adds 1 or 0x10000 with one 32-bit LDS atomic.  The low
@@ -43,6 +51,8 @@
 // maxima of its interior rows straight from LDS and appends them in cell
 // order to its staging list; the accumulator need not reach HBM at all.
 #pragma clang fp contract(off)
+
+#include <type_traits>
 
 #include "hough_impl.h"
 #include "peak_tile.h"
@@ -64,7 +74,6 @@ struct VoteArgs {
     int32_t tiles_per_slice;
     int32_t tile_stride;        // tile t starts at row t*tile_stride + tile_off
     int32_t tile_off;           // 0, or -1 for fused tiles
-    int32_t lds_stride;         // dwords per LDS row
     const EventDesc *desc;      // batch: per-event hit ranges
     const WorkItem *items;      // batch: tile list, or nullptr for a single event
     const int32_t *n_items;     // batch: live item count (device)
@@ -77,12 +86,19 @@ struct VoteArgs {
 
 constexpr int kHitBlock = 512;   // hits staged in LDS per round
 
+// Staged hits of a block are read up to 4 lane-group strides past the end of
+// their list (values that are never used), so the array has that much slack.
+template <int NT>
+constexpr int hit_slack() { return 4 * (NT / 64) * 2; }
+
 template <int NT>
 struct TileScratch {
-    float4 hits[kHitBlock];          // kept hits of the current block: x, y, r2, 1/r2 (2D)
+    float4 hits[kHitBlock + hit_slack<NT>()];   // kept hits of the current block
     CompactScratch<NT> sc;
+    int32_t cnt[NT];                 // fused peak search: candidates per (row, kappa segment)
+    int32_t wave_tot[NT / 64];
     unsigned long long red[NT / 64];
-    int32_t n_kept[2];
+    int32_t n_kept[2][2];            // per block parity: hits staged at the front, at the back
     int32_t next_item;
 };
 
@@ -107,6 +123,14 @@ __device__ __forceinline__ bool arc_meets(uint32_t arc, int a, int rows, int n) 
     return len > 0 && (da < len || ds < rows);
 }
 
+// Hit j of a wavefront's register batch (lane j holds it), as wave-uniform values.
+__device__ __forceinline__ float4 lane_hit(const float4 &v, int j) {
+    return make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), j)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), j)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.z), j)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.w), j)));
+}
+
 // Vote hits [h_begin, h_end) of event e into tile t of d0 slice l, then either
 // flush it (unfused) or search its interior rows for peaks (fused).
 template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
@@ -119,7 +143,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     constexpr int NW = NT / 64;
     const GridArgs &g = a.g;
     const int tid = threadIdx.x;
-    const int stride = a.lds_stride;
+    constexpr int stride = ROWS;                            // dwords per LDS kappa column
     const int n_phi = g.n_phi;
     const int first = t * a.tile_stride + a.tile_off;      // may be -1 for a fused tile
     int len, s_here = 0;
@@ -130,38 +154,38 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         len = min(ROWS, n_phi - first);
     }
 
-    for (int i = tid; i < len * stride; i += NT)
+    // row_dwords kappa columns plus one spare column that takes the no-vote adds
+    for (int i = tid; i < (g.row_dwords + 1) * stride; i += NT)
         lds[i] = 0u;
     if constexpr (FUSED) {
         for (int i = tid; i < kDigits; i += NT)
             ts.sc.hist[i] = 0u;
     }
-    if (tid == 0) {
-        ts.n_kept[0] = 0;
-        ts.n_kept[1] = 0;
-    }
+    if (tid < 4)
+        ts.n_kept[tid >> 1][tid & 1] = 0;
 
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rlane = lane % RL;
     const int hsub = lane / RL;
-    float c[RPT], s[RPT];
+    float c[RPT], s[RPT], nk_row[RPT];
     int rowoff[RPT];
-    bool live[RPT];
+    const float nkf = static_cast<float>(g.n_kappa);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int r = rlane + RL * i;
-        live[i] = r < len;
+        const bool live = r < len;
         int j = first + r;
         if (j < 0)
             j += n_phi;
         if (j >= n_phi)
             j -= n_phi;
-        if (!live[i])
+        if (!live)
             j = 0;
         c[i] = g.cos_phi[j];
         s[i] = g.sin_phi[j];
-        rowoff[i] = r * stride;
+        nk_row[i] = live ? nkf : 0.0f;   // rows past the tile accept no bin
+        rowoff[i] = r;
     }
     const float d = D3 ? g.d0[l] : 0.0f;
     // Let the row constants land now: the memory counter is in order, so a
@@ -171,7 +195,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const float dd = d * d;
     const float kmin = g.kappa_min;
     const float kscale = g.kappa_scale;
-    const float nkf = static_cast<float>(g.n_kappa);
+    const int trash = U16 ? 2 * g.row_dwords : g.row_dwords;   // bin index of the spare column
     const bool div_fast = a.div_fast != 0;
     const float *__restrict__ xs = a.x;
     const float *__restrict__ ys = a.y;
@@ -179,38 +203,85 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const int64_t astep = a.arc_step;
     const int tile_first = first < 0 ? first + n_phi : first;   // rows [tile_first, +len) mod n_phi
 
-    // Kappa bin of one hit at row i of this lane; *ok tells whether it votes.
-    auto bin = [&](const float4 &h, int i, bool *ok) -> int {
+    // The spare column's bin index, held in a VGPR so that the select below is
+    // a single v_cndmask.
+    int trash_v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(trash_v) : "s"(trash));
+
+    // Kappa bin of one staged hit (x, y, z, w) at row i of this lane: the bin
+    // to add to, which is the spare column when the hit casts no vote there.
+    // FAST (2D only): z = r2/2 and w its refined reciprocal; u / (r2/2) is the
+    // same real number as 2u / r2, so its correctly rounded quotient is the
+    // same.  Otherwise z = r2 (2D) and the operator divides.
+    auto bin = [&](const float4 &h, int i, bool valid, auto fast) -> int {
         const float u = h.y * c[i] - h.x * s[i];
         float kappa;
         if constexpr (D3) {
             const float num = 2.0f * (u - d);
             const float den = (h.z - d2 * u) + dd;
             kappa = num / den;
+        } else if constexpr (decltype(fast)::value) {
+            kappa = quot_apply(u, h.z, h.w);
         } else {
-            float num = 2.0f * u;
-            if (h.w != 0.0f) {
-                kappa = quot_apply(num, h.z, h.w);
-            } else {
-                // Rare: keep the operator's division out of the common path.
-                asm volatile("" : "+v"(num));
-                kappa = num / h.z;
-            }
+            kappa = (2.0f * u) / h.z;
         }
         const float kf = (kappa - kmin) * kscale;
-        *ok = live[i] && kf >= 0.0f && kf < nkf;
-        return static_cast<int>(kf);
+        const bool ok = valid && kf >= 0.0f && kf < nk_row[i];
+        return ok ? static_cast<int>(kf) : trash_v;
     };
-    auto vote = [&](int k, int i) {
+    auto vote = [&](int kk, int i) {
         if constexpr (U16)
-            lds_add(&lds[rowoff[i] + (k >> 1)], (k & 1) ? 0x10000u : 1u);
+            lds_add(&lds[(kk >> 1) * stride + rowoff[i]], 1u << ((kk & 1) << 4));
         else
-            lds_add(&lds[rowoff[i] + k], 1u);
+            lds_add(&lds[kk * stride + rowoff[i]], 1u);
+    };
+    // Evaluate and vote two hits of this lane group (valid: the hit exists).
+    auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast) {
+        int ka[RPT], kb[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            ka[i] = bin(ha, i, va, fast);
+            kb[i] = bin(hb, i, vb, fast);
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            vote(ka[i], i);
+            vote(kb[i], i);
+        }
+    };
+    // Staged hits [lo, hi) of the current block (lo, hi wave-uniform).  An
+    // iteration covers 2G consecutive hits: lane group lg = wave*HPW + hsub
+    // takes hits it + lg and it + G + lg.  Two iterations per trip with the
+    // next pair read before the current votes are cast (two register sets, no
+    // copies), so waiting for a read never waits for atomics still in flight.
+    // Full trips need no per-lane checks; the tail (< 4G hits) checks.
+    constexpr int G = NW * HPW;
+    const int lg = wave * HPW + hsub;
+    auto sweep = [&](int lo, int hi, auto fast) {
+        if (lo >= hi)
+            return;
+        const float4 *hp = ts.hits + lg;
+        int it = lo;
+        float4 a0 = hp[it], b0 = hp[it + G];
+        for (; it + 4 * G <= hi; it += 4 * G) {
+            const float4 a1 = hp[it + 2 * G], b1 = hp[it + 3 * G];
+            eval2(a0, b0, true, true, fast);
+            a0 = hp[it + 4 * G];
+            b0 = hp[it + 5 * G];
+            eval2(a1, b1, true, true, fast);
+        }
+        if (it < hi) {
+            const float4 a1 = hp[it + 2 * G], b1 = hp[it + 3 * G];
+            eval2(a0, b0, it + lg < hi, it + G + lg < hi, fast);
+            if (it + 2 * G < hi)
+                eval2(a1, b1, it + 2 * G + lg < hi, it + 3 * G + lg < hi, fast);
+        }
     };
 
     // Hit blocks: every thread loads kHitBlock/NT hits of the next block
     // (loads issued unconditionally, index clamped) while the current block is
-    // evaluated; whether a hit is kept is decided when it is staged.
+    // evaluated.  Kept hits are staged from the front of ts.hits (2D, division
+    // in the hoisted form) or from the back (operator division).
     constexpr int PER = kHitBlock / NT > 0 ? kHitBlock / NT : 1;
     constexpr int STAGERS = kHitBlock / PER;    // threads that stage
     float px[PER], py[PER];
@@ -235,93 +306,163 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             const bool keep = mine && b0 + q * STAGERS + tid < h_end &&
                               (arc_meets(pa[q].x, tile_first, len, n_phi) ||
                                arc_meets(pa[q].y, tile_first, len, n_phi));
-            const uint64_t m = __ballot(keep);
-            int base = 0;
-            if (lane == 0 && m)
-                base = atomicAdd(&ts.n_kept[parity], __popcll(m));
-            base = __shfl(base, 0, 64);
-            if (keep) {
-                const float r2 = px[q] * px[q] + py[q] * py[q];
-                float rec = 0.0f;
-                if constexpr (!D3)
-                    rec = (div_fast && quot_den_ok(r2)) ? quot_recip(r2) : 0.0f;
-                ts.hits[base + rank_below(m)] = make_float4(px[q], py[q], r2, rec);
-            }
+            const float r2 = px[q] * px[q] + py[q] * py[q];
+            const float half = 0.5f * r2;
+            const bool fast = !D3 && div_fast && quot_den_ok(half);
+            const uint64_t mf = __ballot(keep && fast);
+            const uint64_t ms = __ballot(keep && !fast);
+            int bf = 0, bs = 0;
+            if (lane == 0 && mf)
+                bf = atomicAdd(&ts.n_kept[parity][0], __popcll(mf));
+            if (lane == 0 && ms)
+                bs = atomicAdd(&ts.n_kept[parity][1], __popcll(ms));
+            bf = __shfl(bf, 0, 64);
+            bs = __shfl(bs, 0, 64);
+            if (keep && fast)
+                ts.hits[bf + rank_below(mf)] = make_float4(px[q], py[q], half, quot_recip(half));
+            else if (keep)
+                ts.hits[kHitBlock - 1 - (bs + rank_below(ms))] = make_float4(px[q], py[q], r2, 0.0f);
         }
         __syncthreads();
-        const int n = ts.n_kept[parity];
-        if (tid == 0)
-            ts.n_kept[parity ^ 1] = 0;           // free: every thread passed the last barrier
+        const int n_fast = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][0]);
+        const int n_slow = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][1]);
+        if (tid < 2)
+            ts.n_kept[parity ^ 1][tid] = 0;      // free: every thread passed the last barrier
         if (b0 + kHitBlock < h_end)
             fetch(b0 + kHitBlock);
-        // Two groups of HPW hits per iteration: all bins first, then the votes.
-        for (int i0 = wave * HPW; i0 < n; i0 += 2 * NW * HPW) {
-            const int ia = i0 + hsub;
-            const int ib = i0 + NW * HPW + hsub;
-            const float4 ha = ts.hits[ia < n ? ia : 0];
-            const float4 hb = ts.hits[ib < n ? ib : 0];
-            int ka[RPT], kb[RPT];
-            bool oa[RPT], ob[RPT];
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                ka[i] = bin(ha, i, &oa[i]);
-                kb[i] = bin(hb, i, &ob[i]);
-            }
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                if (ia < n && oa[i])
-                    vote(ka[i], i);
-                if (ib < n && ob[i])
-                    vote(kb[i], i);
-            }
-        }
+        if constexpr (!D3)
+            sweep(0, n_fast, std::true_type{});
+        sweep(kHitBlock - n_slow, kHitBlock, std::false_type{});
     }
     __syncthreads();
 
     const int rd = g.row_dwords;
     unsigned long long votes = 0;
+    // Post-vote work runs with lanes across rows (conflict-free LDS reads):
+    // thread tid handles row rr = tid % ROWS over kappa segment tid / ROWS.
+    constexpr int SEGS = NT / ROWS > 0 ? NT / ROWS : 1;
+    const int rr = tid % ROWS;
+    const int seg = tid / ROWS;
     if constexpr (FUSED) {
         // Interior rows 1..s_here of the tile are phi0 rows j_first.. of slice 0.
         const int j_first = t * a.tile_stride;
         const int nk = g.n_kappa;
         const int32_t *tile = reinterpret_cast<const int32_t *>(lds);
         const int32_t thr = a.threshold;
+        const int kseg = (nk + SEGS - 1) / SEGS;
+        const int k_lo = min(nk, seg * kseg);
+        const int k_hi = min(nk, k_lo + kseg);
+        const bool row_ok = tid < ROWS * SEGS && rr >= 1 && rr <= s_here;
+        // Asymmetric 3x3 test of cell (rr, k) in the kappa-major tile:
+        // neighbours at offsets (phi0, kappa) that are lexicographically
+        // negative -- row rr-1, or row rr at k-1 -- need val > w, the others
+        // val >= w.
+        auto peak = [&](int k, int32_t *v) {
+            const int32_t *col = tile + k * stride + rr;
+            const int32_t val = col[0];
+            *v = val;
+            if (val < thr)
+                return false;
+            bool ok = val > col[-1] && val >= col[1];
+            if (k > 0) {
+                const int32_t *cm = col - stride;
+                ok = ok && val > cm[-1] && val > cm[0] && val >= cm[1];
+            }
+            if (k + 1 < nk) {
+                const int32_t *cp = col + stride;
+                ok = ok && val > cp[-1] && val >= cp[0] && val >= cp[1];
+            }
+            return ok;
+        };
+        // pass 1: count per (row, segment); scan in row-major order
+        int mine = 0;
+        if (row_ok) {
+            for (int k = k_lo; k < k_hi; ++k) {
+                int32_t v;
+                mine += peak(k, &v) ? 1 : 0;
+            }
+        }
+        const int order = rr * SEGS + seg;       // position of (row, segment) in cell order
+        if (tid < ROWS * SEGS)
+            ts.cnt[order] = mine;
+        __syncthreads();
+        int v_in = tid < ROWS * SEGS ? ts.cnt[tid] : 0;
+        int incl = v_in;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off, 64);
+            if (lane >= off)
+                incl += o;
+        }
+        if (lane == 63)
+            ts.wave_tot[wave] = incl;
+        __syncthreads();
+        int wpre = 0, total = 0;
+#pragma unroll
+        for (int wv = 0; wv < NW; ++wv) {
+            const int c0 = ts.wave_tot[wv];
+            wpre += wv < wave ? c0 : 0;
+            total += c0;
+        }
+        __syncthreads();
+        if (tid < ROWS * SEGS)
+            ts.cnt[tid] = wpre + incl - v_in;   // exclusive offset
+        __syncthreads();
+        // pass 2: write in cell order, histogram the first sort digit
         Cand *out = a.w.s0.stage + (static_cast<int64_t>(e) * a.w.s0.n_blocks0 + t) * a.w.s0.cap0;
-        uint32_t kmin_key, kmax_key;
-        const int count = compact_ordered<NT>(
-            s_here * nk,
-            [&](int idx, int32_t *v, int32_t *cell) {
-                const int rr = idx / nk;
-                const int k = idx - rr * nk;
-                const int32_t *row = tile + (rr + 1) * stride;
-                const int32_t val = row[k];
-                if (val < thr || !is_peak_2d(row, stride, nk, k, val))
-                    return false;
-                *v = val;
-                *cell = (j_first + rr) * nk + k;
-                return true;
-            },
-            out, ts.sc, &kmin_key, &kmax_key);
-        publish_block<NT>(a.w, e, t, count, ts.sc, kmin_key, kmax_key);
-        uint32_t *dst = acc_event ? acc_event + static_cast<int64_t>(j_first) * rd : nullptr;
-        for (int rr = 0; rr < s_here; ++rr)
-            for (int wd = tid; wd < rd; wd += NT) {
-                const uint32_t v = lds[(rr + 1) * stride + wd];
+        uint32_t kmin_key = 0xffffffffu, kmax_key = 0u;
+        if (row_ok && mine > 0) {
+            int pos = ts.cnt[order];
+            for (int k = k_lo; k < k_hi; ++k) {
+                int32_t v;
+                if (peak(k, &v)) {
+                    out[pos++] = Cand{v, (j_first + rr - 1) * nk + k};
+                    const uint32_t key = sort_key(v);
+                    atomicAdd(&ts.sc.hist[key & 0xffu], 1u);
+                    kmin_key = min(kmin_key, key);
+                    kmax_key = max(kmax_key, key);
+                }
+            }
+        }
+        kmin_key = wave_min_u32(kmin_key);
+        kmax_key = wave_max_u32(kmax_key);
+        if (lane == 0) {
+            ts.sc.red_min[wave] = kmin_key;
+            ts.sc.red_max[wave] = kmax_key;
+        }
+        __syncthreads();
+        uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+        for (int wv = 0; wv < NW; ++wv) {
+            mn = min(mn, ts.sc.red_min[wv]);
+            mx = max(mx, ts.sc.red_max[wv]);
+        }
+        publish_block<NT>(a.w, e, t, total, ts.sc, mn, mx);
+        // vote count (and the accumulator, if wanted) of the interior rows
+        uint32_t *dst = acc_event ? acc_event + static_cast<int64_t>(j_first + rr - 1) * rd : nullptr;
+        if (row_ok) {
+            for (int k = k_lo; k < k_hi; ++k) {
+                const uint32_t v = lds[k * stride + rr];
                 votes += v;
                 if (dst)
-                    dst[static_cast<int64_t>(rr) * rd + wd] = v;
+                    dst[k] = v;
             }
+        }
     } else {
-        uint32_t *dst = acc_event + (static_cast<int64_t>(l) * n_phi + first) * rd;
-        for (int rr = 0; rr < len; ++rr)
-            for (int wd = tid; wd < rd; wd += NT) {
-                const uint32_t v = lds[rr * stride + wd];
+        const int kseg = (rd + SEGS - 1) / SEGS;
+        const int w_lo = min(rd, seg * kseg);
+        const int w_hi = min(rd, w_lo + kseg);
+        if (tid < ROWS * SEGS && rr < len) {
+            uint32_t *dst = acc_event + (static_cast<int64_t>(l) * n_phi + first + rr) * rd;
+            for (int wd = w_lo; wd < w_hi; ++wd) {
+                const uint32_t v = lds[wd * stride + rr];
                 votes += cell_sum<U16>(v);
                 if (!atomic_flush)
-                    dst[static_cast<int64_t>(rr) * rd + wd] = v;
+                    dst[wd] = v;
                 else if (v)
-                    atomicAdd(&dst[static_cast<int64_t>(rr) * rd + wd], v);
+                    atomicAdd(&dst[wd], v);
             }
+        }
     }
     if (n_votes) {
         const unsigned long long wsum = wave_sum_u64(votes);
@@ -566,13 +707,14 @@ void fill_inputs(VoteArgs &a, const VoteInputs &in) {
 }  // namespace
 
 size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords) {
-    return static_cast<size_t>(s.rows) * static_cast<size_t>(row_dwords + s.pad) * sizeof(uint32_t);
+    // kappa-major tile: row_dwords columns of `rows` dwords, plus the spare column
+    return (static_cast<size_t>(row_dwords) + 1) * static_cast<size_t>(s.rows) * sizeof(uint32_t);
 }
 
 bool vote_shape_supported(const VoteShape &s, bool u16, int32_t row_dwords) {
     if (!pick_vote(u16, false, false, s.rows, s.threads))
         return false;
-    if (s.pad < 0 || s.pad > 1 || s.split < 1 || s.split > 64)
+    if (s.split < 1 || s.split > 64)
         return false;
     // dynamic tile + static scratch (staged hits, compaction and reductions)
     return vote_lds_bytes(s, row_dwords) + sizeof(TileScratch<1024>) <= 160u * 1024u;
@@ -644,7 +786,6 @@ hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, c
     a.n_hits = n_hits;
     a.split = s.split;
     tile_geometry(g, s, false, &a.tiles_per_slice, &a.tile_stride, &a.tile_off);
-    a.lds_stride = g.row_dwords + s.pad;
     a.acc = acc;
     a.n_votes = n_votes;
     hipError_t e = hipSuccess;
@@ -666,7 +807,6 @@ hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const Vote
     fill_inputs(a, in);
     a.split = 1;
     tile_geometry(g, s, fused, &a.tiles_per_slice, &a.tile_stride, &a.tile_off);
-    a.lds_stride = g.row_dwords + s.pad;
     a.desc = desc;
     a.items = items;
     a.n_items = n_items_dev;

@@ -12,15 +12,17 @@
 // performs the same operations, so its result is bit-identical to a / b;
 // outside it the caller divides with the operator.
 //
-// In 2D the denominator r2 is the same for all phi0 rows of a hit, so y is
+// In 2D the denominator is the same for all phi0 rows of a hit, so y is
 // computed once per hit and each evaluation costs five FMA-pipe operations
-// instead of eleven.
+// instead of eleven.  The 2D kernels divide u by r2/2 (both exact scalings of
+// 2u and r2, so the real quotient, and with it the rounded one, is unchanged).
 //
-// Range of the 2D numerator.  With a phi0 table of bin centres
-// (|cos|, |sin| <= 1 + 1e-6, and neither closer to 0 than sin(pi / n_phi),
-// n_phi <= 32768) and r2 = x*x + y*y in [2^-30, 2^30]: |2u| <= 2^17, and a
-// nonzero u = RN(RN(y c) - RN(x s)) is at least 2^-25 max(|y c|, |x s|) >=
-// 2^-54 in magnitude, so every nonzero numerator is in the range below.  A
+// Range of the 2D operands.  With a phi0 table of bin centres (|cos|, |sin|
+// <= 1 + 1e-6, and neither closer to 0 than sin(pi / n_phi), n_phi <= 32768)
+// and r2/2 in [2^-30, 2^30]: r < 2^16, so |u| <= 2^17, and a nonzero
+// u = RN(RN(y c) - RN(x s)) is at least 2^-25 max(|y c|, |x s|) >= 2^-54 in
+// magnitude (max(|x|, |y|) >= r / sqrt(2) >= 2^-15 and the smaller of |c|, |s|
+// is at least 2^-14), so every nonzero numerator is in the range below.  A
 // zero numerator may come out as +0 instead of -0, which moves no vote:
 // (+-0 - kappa_min) is the same number, or +-0 when kappa_min is 0, and both
 // zeros pass the range test into bin 0.

@@ -79,9 +79,9 @@ def load(path: str = LIB_PATH):
     lib.hough_vote_batch.restype = i32
     lib.hough_vote_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.hough_set_launch.restype = i32
-    lib.hough_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
+    lib.hough_set_launch.argtypes = [vp, i32, i32, i32, i32]
     lib.hough_get_launch.restype = i32
-    lib.hough_get_launch.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
+    lib.hough_get_launch.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 3
     lib.hough_set_timing.restype = i32
     lib.hough_set_timing.argtypes = [vp, i32]
     lib.hough_get_timing.restype = i32
@@ -253,8 +253,8 @@ class HoughContext:
                "hough_vote_batch")
         return acc, n_votes
 
-    def set_launch(self, which, rows, threads, split=1, pad=0):
-        _check(self.lib.hough_set_launch(self.handle, which, rows, threads, split, pad), "hough_set_launch")
+    def set_launch(self, which, rows, threads, split=1):
+        _check(self.lib.hough_set_launch(self.handle, which, rows, threads, split), "hough_set_launch")
 
     def set_timing(self, enable: bool):
         _check(self.lib.hough_set_timing(self.handle, 1 if enable else 0), "hough_set_timing")
@@ -266,7 +266,7 @@ class HoughContext:
         return v.value, t.value
 
     def get_launch(self, which):
-        vals = [ctypes.c_int32() for _ in range(4)]
+        vals = [ctypes.c_int32() for _ in range(3)]
         _check(self.lib.hough_get_launch(self.handle, which, *[ctypes.byref(v) for v in vals]),
                "hough_get_launch")
         return tuple(v.value for v in vals)

@@ -73,23 +73,23 @@ def test_workload_event_matches_oracle(cfg):
     _assert_same(_gpu_find(ctx, ev.x, ev.y, wc.threshold), ref, f"workload {cfg}")
 
 
-@pytest.mark.parametrize("shape", [(64, 256, 1, 0), (64, 512, 4, 1), (64, 1024, 2, 0), (64, 512, 16, 0),
-                                   (64, 256, 64, 1)])
+@pytest.mark.parametrize("shape", [(64, 256, 1), (64, 512, 4), (64, 1024, 2), (64, 512, 16), (64, 256, 64),
+                                   (32, 256, 1), (32, 512, 4), (32, 1024, 8)])
 def test_vote_launch_shapes_agree_2d(shape):
     print(f"[parity] 2D shape {shape}", flush=True)
     wc = synth.CONFIGS[2]
     ev = synth.gen_config_event(2)
     ref = _oracle(("cfg", 2), ev.x, ev.y, wc.grid, wc.threshold)
     ctx = hough.HoughContext(wc.grid, max_hits=ev.n_hits)
-    rows, threads, split, pad = shape
-    ctx.set_launch(0, rows, threads, split, pad)
+    ctx.set_launch(0, *shape)
     acc, nv = ctx.vote(_t(ev.x), _t(ev.y))
     torch.cuda.synchronize()
     np.testing.assert_array_equal(hough.acc_to_numpy(acc, ctx.spec).reshape(-1), ref[0].reshape(-1))
     assert int(nv.item()) == ref[1]
 
 
-@pytest.mark.parametrize("shape", [(64, 256, 1, 0), (64, 512, 2, 1), (128, 1024, 1, 0), (128, 256, 3, 1)])
+@pytest.mark.parametrize("shape", [(64, 256, 1), (64, 512, 2), (128, 1024, 1), (128, 256, 3), (32, 512, 1),
+                                   (32, 256, 2)])
 def test_vote_launch_shapes_agree_3d(shape):
     print(f"[parity] 3D shape {shape}", flush=True)
     wc = synth.CONFIGS[3]
@@ -137,9 +137,9 @@ def test_odd_small_grids(dims):
     ev = synth.gen_config_event(1)
     ref = oracle.find(ev.x, ev.y, grid, 2)
     ctx = hough.HoughContext(grid)
-    for rows, threads, split in ((64, 256, 1), (64, 512, 3), (128, 256, 1)):
+    for rows, threads, split in ((64, 256, 1), (64, 512, 3), (128, 256, 1), (32, 512, 2)):
         try:
-            ctx.set_launch(0, rows, threads, split, 0)
+            ctx.set_launch(0, rows, threads, split)
         except hough.HoughError:
             assert rows * (ctx.spec.n_kappa // (2 if ctx.spec.acc_u16 else 1)) * 4 > 120000
             continue
@@ -211,14 +211,14 @@ def test_invalid_arguments_raise():
     with pytest.raises(hough.HoughError):
         ctx.vote(x, x)                                     # more than max_hits
     with pytest.raises(hough.HoughError):
-        ctx.set_launch(0, 24, 256, 1, 0)                   # unsupported tile height
+        ctx.set_launch(0, 24, 256, 1)                 # unsupported tile height
     with pytest.raises(hough.HoughError):
-        ctx.set_launch(0, 64, 384, 1, 0)                   # unsupported workgroup size
+        ctx.set_launch(0, 64, 384, 1)                 # unsupported workgroup size
     big = hough.HoughContext(synth.GRID_2D)
     with pytest.raises(hough.HoughError):
-        big.set_launch(0, 128, 512, 1, 0)                  # 256 KiB of LDS
+        big.set_launch(0, 128, 512, 1)                # 256 KiB of LDS
     with pytest.raises(hough.HoughError):
-        ctx.set_launch(1, 64, 256, 2, 0)                   # batch tiles are never split
+        ctx.set_launch(1, 64, 256, 2)                 # batch tiles are never split
     with pytest.raises(hough.HoughError):
         ctx.event_batch(np.array([0, 5, 3]), x, x, 7)      # decreasing offsets
 
@@ -352,7 +352,7 @@ def test_culling_stress_displaced_hits_near_the_d0_circles():
     y[:8] = [5, -5, 0, 0, 1e-39, 1, 0, 0]
     ref = oracle.find(x, y, grid, 3)
     ctx = hough.HoughContext(grid, max_hits=x.size)
-    for shape in ((64, 512, 1, 0), (128, 256, 1, 0)):
+    for shape in ((64, 512, 1), (128, 256, 1), (32, 512, 1)):
         ctx.set_launch(0, *shape)
         _assert_same(_gpu_find(ctx, x, y, 3), ref, f"3D stress {shape}")
 
@@ -407,8 +407,12 @@ def test_batch_tile_shapes_agree():
     g = synth.GRID_2D
     base = None
     ctx = hough.HoughContext(g, max_events=6, max_hits=b.n_hits)
-    for shape in ((64, 512), (64, 1024), (64, 256)):
-        ctx.set_launch(1, shape[0], shape[1], 1, 0)
+    for shape in ((32, 512), (64, 512), (64, 1024), (64, 256), (32, 256), (32, 1024), (128, 512)):
+        try:
+            ctx.set_launch(1, shape[0], shape[1], 1)
+        except hough.HoughError:
+            assert shape[0] == 128     # a 128-row int32 tile of 512 kappa bins does not fit in LDS
+            continue
         res = _batch_results(ctx, b, 7)
         if base is None:
             base = res
