@@ -44,6 +44,9 @@ def parse_args():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-events", type=int, default=64)
+    ap.add_argument("--skip-per-event", action="store_true", help="skip the per-event-launch comparison")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -65,6 +68,51 @@ def cpu_baseline(batch, grid, threshold, budget_s):
     return {"value": n / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} of the {batch.n_events} events of the batch, vote + peaks + sort, "
                       f"one thread, {dt:.1f} s"}
+
+
+def per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off, events_per_s):
+    """Per-event launches (hough_vote + hough_peaks) on the same resident
+    events, and a closed loop with host round trips per event."""
+    log("per-event launches")
+    n_ev = batch.n_events
+    single = hough.HoughContext(grid, device=dev, max_hits=int(np.diff(hit_off).max()))
+    acc1 = single.new_acc()
+    out1 = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    nf1 = torch.empty(1, dtype=torch.int32, device=dev)
+    nv1 = torch.empty(1, dtype=torch.int64, device=dev)
+    views = [(x[hit_off[e]:hit_off[e + 1]], y[hit_off[e]:hit_off[e + 1]]) for e in range(n_ev)]
+    for xe, ye in views[:4]:
+        single.vote(xe, ye, acc1, nv1)
+        single.peaks(acc1, thr, cap, out1, nf1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for xe, ye in views:
+        single.vote(xe, ye, acc1, nv1)
+        single.peaks(acc1, thr, cap, out1, nf1)
+    torch.cuda.synchronize()
+    per_event_rate = n_ev / (time.perf_counter() - t0)
+    # closed loop with host round trips: pinned H2D hits -> vote -> peaks -> D2H list -> sync
+    lat = []
+    hx = torch.from_numpy(batch.x).pin_memory()
+    hy = torch.from_numpy(batch.y).pin_memory()
+    host_out = torch.empty((cap, 2), dtype=torch.int32).pin_memory()
+    xd = torch.empty(int(np.diff(hit_off).max()), dtype=torch.float32, device=dev)
+    yd = torch.empty_like(xd)
+    for e in range(min(args.latency_events, n_ev)):
+        a, b = int(hit_off[e]), int(hit_off[e + 1])
+        ts = time.perf_counter()
+        xd[:b - a].copy_(hx[a:b], non_blocking=True)
+        yd[:b - a].copy_(hy[a:b], non_blocking=True)
+        single.vote(xd[:b - a], yd[:b - a], acc1, nv1)
+        single.peaks(acc1, thr, cap, out1, nf1)
+        n = int(nf1.item())
+        host_out[:n].copy_(out1[:n])
+        lat.append(time.perf_counter() - ts)
+    lat_ms = 1e3 * np.array(lat)
+    return {"events_per_s": per_event_rate, "batched_speedup": events_per_s / per_event_rate,
+            "closed_loop_p50_ms": float(np.percentile(lat_ms, 50)),
+            "closed_loop_p99_ms": float(np.percentile(lat_ms, 99)),
+            "closed_loop_events": len(lat)}
 
 
 def main():
@@ -145,42 +193,18 @@ def main():
     lds = {"achieved": votes / (vote_ms * 1e-3) / 1e12, "peak": PEAK_LDS_ATOMIC / 1e12, "unit": "T atomics/s",
            "frac": votes / (vote_ms * 1e-3) / PEAK_LDS_ATOMIC}
 
-    # Per-event launch on the same resident events: hough_vote + hough_peaks per event.
-    log("per-event launches")
-    single = hough.HoughContext(grid, device=dev, max_hits=int(np.diff(hit_off).max()))
-    acc1 = single.new_acc()
-    out1 = torch.empty((cap, 2), dtype=torch.int32, device=dev)
-    nf1 = torch.empty(1, dtype=torch.int32, device=dev)
-    nv1 = torch.empty(1, dtype=torch.int64, device=dev)
-    views = [(x[hit_off[e]:hit_off[e + 1]], y[hit_off[e]:hit_off[e + 1]]) for e in range(n_ev)]
-    for xe, ye in views[:4]:
-        single.vote(xe, ye, acc1, nv1)
-        single.peaks(acc1, thr, cap, out1, nf1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for xe, ye in views:
-        single.vote(xe, ye, acc1, nv1)
-        single.peaks(acc1, thr, cap, out1, nf1)
-    torch.cuda.synchronize()
-    per_event_rate = n_ev / (time.perf_counter() - t0)
-    # closed loop with host round trips: pinned H2D hits -> vote -> peaks -> D2H list -> sync
-    lat = []
-    hx = torch.from_numpy(batch.x).pin_memory()
-    hy = torch.from_numpy(batch.y).pin_memory()
-    host_out = torch.empty((cap, 2), dtype=torch.int32).pin_memory()
-    xd = torch.empty(int(np.diff(hit_off).max()), dtype=torch.float32, device=dev)
-    yd = torch.empty_like(xd)
-    for e in range(min(args.latency_events, n_ev)):
-        a, b = int(hit_off[e]), int(hit_off[e + 1])
-        ts = time.perf_counter()
-        xd[:b - a].copy_(hx[a:b], non_blocking=True)
-        yd[:b - a].copy_(hy[a:b], non_blocking=True)
-        single.vote(xd[:b - a], yd[:b - a], acc1, nv1)
-        single.peaks(acc1, thr, cap, out1, nf1)
-        n = int(nf1.item())
-        host_out[:n].copy_(out1[:n])
-        lat.append(time.perf_counter() - ts)
-    lat_ms = 1e3 * np.array(lat)
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    line_extra = {}
+    if not args.skip_per_event:
+        line_extra["per_event_launch"] = per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off,
+                                                   events_per_s)
 
     line = {
         "metric": "events/s (batched vote + peaks + sorted candidates, one graph per 256-event batch)",
@@ -200,13 +224,10 @@ def main():
         "votes_per_s": votes * args.steps / dt,
         "evals_per_s": evals * args.steps / dt,
         "candidates_per_step": found,
-        "per_event_launch": {"events_per_s": per_event_rate, "batched_speedup": events_per_s / per_event_rate,
-                             "closed_loop_p50_ms": float(np.percentile(lat_ms, 50)),
-                             "closed_loop_p99_ms": float(np.percentile(lat_ms, 99)),
-                             "closed_loop_events": len(lat)},
         "roofline": roofline,
         "lds_atomic_roofline": lds,
     }
+    line.update(line_extra)
     if not args.no_cpu:
         log("oracle sample on the host")
         line["cpu_baseline"] = cpu_baseline(batch, grid, thr, args.cpu_seconds)

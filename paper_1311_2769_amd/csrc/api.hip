@@ -85,8 +85,9 @@ struct hough_ctx {
     uint32_t *hist = nullptr;
     Cand *tmp0 = nullptr;
     uint32_t *acc_ws = nullptr;   // batch accumulators when the caller passes none
-    uint2 *arcs = nullptr;        // [n_d0][max_hits], when cull_ok
-    uint2 *full = nullptr;        // one full-circle arc entry: culling off
+    float4 *hits = nullptr;       // [max_hits] hit records written by hit_prep
+    uint2 *ranges = nullptr;      // [n_d0][max_hits] tile ranges per hit, when cull_ok
+    uint2 *all_tiles = nullptr;   // one all-tiles entry: culling off
 
     // batch descriptors
     size_t desc_bytes = 0;
@@ -126,8 +127,8 @@ void free_ctx(hough_ctx *c) {
         (void)hipStreamDestroy(c->capture_stream);
     if (c->desc_host)
         (void)hipHostFree(c->desc_host);
-    void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->arcs, c->full, c->desc_dev,
-                   c->work_counter};
+    void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->hits, c->ranges, c->all_tiles,
+                   c->desc_dev, c->work_counter};
     for (void *p : dev)
         if (p)
             (void)hipFree(p);
@@ -138,15 +139,20 @@ int32_t batch_tiles_per_event(const hough_ctx *c, const VoteShape &s, bool fused
     return c->g.n_d0 * vote_tiles_per_slice(c->g, s, fused);
 }
 
-VoteInputs vote_inputs(const hough_ctx *c, const float *x, const float *y) {
+VoteInputs vote_inputs(const hough_ctx *c) {
     VoteInputs in{};
-    in.x = x;
-    in.y = y;
-    in.arcs = c->cull_ok ? c->arcs : c->full;
-    in.arc_stride = c->cull_ok ? c->max_hits : 0;
-    in.arc_step = c->cull_ok ? 1 : 0;
-    in.div_fast = c->cull_ok ? 1 : 0;
+    in.hits = c->hits;
+    in.ranges = c->cull_ok ? c->ranges : c->all_tiles;
+    in.range_stride = c->cull_ok ? c->max_hits : 0;
+    in.range_step = c->cull_ok ? 1 : 0;
     return in;
+}
+
+// Hit records (and tile ranges) for a vote launch of shape s.
+hipError_t hit_prep(const hough_ctx *c, const VoteShape &s, bool fused, const float *x, const float *y,
+                    int64_t n_hits, const int64_t *n_hits_dev, hipStream_t stream) {
+    return launch_hit_prep(c->g, vote_tile_geom(c->g, s, fused), x, y, n_hits, n_hits_dev, c->hits,
+                           c->cull_ok ? c->ranges : nullptr, c->max_hits, c->cull_ok, stream);
 }
 
 SortWork sort_work(const hough_ctx *c, bool fused_layout) {
@@ -311,13 +317,13 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
         ce = hipEventRecord(ctx->ev_start, cs);
     if (ce == hipSuccess)
         ce = launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, cs);
-    if (ce == hipSuccess && ctx->cull_ok)
-        ce = launch_hit_prep(ctx->g, x, y, bucket, &dd.hdr->n_hits, ctx->arcs, ctx->max_hits, cs);
+    if (ce == hipSuccess)
+        ce = hit_prep(ctx, vs, fused, x, y, bucket, &dd.hdr->n_hits, cs);
     if (ce == hipSuccess && timed)
         ce = hipEventRecord(ctx->ev_vote0, cs);
     uint32_t *a = (fused || acc_dw) ? acc_dw : ctx->acc_ws;
     if (ce == hipSuccess)
-        ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, x, y), dd.desc,
+        ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx), dd.desc,
                                &dd.hdr->n_items, dd.items, ctx->max_items, ctx->work_counter,
                                ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs);
     if (ce == hipSuccess && timed)
@@ -447,12 +453,13 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     e = e ? e : dev_alloc(&c->hist, E * static_cast<size_t>(c->hist_chunks) * kDigits);
     e = e ? e : dev_alloc(&c->tmp0, E * static_cast<size_t>(c->bound));
     e = e ? e : dev_alloc(&c->acc_ws, E * static_cast<size_t>(g.acc_dwords));
+    e = e ? e : dev_alloc(&c->hits, static_cast<size_t>(c->max_hits));
     if (c->cull_ok)
-        e = e ? e : dev_alloc(&c->arcs, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
-    e = e ? e : dev_alloc(&c->full, 1);
+        e = e ? e : dev_alloc(&c->ranges, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
+    e = e ? e : dev_alloc(&c->all_tiles, 1);
     if (e == hipSuccess) {
-        const uint2 full_circle = make_uint2(static_cast<uint32_t>(g.n_phi) << 16, 0u);
-        e = hipMemcpy(c->full, &full_circle, sizeof(uint2), hipMemcpyHostToDevice);
+        const uint2 all = make_uint2(kAllTiles, 0u);
+        e = hipMemcpy(c->all_tiles, &all, sizeof(uint2), hipMemcpyHostToDevice);
     }
     e = e ? e : dev_alloc(&c->desc_dev, c->desc_bytes);
     e = e ? e : dev_alloc(&c->work_counter, 1);
@@ -557,9 +564,8 @@ hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t 
     const VoteShape &vs = ctx->shape_single;
     if (nv)
         HIP_TRY(launch_prep(nullptr, 1, nv, s));
-    if (ctx->cull_ok)
-        HIP_TRY(launch_hit_prep(ctx->g, x, y, n_hits, nullptr, ctx->arcs, ctx->max_hits, s));
-    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, vs, vote_inputs(ctx, x, y), n_hits,
+    HIP_TRY(hit_prep(ctx, vs, false, x, y, n_hits, nullptr, s));
+    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, vs, vote_inputs(ctx), n_hits,
                                static_cast<uint32_t *>(acc), nv, s));
     return HOUGH_OK;
 }
@@ -601,9 +607,8 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
     const VoteShape &vs = ctx->shape_batch;
     auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
     HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, s));
-    if (ctx->cull_ok)
-        HIP_TRY(launch_hit_prep(ctx->g, x, y, hit_off[n_events], nullptr, ctx->arcs, ctx->max_hits, s));
-    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, x, y), dd.desc, &dd.hdr->n_items,
+    HIP_TRY(hit_prep(ctx, vs, false, x, y, hit_off[n_events], nullptr, s));
+    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx), dd.desc, &dd.hdr->n_items,
                               dd.items, ctx->max_items, ctx->work_counter, ctx->persistent_groups,
                               static_cast<uint32_t *>(acc), nv, nullptr, 0, s));
     return HOUGH_OK;

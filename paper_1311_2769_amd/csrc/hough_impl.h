@@ -94,14 +94,26 @@ struct SortWork {
     const int32_t *n_events_dev;  // batch: live event count on the device, or nullptr
 };
 
-// Hit inputs of a vote launch: coordinates and optional phi0 arcs.
+// Hit inputs of a vote launch, as written by hit_prep: one record per hit
+// and, with culling, two tile ranges per hit and d0 slice.
 struct VoteInputs {
-    const float *x;
-    const float *y;
-    const uint2 *arcs;         // [n_d0][arc_stride] arcs per hit, or one full-circle entry
-    int64_t arc_stride;        // 0 with the full-circle entry
-    int32_t arc_step;          // 1 with arcs, 0 with the full-circle entry
-    int32_t div_fast;          // 2D hoisted-reciprocal division allowed (bin-centre phi0 table)
+    const float4 *hits;        // [n] (x, y, z, w): see launch_hit_prep
+    const uint2 *ranges;       // [n_d0][range_stride] tile ranges per hit, or one all-tiles entry
+    int64_t range_stride;      // 0 with the all-tiles entry
+    int32_t range_step;        // 1 with ranges, 0 with the all-tiles entry
+};
+
+// A tile range packs first | count << 16 (tile indices of one d0 slice,
+// cyclic); count 0 is empty and kAllTiles covers every tile.
+constexpr uint32_t kAllTiles = 0xffffu << 16;
+
+// Tile geometry of a vote launch: tile t of a slice owns phi0 rows
+// [t*stride, min((t+1)*stride, n_phi)); with halo it also votes the row
+// before and the row after (cyclically), for the fused peak search.
+struct TileGeom {
+    int32_t tiles;
+    int32_t stride;
+    int32_t halo;
 };
 
 // Launch shape of a vote kernel.
@@ -117,6 +129,7 @@ struct VoteShape {
 bool vote_shape_supported(const VoteShape &s, bool u16, int32_t row_dwords);
 size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords);
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
+TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused);
 int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);
 
 hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *n_votes,
@@ -125,10 +138,15 @@ hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *
 hipError_t launch_prep_batch(EventState *state, int32_t max_events, const int32_t *n_events_dev,
                              unsigned long long *n_votes, int32_t *work_counter, hipStream_t stream);
 hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
-// The two phi0 arcs, per hit and d0 slice, outside which a hit cannot vote
-// (arcs[l*arc_stride + h]; each arc packed as start | length << 16, in rows).
-hipError_t launch_hit_prep(const GridArgs &g, const float *x, const float *y, int64_t n_hits,
-                           const int64_t *n_hits_dev, uint2 *arcs, int64_t arc_stride, hipStream_t stream);
+// Per-hit preparation of a vote launch with tile geometry tg.  hits[h] =
+// (x, y, r2/2, refined 1/(r2/2)) for 2D hits whose quotient may use the
+// hoisted division (div_fast and r2/2 in range), else (x, y, r2, 0).  With
+// ranges: ranges[l*range_stride + h] holds the two tile ranges of slice l
+// outside which hit h cannot vote.  n_hits_dev, when given, overrides n_hits
+// (which then only sizes the grid).
+hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x, const float *y, int64_t n_hits,
+                           const int64_t *n_hits_dev, float4 *hits, uint2 *ranges, int64_t range_stride,
+                           bool div_fast, hipStream_t stream);
 
 // One event: hits [0, n_hits).
 hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,

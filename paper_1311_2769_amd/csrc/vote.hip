@@ -13,33 +13,38 @@
 // the LDS atomics of one instruction fall in distinct banks whatever kappa
 // bins the hit produces.  Every lane adds on every evaluation: a lane whose
 // hit casts no vote in its row adds into one spare kappa column past the
-// grid, which keeps the loop free of branches and selects.  The finished tile
-// is flushed to HBM, lanes again across rows -- no global atomics on the
-// accumulator -- and the vote count is reduced per wavefront and added once
-// per workgroup.
+// grid, which keeps the loop free of branches.  The finished tile is flushed
+// to HBM, lanes again across rows -- no global atomics on the accumulator --
+// and the vote count is reduced per wavefront and added once per workgroup.
 //
-// Hits stream through LDS in blocks: each thread loads its share of the next
-// block while the current one is evaluated, and only the hits that may vote
-// in the tile are staged, with r2, for LDS reads that each lane group issues
-// one iteration ahead of its votes.
+// Hits.  hit_prep_kernel writes one record per hit (x, y and the hit's
+// denominator terms) and, per d0 slice, the two cyclic ranges of tiles
+// outside which the hit cannot vote.  A tile streams the event's records
+// through LDS in blocks of kHitBlock: each thread loads its share of the next
+// block while the current one is evaluated, and only the hits whose ranges
+// hold the tile are staged.  Lane groups read staged hits one iteration ahead
+// of their votes; the fewer than 4G hits left over after whole iterations are
+// carried into the next block, so only the last block of a tile has a
+// partial iteration.
 //
 // Culling.  A hit can only vote in the phi0 rows where its curvature lies in
 // the kappa range: two arcs of phi0 per d0 slice.  hit_prep_kernel computes
-// both arcs per hit and slice, widened by bounds on every fp32 rounding of the
-// vote arithmetic (see below); a hit is staged for a tile only if an arc meets
-// the tile's rows.  Which votes are cast is still decided only by the exact
-// fp32 test, so culling changes no result.
+// both arcs, widened by bounds on every fp32 rounding of the vote arithmetic
+// (see below), and converts them to the tiles whose voted rows meet them.
+// Which votes are cast is still decided only by the exact fp32 test, so
+// culling changes no result.
 //
 // Arithmetic is the fp32 definition in hough.h, op for op; this file is
 // compiled with -ffp-contract=off.  r2 = x*x + y*y is computed with the same
-// operations when a hit is staged.  For the 2D grid (d0 == +0) the numerator
+// operations in hit_prep_kernel.  For the 2D grid (d0 == +0) the numerator
 // 2*(u - 0) equals 2*u and the denominator (r2 - 0*u) + 0*0 equals r2 for every
 // finite u, and both forms give NaN or an out-of-range kf otherwise, so the 2D
 // kernels divide 2*u by r2.  Hits whose r2/2 lies in the range of vote_math.h
-// are staged at the front of the block as (x, y, r2/2, refined 1/(r2/2)) and
-// evaluated as u / (r2/2) with the hoisted division: the same real quotient as
-// 2u / r2, so the same correctly rounded result.  The others (and every 3D
-// hit) are staged at the back and divide with the operator.
+// carry (x, y, r2/2, refined 1/(r2/2)), are staged at the front of the block
+// and are evaluated as u / (r2/2) with the hoisted division: the same real
+// quotient as 2u / r2, so the same correctly rounded result.  The others (and
+// every 3D hit) carry (x, y, r2, 0), are staged at the back and divide with
+// the operator.
 //
 // uint16 accumulators are packed two cells per dword in LDS (even kappa bin in
 // the low half): a vote adds 1 or 0x10000 with one 32-bit LDS atomic.  The low
@@ -52,6 +57,7 @@
 // order to its staging list; the accumulator need not reach HBM at all.
 #pragma clang fp contract(off)
 
+#include <climits>
 #include <type_traits>
 
 #include "hough_impl.h"
@@ -63,12 +69,10 @@ namespace {
 
 struct VoteArgs {
     GridArgs g;
-    const float *x;
-    const float *y;
-    const uint2 *arcs;          // [n_d0][arc_stride] phi0 arcs per hit; or one full-circle entry (step 0)
-    int64_t arc_stride;
-    int32_t arc_step;           // 1 with arcs, 0 without
-    int32_t div_fast;           // 2D: hoisted-reciprocal division allowed (bin-centre phi0 table)
+    const float4 *hits;         // hit records (x, y, z, w)
+    const uint2 *ranges;        // [n_d0][range_stride] tile ranges per hit; or one all-tiles entry (step 0)
+    int64_t range_stride;
+    int32_t range_step;         // 1 with ranges, 0 without
     int32_t n_hits;             // single event
     int32_t split;              // single event: hit chunks per tile
     int32_t tiles_per_slice;
@@ -84,21 +88,28 @@ struct VoteArgs {
     int32_t threshold;          // fused
 };
 
-constexpr int kHitBlock = 512;   // hits staged in LDS per round
+constexpr int kHitBlock = 512;   // hit records examined per block
 
-// Staged hits of a block are read up to 4 lane-group strides past the end of
-// their list (values that are never used), so the array has that much slack.
+// Staged hits of a block: fast ones from the front (a carried remainder of
+// fewer than 4G, then up to kHitBlock new ones), slow ones downwards from
+// slow_end, and 4G slots of slack after that for the reads a lane group
+// issues past the end of a list (values that are never used).  G, the lane
+// groups of a workgroup, is at most twice its wavefronts.
 template <int NT>
-constexpr int hit_slack() { return 4 * (NT / 64) * 2; }
+constexpr int max_groups() { return 2 * (NT / 64); }
+template <int NT>
+constexpr int slow_end() { return kHitBlock + 4 * max_groups<NT>(); }
+template <int NT>
+constexpr int hit_slots() { return slow_end<NT>() + 4 * max_groups<NT>(); }
 
 template <int NT>
 struct TileScratch {
-    float4 hits[kHitBlock + hit_slack<NT>()];   // kept hits of the current block
+    float4 hits[hit_slots<NT>()];
     CompactScratch<NT> sc;
     int32_t cnt[NT];                 // fused peak search: candidates per (row, kappa segment)
     int32_t wave_tot[NT / 64];
     unsigned long long red[NT / 64];
-    int32_t n_kept[2][2];            // per block parity: hits staged at the front, at the back
+    int32_t n_kept[2][2];            // per block parity: staged at the front, at the back
     int32_t next_item;
 };
 
@@ -111,26 +122,6 @@ __device__ __forceinline__ uint32_t cell_sum(uint32_t v) {
     return U16 ? (v & 0xffffu) + (v >> 16) : v;
 }
 
-// Does the arc (start, length) of phi0 rows meet rows [a, a + rows) (all
-// modulo n, a in [0, n))?
-__device__ __forceinline__ bool arc_meets(uint32_t arc, int a, int rows, int n) {
-    const int start = static_cast<int>(arc & 0xffffu);
-    const int len = static_cast<int>(arc >> 16);
-    int da = a - start;
-    da += da < 0 ? n : 0;
-    int ds = start - a;
-    ds += ds < 0 ? n : 0;
-    return len > 0 && (da < len || ds < rows);
-}
-
-// Hit j of a wavefront's register batch (lane j holds it), as wave-uniform values.
-__device__ __forceinline__ float4 lane_hit(const float4 &v, int j) {
-    return make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), j)),
-                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), j)),
-                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.z), j)),
-                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.w), j)));
-}
-
 // Vote hits [h_begin, h_end) of event e into tile t of d0 slice l, then either
 // flush it (unfused) or search its interior rows for peaks (fused).
 template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
@@ -141,10 +132,14 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     constexpr int HPW = 64 / RL;                // hits per wavefront instruction
     constexpr int RPT = ROWS / RL;              // rows per lane
     constexpr int NW = NT / 64;
+    constexpr int G = NW * HPW;                 // lane groups
+    constexpr int SLOW_END = slow_end<NT>();
+    constexpr int stride = ROWS;                // dwords per LDS kappa column
+    static_assert(G <= max_groups<NT>(), "staging slack");
     const GridArgs &g = a.g;
     const int tid = threadIdx.x;
-    constexpr int stride = ROWS;                            // dwords per LDS kappa column
     const int n_phi = g.n_phi;
+    const int T = a.tiles_per_slice;
     const int first = t * a.tile_stride + a.tile_off;      // may be -1 for a fused tile
     int len, s_here = 0;
     if constexpr (FUSED) {
@@ -196,23 +191,17 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const float kmin = g.kappa_min;
     const float kscale = g.kappa_scale;
     const int trash = U16 ? 2 * g.row_dwords : g.row_dwords;   // bin index of the spare column
-    const bool div_fast = a.div_fast != 0;
-    const float *__restrict__ xs = a.x;
-    const float *__restrict__ ys = a.y;
-    const uint2 *__restrict__ arow = a.arcs + static_cast<int64_t>(l) * a.arc_stride;
-    const int64_t astep = a.arc_step;
-    const int tile_first = first < 0 ? first + n_phi : first;   // rows [tile_first, +len) mod n_phi
-
-    // The spare column's bin index, held in a VGPR so that the select below is
-    // a single v_cndmask.
+    // ... held in a VGPR so that the select below is a single v_cndmask
     int trash_v;
     asm volatile("v_mov_b32 %0, %1" : "=v"(trash_v) : "s"(trash));
+    const float4 *__restrict__ hrec = a.hits;
+    const uint2 *__restrict__ rrow = a.ranges + static_cast<int64_t>(l) * a.range_stride;
+    const int64_t rstep = a.range_step;
 
     // Kappa bin of one staged hit (x, y, z, w) at row i of this lane: the bin
     // to add to, which is the spare column when the hit casts no vote there.
-    // FAST (2D only): z = r2/2 and w its refined reciprocal; u / (r2/2) is the
-    // same real number as 2u / r2, so its correctly rounded quotient is the
-    // same.  Otherwise z = r2 (2D) and the operator divides.
+    // fast (2D only): z = r2/2 and w its refined reciprocal.  Otherwise z = r2
+    // and the operator divides.
     auto bin = [&](const float4 &h, int i, bool valid, auto fast) -> int {
         const float u = h.y * c[i] - h.x * s[i];
         float kappa;
@@ -249,13 +238,12 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             vote(kb[i], i);
         }
     };
-    // Staged hits [lo, hi) of the current block (lo, hi wave-uniform).  An
-    // iteration covers 2G consecutive hits: lane group lg = wave*HPW + hsub
-    // takes hits it + lg and it + G + lg.  Two iterations per trip with the
-    // next pair read before the current votes are cast (two register sets, no
-    // copies), so waiting for a read never waits for atomics still in flight.
-    // Full trips need no per-lane checks; the tail (< 4G hits) checks.
-    constexpr int G = NW * HPW;
+    // Staged hits [lo, hi) (lo, hi wave-uniform).  An iteration covers 2G
+    // consecutive hits: lane group lg = wave*HPW + hsub takes hits it + lg and
+    // it + G + lg.  Two iterations per trip, the next pair read before the
+    // current votes are cast (two register sets, no copies), so waiting for a
+    // read never waits for atomics still in flight.  Whole trips need no
+    // per-lane checks; a tail of fewer than 4G hits checks.
     const int lg = wave * HPW + hsub;
     auto sweep = [&](int lo, int hi, auto fast) {
         if (lo >= hi)
@@ -277,38 +265,42 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
                 eval2(a1, b1, it + 2 * G + lg < hi, it + 3 * G + lg < hi, fast);
         }
     };
+    // Is this tile in the cyclic tile range r?
+    auto in_range = [&](uint32_t r) {
+        int dt = t - static_cast<int>(r & 0xffffu);
+        dt += dt < 0 ? T : 0;
+        return dt < static_cast<int>(r >> 16);
+    };
 
-    // Hit blocks: every thread loads kHitBlock/NT hits of the next block
+    // Hit blocks: every thread loads kHitBlock/NT records of the next block
     // (loads issued unconditionally, index clamped) while the current block is
-    // evaluated.  Kept hits are staged from the front of ts.hits (2D, division
-    // in the hoisted form) or from the back (operator division).
+    // evaluated; whether a hit is kept is decided when it is staged.
     constexpr int PER = kHitBlock / NT > 0 ? kHitBlock / NT : 1;
     constexpr int STAGERS = kHitBlock / PER;    // threads that stage
-    float px[PER], py[PER];
-    uint2 pa[PER];
+    float4 ph[PER];
+    uint2 pr[PER];
     auto fetch = [&](int64_t b0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int64_t h = min(b0 + q * STAGERS + tid, h_end - 1);
-            pa[q] = arow[h * astep];
-            px[q] = xs[h];
-            py[q] = ys[h];
+            pr[q] = rrow[h * rstep];
+            ph[q] = hrec[h];
         }
     };
     if (h_begin < h_end)
         fetch(h_begin);
     int parity = 0;
+    int carry = 0;                               // fast hits carried into this block
+    float4 carry_v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // this thread's carried hit (tid < carry)
     for (int64_t b0 = h_begin; b0 < h_end; b0 += kHitBlock, parity ^= 1) {
         __syncthreads();                         // the previous block is fully evaluated
+        if (tid < carry)
+            ts.hits[tid] = carry_v;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const bool mine = tid < STAGERS;
-            const bool keep = mine && b0 + q * STAGERS + tid < h_end &&
-                              (arc_meets(pa[q].x, tile_first, len, n_phi) ||
-                               arc_meets(pa[q].y, tile_first, len, n_phi));
-            const float r2 = px[q] * px[q] + py[q] * py[q];
-            const float half = 0.5f * r2;
-            const bool fast = !D3 && div_fast && quot_den_ok(half);
+            const bool keep = mine && b0 + q * STAGERS + tid < h_end && (in_range(pr[q].x) || in_range(pr[q].y));
+            const bool fast = !D3 && ph[q].w != 0.0f;
             const uint64_t mf = __ballot(keep && fast);
             const uint64_t ms = __ballot(keep && !fast);
             int bf = 0, bs = 0;
@@ -319,20 +311,26 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             bf = __shfl(bf, 0, 64);
             bs = __shfl(bs, 0, 64);
             if (keep && fast)
-                ts.hits[bf + rank_below(mf)] = make_float4(px[q], py[q], half, quot_recip(half));
+                ts.hits[bf + rank_below(mf)] = ph[q];
             else if (keep)
-                ts.hits[kHitBlock - 1 - (bs + rank_below(ms))] = make_float4(px[q], py[q], r2, 0.0f);
+                ts.hits[SLOW_END - 1 - (bs + rank_below(ms))] = ph[q];
         }
         __syncthreads();
-        const int n_fast = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][0]);
+        const int n_fast = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][0]);   // with the carried hits
         const int n_slow = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][1]);
+        const bool last = b0 + kHitBlock >= h_end;
+        const int whole = last ? n_fast : n_fast - n_fast % (4 * G);
+        const int carry_next = n_fast - whole;
         if (tid < 2)
-            ts.n_kept[parity ^ 1][tid] = 0;      // free: every thread passed the last barrier
-        if (b0 + kHitBlock < h_end)
+            ts.n_kept[parity ^ 1][tid] = tid == 0 ? carry_next : 0;   // every thread passed the last barrier
+        if (tid < carry_next)
+            carry_v = ts.hits[whole + tid];      // nothing writes the staged hits until the next barrier
+        if (!last)
             fetch(b0 + kHitBlock);
         if constexpr (!D3)
-            sweep(0, n_fast, std::true_type{});
-        sweep(kHitBlock - n_slow, kHitBlock, std::false_type{});
+            sweep(0, whole, std::true_type{});
+        sweep(SLOW_END - n_slow, SLOW_END, std::false_type{});
+        carry = carry_next;
     }
     __syncthreads();
 
@@ -340,53 +338,79 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     unsigned long long votes = 0;
     // Post-vote work runs with lanes across rows (conflict-free LDS reads):
     // thread tid handles row rr = tid % ROWS over kappa segment tid / ROWS.
-    constexpr int SEGS = NT / ROWS > 0 ? NT / ROWS : 1;
+    constexpr int SEGS = NT / ROWS;
+    static_assert(SEGS * ROWS == NT, "tile rows divide the workgroup");
     const int rr = tid % ROWS;
     const int seg = tid / ROWS;
     if constexpr (FUSED) {
         // Interior rows 1..s_here of the tile are phi0 rows j_first.. of slice 0.
         const int j_first = t * a.tile_stride;
         const int nk = g.n_kappa;
-        const int32_t *tile = reinterpret_cast<const int32_t *>(lds);
+        const int32_t *col = reinterpret_cast<const int32_t *>(lds) + rr;   // column k of this row at col[k*stride]
         const int32_t thr = a.threshold;
         const int kseg = (nk + SEGS - 1) / SEGS;
         const int k_lo = min(nk, seg * kseg);
         const int k_hi = min(nk, k_lo + kseg);
-        const bool row_ok = tid < ROWS * SEGS && rr >= 1 && rr <= s_here;
-        // Asymmetric 3x3 test of cell (rr, k) in the kappa-major tile:
-        // neighbours at offsets (phi0, kappa) that are lexicographically
-        // negative -- row rr-1, or row rr at k-1 -- need val > w, the others
-        // val >= w.
-        auto peak = [&](int k, int32_t *v) {
-            const int32_t *col = tile + k * stride + rr;
-            const int32_t val = col[0];
-            *v = val;
-            if (val < thr)
-                return false;
-            bool ok = val > col[-1] && val >= col[1];
-            if (k > 0) {
-                const int32_t *cm = col - stride;
-                ok = ok && val > cm[-1] && val > cm[0] && val >= cm[1];
+        const bool row_ok = rr >= 1 && rr <= s_here;
+        uint32_t *dst = (acc_event && row_ok) ? acc_event + static_cast<int64_t>(j_first + rr - 1) * rd : nullptr;
+
+        // Scan cells (rr, k_lo..k_hi) in order with a sliding 3x3 window of
+        // (row above, row, row below) columns k-1, k, k+1; kappa columns
+        // outside the grid read as INT_MIN, so they never stop a peak.
+        // Offsets (phi0, kappa) that are lexicographically negative -- the row
+        // above, or this row at k-1 -- must be exceeded, the others reached.
+        auto scan = [&](auto on_cell) {
+            int32_t uA = INT_MIN, mA = INT_MIN, dA = INT_MIN;
+            if (k_lo > 0) {
+                const int32_t *q = col + (k_lo - 1) * stride;
+                uA = q[-1];
+                mA = q[0];
+                dA = q[1];
             }
-            if (k + 1 < nk) {
-                const int32_t *cp = col + stride;
-                ok = ok && val > cp[-1] && val >= cp[0] && val >= cp[1];
+            const int32_t *q = col + k_lo * stride;
+            int32_t uB = q[-1], mB = q[0], dB = q[1];
+            auto cell = [&](int k, int32_t uC, int32_t mC, int32_t dC) {
+                const int32_t above = max(max(uA, uB), max(uC, mA));
+                const int32_t below = max(max(dA, dB), max(dC, mC));
+                on_cell(k, mB, mB >= thr && mB > above && mB >= below);
+                uA = uB;
+                mA = mB;
+                dA = dB;
+                uB = uC;
+                mB = mC;
+                dB = dC;
+            };
+            const int k_stop = min(k_hi, nk - 1);
+            int k = k_lo;
+            for (; k < k_stop; ++k) {
+                q += stride;
+                cell(k, q[-1], q[0], q[1]);
             }
-            return ok;
+            if (k < k_hi)
+                cell(k, INT_MIN, INT_MIN, INT_MIN);
         };
-        // pass 1: count per (row, segment); scan in row-major order
+
+        // pass 1: peaks per (row, segment) as a bit mask, vote count and the
+        // accumulator row if wanted
+        uint64_t pm = 0;
         int mine = 0;
-        if (row_ok) {
-            for (int k = k_lo; k < k_hi; ++k) {
-                int32_t v;
-                mine += peak(k, &v) ? 1 : 0;
-            }
+        if (row_ok && k_lo < k_hi) {
+            scan([&](int k, int32_t v, bool pk) {
+                votes += static_cast<uint32_t>(v);
+                if (dst)
+                    dst[k] = static_cast<uint32_t>(v);
+                if (pk) {
+                    ++mine;
+                    if (k - k_lo < 64)
+                        pm |= 1ull << (k - k_lo);
+                }
+            });
         }
-        const int order = rr * SEGS + seg;       // position of (row, segment) in cell order
-        if (tid < ROWS * SEGS)
-            ts.cnt[order] = mine;
+        // exclusive offsets in cell order: (row, segment) pairs row-major
+        const int order = rr * SEGS + seg;
+        ts.cnt[order] = mine;
         __syncthreads();
-        int v_in = tid < ROWS * SEGS ? ts.cnt[tid] : 0;
+        const int v_in = ts.cnt[tid];
         int incl = v_in;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -405,23 +429,30 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             total += c0;
         }
         __syncthreads();
-        if (tid < ROWS * SEGS)
-            ts.cnt[tid] = wpre + incl - v_in;   // exclusive offset
+        ts.cnt[tid] = wpre + incl - v_in;
         __syncthreads();
         // pass 2: write in cell order, histogram the first sort digit
         Cand *out = a.w.s0.stage + (static_cast<int64_t>(e) * a.w.s0.n_blocks0 + t) * a.w.s0.cap0;
         uint32_t kmin_key = 0xffffffffu, kmax_key = 0u;
-        if (row_ok && mine > 0) {
+        if (mine > 0) {
             int pos = ts.cnt[order];
-            for (int k = k_lo; k < k_hi; ++k) {
-                int32_t v;
-                if (peak(k, &v)) {
-                    out[pos++] = Cand{v, (j_first + rr - 1) * nk + k};
-                    const uint32_t key = sort_key(v);
-                    atomicAdd(&ts.sc.hist[key & 0xffu], 1u);
-                    kmin_key = min(kmin_key, key);
-                    kmax_key = max(kmax_key, key);
+            auto emit = [&](int k, int32_t v) {
+                out[pos++] = Cand{v, (j_first + rr - 1) * nk + k};
+                const uint32_t key = sort_key(v);
+                atomicAdd(&ts.sc.hist[key & 0xffu], 1u);
+                kmin_key = min(kmin_key, key);
+                kmax_key = max(kmax_key, key);
+            };
+            if (k_hi - k_lo <= 64) {
+                for (uint64_t m = pm; m; m &= m - 1) {
+                    const int k = k_lo + __builtin_ctzll(m);
+                    emit(k, col[k * stride]);
                 }
+            } else {
+                scan([&](int k, int32_t v, bool pk) {
+                    if (pk)
+                        emit(k, v);
+                });
             }
         }
         kmin_key = wave_min_u32(kmin_key);
@@ -438,21 +469,11 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             mx = max(mx, ts.sc.red_max[wv]);
         }
         publish_block<NT>(a.w, e, t, total, ts.sc, mn, mx);
-        // vote count (and the accumulator, if wanted) of the interior rows
-        uint32_t *dst = acc_event ? acc_event + static_cast<int64_t>(j_first + rr - 1) * rd : nullptr;
-        if (row_ok) {
-            for (int k = k_lo; k < k_hi; ++k) {
-                const uint32_t v = lds[k * stride + rr];
-                votes += v;
-                if (dst)
-                    dst[k] = v;
-            }
-        }
     } else {
         const int kseg = (rd + SEGS - 1) / SEGS;
         const int w_lo = min(rd, seg * kseg);
         const int w_hi = min(rd, w_lo + kseg);
-        if (tid < ROWS * SEGS && rr < len) {
+        if (rr < len) {
             uint32_t *dst = acc_event + (static_cast<int64_t>(l) * n_phi + first + rr) * rd;
             for (int wd = w_lo; wd < w_hi; ++wd) {
                 const uint32_t v = lds[wd * stride + rr];
@@ -522,7 +543,8 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-hit preparation: the two phi0 arcs per d0 slice where a hit may vote.
+// Per-hit preparation: the hit record, and the two phi0 arcs per d0 slice
+// where a hit may vote, as ranges of tiles.
 //
 // Bound used (angles in radians, K = max |kappa edge|).  If a vote is cast,
 // the fp32 curvature kappa_c lies within K(1 + 2^-19).  kappa_c rounds
@@ -539,10 +561,14 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
 // that are not finite, sit within 1e-15 of the origin or beyond 1e15, or fail
 // the conditioning test get the full circle.  The phi0 table must hold the bin
 // centres (j + 1/2) 2 pi / n_phi (checked when the context is created;
-// otherwise no arcs are used).
+// otherwise no ranges are used).
 //
-// An arc is packed as start | length << 16 in rows (length 0: empty; length
-// n_phi: the full circle), so n_phi is limited to 32768.
+// An arc of rows (start, length; length 0: empty, n_phi: the full circle) is
+// turned into the cyclic range of tiles that vote any of its rows: the tile
+// owning its first row (or, with halos, the tile before when that row is the
+// first of its tile) through the tile owning its last row (or the tile after
+// when that row is the last of its tile).  n_phi is limited to 32768, so the
+// tile count fits the 16-bit fields.
 // ---------------------------------------------------------------------------
 
 struct PrepArgs {
@@ -550,10 +576,13 @@ struct PrepArgs {
     const float *y;
     int64_t n_hits;
     const int64_t *n_hits_dev;  // batch: live hit count (overrides n_hits), or nullptr
-    uint2 *arcs;
-    int64_t arc_stride;
+    float4 *hits;
+    uint2 *ranges;              // nullptr: no culling
+    int64_t range_stride;
     const float *d0;            // nullptr for 2D
     int32_t n_phi;
+    int32_t tiles, tile_stride, halo;
+    int32_t div_fast;
     double kabs;
 };
 
@@ -573,16 +602,56 @@ __device__ __forceinline__ uint32_t pack_arc(double phi_a, double phi_b, int n) 
     return static_cast<uint32_t>(start) | (static_cast<uint32_t>(rows) << 16);
 }
 
+__device__ __forceinline__ uint32_t tile_range(uint32_t arc, const PrepArgs &p) {
+    const int n = p.n_phi;
+    const int len = static_cast<int>(arc >> 16);
+    if (len == 0)
+        return 0u;
+    if (len >= n)
+        return kAllTiles;
+    const int S = p.tile_stride;
+    const int T = p.tiles;
+    const int start = static_cast<int>(arc & 0xffffu);
+    const int end_u = start + len - 1;                 // unwrapped, < 2n
+    const int end = end_u >= n ? end_u - n : end_u;
+    int lo = start / S;
+    if (p.halo && start == lo * S)
+        lo -= 1;                                       // the tile before votes it as its upper halo
+    const int oe = end / S;
+    int hi = (end_u >= n ? T : 0) + oe;
+    if (p.halo && end == oe * S + min(S, n - oe * S) - 1)
+        hi += 1;                                       // the tile after votes it as its lower halo
+    const int cnt = hi - lo + 1;
+    if (cnt >= T)
+        return kAllTiles;
+    if (lo < 0)
+        lo += T;
+    return static_cast<uint32_t>(lo) | (static_cast<uint32_t>(cnt) << 16);
+}
+
 __global__ void hit_prep_kernel(PrepArgs p) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int l = blockIdx.y;
     const int64_t n = p.n_hits_dev ? *p.n_hits_dev : p.n_hits;
     if (i >= n)
         return;
-    const double X = p.x[i];
-    const double Y = p.y[i];
-    const uint32_t full = static_cast<uint32_t>(p.n_phi) << 16;
-    uint2 out = make_uint2(full, 0u);
+    const float xf = p.x[i];
+    const float yf = p.y[i];
+    if (l == 0) {
+        const float r2 = xf * xf + yf * yf;
+        float4 rec = make_float4(xf, yf, r2, 0.0f);
+        if (p.div_fast && p.d0 == nullptr) {
+            const float half = 0.5f * r2;
+            if (quot_den_ok(half))
+                rec = make_float4(xf, yf, half, quot_recip(half));
+        }
+        p.hits[i] = rec;
+    }
+    if (!p.ranges)
+        return;
+    const double X = xf;
+    const double Y = yf;
+    uint2 out = make_uint2(kAllTiles, 0u);
     const double r = sqrt(X * X + Y * Y);
     const double d = p.d0 ? static_cast<double>(p.d0[l]) : 0.0;
     const double ad = fabs(d);
@@ -601,10 +670,11 @@ __global__ void hit_prep_kernel(PrepArgs p) {
             const double ahi = asin(fmin(shi, 1.0));
             const double ph = atan2(Y, X);
             const double pi = 3.141592653589793;
-            out = make_uint2(pack_arc(ph - ahi, ph - alo, p.n_phi), pack_arc(ph - pi + alo, ph - pi + ahi, p.n_phi));
+            out = make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi), p),
+                             tile_range(pack_arc(ph - pi + alo, ph - pi + ahi, p.n_phi), p));
         }
     }
-    p.arcs[static_cast<int64_t>(l) * p.arc_stride + i] = out;
+    p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = out;
 }
 
 __global__ void prep_kernel(EventState *state, int32_t n_events, unsigned long long *n_votes) {
@@ -683,28 +753,29 @@ hipError_t launch_vote(const VoteArgs &a, bool u16, bool fused, const VoteShape 
     return hipGetLastError();
 }
 
-void tile_geometry(const GridArgs &g, const VoteShape &s, bool fused, int32_t *tiles, int32_t *stride,
-                   int32_t *off) {
-    if (fused) {
-        *stride = s.rows - 2;
-        *off = -1;
-    } else {
-        *stride = s.rows;
-        *off = 0;
-    }
-    *tiles = (g.n_phi + *stride - 1) / *stride;
+void fill_inputs(VoteArgs &a, const VoteInputs &in) {
+    a.hits = in.hits;
+    a.ranges = in.ranges;
+    a.range_stride = in.range_stride;
+    a.range_step = in.range_step;
 }
 
-void fill_inputs(VoteArgs &a, const VoteInputs &in) {
-    a.x = in.x;
-    a.y = in.y;
-    a.arcs = in.arcs;
-    a.arc_stride = in.arc_stride;
-    a.arc_step = in.arc_step;
-    a.div_fast = in.div_fast;
+void set_geometry(VoteArgs &a, const GridArgs &g, const VoteShape &s, bool fused) {
+    const TileGeom tg = vote_tile_geom(g, s, fused);
+    a.tiles_per_slice = tg.tiles;
+    a.tile_stride = tg.stride;
+    a.tile_off = tg.halo ? -1 : 0;
 }
 
 }  // namespace
+
+TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused) {
+    TileGeom tg{};
+    tg.stride = fused ? s.rows - 2 : s.rows;
+    tg.halo = fused ? 1 : 0;
+    tg.tiles = (g.n_phi + tg.stride - 1) / tg.stride;
+    return tg;
+}
 
 size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords) {
     // kappa-major tile: row_dwords columns of `rows` dwords, plus the spare column
@@ -721,9 +792,7 @@ bool vote_shape_supported(const VoteShape &s, bool u16, int32_t row_dwords) {
 }
 
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused) {
-    int32_t tiles, stride, off;
-    tile_geometry(g, s, fused, &tiles, &stride, &off);
-    return tiles;
+    return vote_tile_geom(g, s, fused).tiles;
 }
 
 int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s) {
@@ -732,8 +801,9 @@ int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s) {
     return ((S + 1) / 2) * ((g.n_kappa + 1) / 2);
 }
 
-hipError_t launch_hit_prep(const GridArgs &g, const float *x, const float *y, int64_t n_hits,
-                           const int64_t *n_hits_dev, uint2 *arcs, int64_t arc_stride, hipStream_t stream) {
+hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x, const float *y, int64_t n_hits,
+                           const int64_t *n_hits_dev, float4 *hits, uint2 *ranges, int64_t range_stride,
+                           bool div_fast, hipStream_t stream) {
     if (n_hits <= 0)
         return hipSuccess;
     PrepArgs p{};
@@ -741,15 +811,20 @@ hipError_t launch_hit_prep(const GridArgs &g, const float *x, const float *y, in
     p.y = y;
     p.n_hits = n_hits;
     p.n_hits_dev = n_hits_dev;
-    p.arcs = arcs;
-    p.arc_stride = arc_stride;
+    p.hits = hits;
+    p.ranges = ranges;
+    p.range_stride = range_stride;
     p.d0 = g.d0;
     p.n_phi = g.n_phi;
+    p.tiles = tg.tiles;
+    p.tile_stride = tg.stride;
+    p.halo = tg.halo;
+    p.div_fast = div_fast ? 1 : 0;
     const double kmin = g.kappa_min;
     const double kmax = static_cast<double>(g.kappa_min) + static_cast<double>(g.n_kappa) / g.kappa_scale;
     p.kabs = fmax(fabs(kmin), fabs(kmax));
     const unsigned blocks = static_cast<unsigned>((n_hits + 255) / 256);
-    hipLaunchKernelGGL(hit_prep_kernel, dim3(blocks, g.n_d0), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(hit_prep_kernel, dim3(blocks, ranges ? g.n_d0 : 1), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -785,7 +860,7 @@ hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, c
     fill_inputs(a, in);
     a.n_hits = n_hits;
     a.split = s.split;
-    tile_geometry(g, s, false, &a.tiles_per_slice, &a.tile_stride, &a.tile_off);
+    set_geometry(a, g, s, false);
     a.acc = acc;
     a.n_votes = n_votes;
     hipError_t e = hipSuccess;
@@ -806,7 +881,7 @@ hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const Vote
     a.g = g;
     fill_inputs(a, in);
     a.split = 1;
-    tile_geometry(g, s, fused, &a.tiles_per_slice, &a.tile_stride, &a.tile_off);
+    set_geometry(a, g, s, fused);
     a.desc = desc;
     a.items = items;
     a.n_items = n_items_dev;
