@@ -30,9 +30,16 @@ if ROOT not in sys.path:
 # one non-fused, non-packed fp32 operation (157.3 TFLOP/s counts a packed
 # FMA as four flops per lane).
 PEAK_FP32_OPS = 256 * 64 * 2.4e9          # 39.3e12 single fp32 operations / s
-PEAK_LDS_ATOMIC = 256 * 32 * 2.4e9        # 19.7e12 dword atomics / s (32 banks per CU, one per clock)
+PEAK_LDS_ATOMIC = 256 * 64 * 2.4e9        # 39.3e12 dword atomics / s if every bank retires one per clock
 FLOPS_PER_EVAL_2D = 7                     # u: 2 mul + 1 sub; 2u: 1 mul; divide: 1; kf: 1 sub + 1 mul
 FLOPS_PER_HIT_2D = 3                      # r^2: 2 mul + 1 add
+
+# HBM bytes of the dominant kernel from rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE in KiB per dispatch, each scaled by what the counter reads for a
+# plain device copy of known size).  Used only while the kernel's sources are
+# the ones the counters were taken from.
+COUNTERS = os.path.join(ROOT, "profiles", "vote_fused_batch256_2d_counters.md")
+KERNEL_SOURCES = ["vote.hip", "vote_math.h", "peak_tile.h", "hough_impl.h"]
 
 
 def parse_args():
@@ -52,6 +59,34 @@ def parse_args():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1311_2769_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per launch of the vote kernel from the committed counter
+    summary, or None when it is missing or was taken from other sources."""
+    try:
+        with open(COUNTERS) as f:
+            fields = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    fields = {k.strip().strip("-* `"): v.strip().strip("` ") for k, v in fields.items()}
+    try:
+        if fields.get("kernel_source_sha256") != kernel_digest():
+            return None
+        fetch = float(fields["fetch_kib_per_dispatch"]) * float(fields["fetch_scale"])
+        write = float(fields["write_kib_per_dispatch"]) * float(fields["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return 1024.0 * (fetch + write)
 
 
 def cpu_baseline(batch, grid, threshold, budget_s):
@@ -185,13 +220,24 @@ def main():
     assert int(n_votes.sum().item()) == votes
     flops = evals * FLOPS_PER_EVAL_2D + int(batch.n_hits) * FLOPS_PER_HIT_2D
     achieved = flops / (vote_ms * 1e-3)
+    log("throughput probes")
+    lds_peak_meas, valu_peak_meas = hough.diag_rates()
+    traffic = counter_traffic()
     roofline = {"bound": "alu", "kernel": "vote_kernel (batched, persistent, fused peak search)",
                 "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_OPS / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_OPS,
-                "traffic": None, "launch_ms": vote_ms, "batch_ms_unfused_launches": float(np.mean(total_list[1:])),
-                "work_per_launch": {"evaluations": evals, "fp32_ops": flops, "votes": votes}}
-    lds = {"achieved": votes / (vote_ms * 1e-3) / 1e12, "peak": PEAK_LDS_ATOMIC / 1e12, "unit": "T atomics/s",
-           "frac": votes / (vote_ms * 1e-3) / PEAK_LDS_ATOMIC}
+                "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "peak_measured": valu_peak_meas / 1e12, "frac_of_measured": achieved / valu_peak_meas,
+                "launch_ms": vote_ms, "batch_ms_timing_mode": float(np.mean(total_list[1:])),
+                "work_per_launch": {"evaluations": evals, "fp32_ops": flops, "votes": votes,
+                                    "hits": int(batch.n_hits)}}
+    if traffic:
+        roofline["hbm_gbs"] = traffic / (vote_ms * 1e-3) / 1e9
+    vote_rate = votes / (vote_ms * 1e-3)
+    lds = {"achieved": vote_rate / 1e12, "peak": PEAK_LDS_ATOMIC / 1e12, "unit": "T atomics/s",
+           "frac": vote_rate / PEAK_LDS_ATOMIC, "peak_measured": lds_peak_meas / 1e12,
+           "frac_of_measured": vote_rate / lds_peak_meas}
 
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)

@@ -113,8 +113,9 @@ void hough_ctx_destroy(hough_ctx *ctx);
 hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t n_hits,
                         void *acc, uint64_t *n_votes, void *stream);
 
-/* Find the local maxima of an accumulator (Section 3: "looking for local
- * maxima in the parameter space").  acc: [dev] as produced by hough_vote
+/* Find the local maxima of an accumulator (Section 3: once all hits have
+ * voted, the local maxima of the votes are the candidates).  acc: [dev] as
+ * produced by hough_vote
  * (any values are accepted).  out: [dev][cap] sorted candidates (may be NULL
  * when cap == 0).  n_found: [dev] one int32, the full number of candidates.
  * EINVAL: null acc/n_found, cap < 0, threshold < 1 for u16 is allowed. */
@@ -177,6 +178,14 @@ hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms);
  * of mismatches (must be 0) and of pairs checked.  Allocates and frees a
  * 16-byte device buffer; synchronous. */
 hough_status hough_selftest_divide(int64_t n, uint64_t seed, uint64_t *mismatches, uint64_t *checked);
+
+/* Diagnostics (measurement only; no part of the method).  Saturating probes
+ * on the current device: the rate of conflict-free, no-return 32-bit LDS
+ * atomic adds (the vote's one memory operation) and of plain fp32 VALU
+ * operations (unpacked and unfused, as in the vote), both per second over the
+ * whole device.  Allocates and frees 64 bytes of device memory; synchronous.
+ * EINVAL for null outputs, EDEVICE on a HIP failure. */
+hough_status hough_diag_rates(double *lds_atomics_per_s, double *valu_ops_per_s);
 
 const char *hough_status_str(hough_status status);
 /* Text of the last HIP failure seen by this thread (empty if none). */

@@ -6,7 +6,7 @@
  * it.  It is deliberately plain: one thread, loops in the order of the
  * definition, no blocking, no vectorisation tricks.
  *
- * What it computes (Section 3, "The Hough transform ..." paragraph): every
+ * What it computes (Section 3, the description of the Hough transform): every
  * track hypothesis starts with zero votes; every hit adds one vote to every
  * hypothesis it is compatible with; local maxima of the vote array are then
  * the track candidates.
@@ -31,7 +31,7 @@
  *     (int)kf when 0 <= kf < n_kappa; NaN or infinite kf casts no vote;
  *   - a 2D grid is the 3D definition with one d0 bin at d0 = +0.
  *
- * Peak rule (Section 3: "looking for local maxima in the parameter space"):
+ * Peak rule (Section 3: track candidates are the local maxima of the votes):
  * a cell with v >= threshold is a candidate when, for every neighbour w at
  * offset o in {-1,0,1}^3 \ {0} (d0, phi0, kappa order), v > w if o is
  * lexicographically negative and v >= w otherwise.  phi0 is periodic; d0 and

@@ -379,7 +379,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     if (o.max_events == 0)
         o.max_events = 1;
     if (o.max_hits == 0)
-        o.max_hits = 1 << 18;
+        o.max_hits = 1 << 20;
 
     hough_ctx *c = new (std::nothrow) hough_ctx();
     if (!c)
@@ -399,8 +399,12 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     g.n_d0 = grid->n_d0;
     g.n_phi = grid->n_phi;
     g.n_kappa = grid->n_kappa;
-    g.kappa_min = grid->kappa_min;
+    // kappa_min = +0 is stored as -0: kf = (kappa - kappa_min) * kappa_scale
+    // then differs only for kappa = -0, where it is +0 instead of -0 (both vote
+    // bin 0), and is never -0 when kappa_scale >= 1 (see the vote's range test).
+    g.kappa_min = (grid->kappa_min == 0.0f) ? -0.0f : grid->kappa_min;
     g.kappa_scale = grid->kappa_scale;
+    g.bin_bits = grid->kappa_scale >= 1.0f ? 1 : 0;
     g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
     g.cells = cells;
     g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;

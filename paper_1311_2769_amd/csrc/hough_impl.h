@@ -62,6 +62,7 @@ struct GridArgs {
     int32_t n_d0, n_phi, n_kappa;
     float kappa_min, kappa_scale;
     int32_t row_dwords;   // dwords per (d0, phi0) row in global memory
+    int32_t bin_bits;     // kappa_scale >= 1 and kappa_min != +0: the vote's unsigned range test is exact
     int64_t cells;        // cells per event
     int64_t acc_dwords;   // dwords per event accumulator
 };

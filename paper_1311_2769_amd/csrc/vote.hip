@@ -163,7 +163,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rlane = lane % RL;
     const int hsub = lane / RL;
-    float c[RPT], s[RPT], nk_row[RPT];
+    float c[RPT], s[RPT];
     int rowoff[RPT];
     const float nkf = static_cast<float>(g.n_kappa);
 #pragma unroll
@@ -177,9 +177,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             j -= n_phi;
         if (!live)
             j = 0;
-        c[i] = g.cos_phi[j];
-        s[i] = g.sin_phi[j];
-        nk_row[i] = live ? nkf : 0.0f;   // rows past the tile accept no bin
+        // rows past the tile get NaN constants: their kf is NaN, which no bin accepts
+        c[i] = live ? g.cos_phi[j] : __builtin_nanf("");
+        s[i] = live ? g.sin_phi[j] : __builtin_nanf("");
         rowoff[i] = r;
     }
     const float d = D3 ? g.d0[l] : 0.0f;
@@ -202,7 +202,19 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // to add to, which is the spare column when the hit casts no vote there.
     // fast (2D only): z = r2/2 and w its refined reciprocal.  Otherwise z = r2
     // and the operator divides.
-    auto bin = [&](const float4 &h, int i, bool valid, auto fast) -> int {
+    //
+    // The range test 0 <= kf < n_kappa.  With bits (GridArgs::bin_bits) it is
+    // one unsigned minimum: kf >= +0 and kf < n_kappa exactly when the bit
+    // pattern of kf is below that of (float)n_kappa (non-negative floats order
+    // like their patterns; negative numbers and NaNs have larger patterns), so
+    // min(bits(kf), bits(n_kappa)) is kf itself when it votes and n_kappa --
+    // the spare column -- when it does not.  This needs kf never to be -0,
+    // which the oracle would accept: kf = (kappa - kappa_min) * kappa_scale is
+    // -0 only for kappa = -0 with kappa_min = +0 (the context stores -0
+    // instead, which changes no vote) or when a nonzero difference (at least
+    // 2^-149) times kappa_scale rounds to zero, impossible for kappa_scale >= 1.
+    const uint32_t lim_bits = __float_as_uint(nkf);
+    auto bin = [&](const float4 &h, int i, bool valid, auto fast, auto bits) -> int {
         const float u = h.y * c[i] - h.x * s[i];
         float kappa;
         if constexpr (D3) {
@@ -215,8 +227,13 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             kappa = (2.0f * u) / h.z;
         }
         const float kf = (kappa - kmin) * kscale;
-        const bool ok = valid && kf >= 0.0f && kf < nk_row[i];
-        return ok ? static_cast<int>(kf) : trash_v;
+        if constexpr (decltype(bits)::value) {
+            const uint32_t b = valid ? __float_as_uint(kf) : 0xffffffffu;
+            return static_cast<int>(__uint_as_float(min(b, lim_bits)));
+        } else {
+            const bool ok = valid && kf >= 0.0f && kf < nkf;
+            return ok ? static_cast<int>(kf) : trash_v;
+        }
     };
     auto vote = [&](int kk, int i) {
         if constexpr (U16)
@@ -225,12 +242,12 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             lds_add(&lds[kk * stride + rowoff[i]], 1u);
     };
     // Evaluate and vote two hits of this lane group (valid: the hit exists).
-    auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast) {
+    auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast, auto bits) {
         int ka[RPT], kb[RPT];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            ka[i] = bin(ha, i, va, fast);
-            kb[i] = bin(hb, i, vb, fast);
+            ka[i] = bin(ha, i, va, fast, bits);
+            kb[i] = bin(hb, i, vb, fast, bits);
         }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
@@ -245,7 +262,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // read never waits for atomics still in flight.  Whole trips need no
     // per-lane checks; a tail of fewer than 4G hits checks.
     const int lg = wave * HPW + hsub;
-    auto sweep = [&](int lo, int hi, auto fast) {
+    auto sweep_with = [&](int lo, int hi, auto fast, auto bits) {
         if (lo >= hi)
             return;
         const float4 *hp = ts.hits + lg;
@@ -253,17 +270,24 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         float4 a0 = hp[it], b0 = hp[it + G];
         for (; it + 4 * G <= hi; it += 4 * G) {
             const float4 a1 = hp[it + 2 * G], b1 = hp[it + 3 * G];
-            eval2(a0, b0, true, true, fast);
+            eval2(a0, b0, true, true, fast, bits);
             a0 = hp[it + 4 * G];
             b0 = hp[it + 5 * G];
-            eval2(a1, b1, true, true, fast);
+            eval2(a1, b1, true, true, fast, bits);
         }
         if (it < hi) {
             const float4 a1 = hp[it + 2 * G], b1 = hp[it + 3 * G];
-            eval2(a0, b0, it + lg < hi, it + G + lg < hi, fast);
+            eval2(a0, b0, it + lg < hi, it + G + lg < hi, fast, bits);
             if (it + 2 * G < hi)
-                eval2(a1, b1, it + 2 * G + lg < hi, it + 3 * G + lg < hi, fast);
+                eval2(a1, b1, it + 2 * G + lg < hi, it + 3 * G + lg < hi, fast, bits);
         }
+    };
+    const bool bin_bits = g.bin_bits != 0;
+    auto sweep = [&](int lo, int hi, auto fast) {
+        if (bin_bits)
+            sweep_with(lo, hi, fast, std::true_type{});
+        else
+            sweep_with(lo, hi, fast, std::false_type{});
     };
     // Is this tile in the cyclic tile range r?
     auto in_range = [&](uint32_t r) {

@@ -26,7 +26,7 @@ SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
     "hough_vote_batch",
     "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
-    "hough_selftest_divide", "hough_status_str", "hough_last_error", "hough_version",
+    "hough_selftest_divide", "hough_diag_rates", "hough_status_str", "hough_last_error", "hough_version",
 )
 
 
@@ -86,6 +86,8 @@ def load(path: str = LIB_PATH):
     lib.hough_set_timing.argtypes = [vp, i32]
     lib.hough_get_timing.restype = i32
     lib.hough_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+    lib.hough_diag_rates.restype = i32
+    lib.hough_diag_rates.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.hough_selftest_divide.restype = i32
     lib.hough_selftest_divide.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64)]
@@ -294,3 +296,11 @@ def cands_to_numpy(out, n_found, cap=None):
     m = n if cap is None else min(n, cap)
     c = out[:m].detach().cpu().numpy()
     return c[:, 0].astype(np.int64), c[:, 1].astype(np.int64), n
+
+
+def diag_rates():
+    """(LDS atomic adds/s, plain fp32 VALU ops/s) measured on the current device."""
+    lib = load()
+    a, v = ctypes.c_double(), ctypes.c_double()
+    _check(lib.hough_diag_rates(ctypes.byref(a), ctypes.byref(v)), "hough_diag_rates")
+    return a.value, v.value

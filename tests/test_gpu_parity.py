@@ -125,6 +125,31 @@ def test_nonfinite_origin_and_huge_hits():
         _assert_same(_gpu_find(ctx, pts[:, 0], pts[:, 1], 1), ref, f"special hits {grid.shape}")
 
 
+def test_kappa_min_zero_and_coarse_kappa_scale():
+    """kappa_min = +0 (the zero-curvature bin edge: kappa = -0 must still vote
+    bin 0) and kappa_scale < 1 (the vote's compare-form range test)."""
+    import dataclasses
+    ev = synth.gen_config_event(1)
+    # hits on the axes give u = +-0 exactly at phi0 = 0 of an exact table: (5, -0) gives u = -0
+    extra = np.array([[5.0, 0.0], [5.0, -0.0], [-6.0, 0.0], [-7.0, -0.0], [0.0, 7.0], [0.0, -8.0],
+                      [1e-20, 0.0]], np.float32)
+    assert np.signbit(extra[1, 1])
+    x = np.concatenate([ev.x, extra[:, 0]])
+    y = np.concatenate([ev.y, extra[:, 1]])
+    half = make_grid(64, 32, kappa_half_range_inv_cm=33.0)
+    zero_edge = dataclasses.replace(half, kappa_min=np.float32(0.0))
+    exact = make_grid(4, 16, kappa_half_range_inv_cm=33.0, phi_table=np.array([0.0, 0.5, 1.0, 1.5]) * math.pi)
+    exact_zero = dataclasses.replace(exact, kappa_min=np.float32(0.0))
+    coarse = make_grid(64, 8, kappa_half_range_inv_cm=0.1)        # kappa_scale 0.4
+    assert float(coarse.kappa_scale) < 1.0
+    for name, grid in (("kappa_min +0", zero_edge), ("exact table, kappa_min +0", exact_zero),
+                       ("kappa_scale < 1", coarse)):
+        print(f"[parity] {name}", flush=True)
+        ref = oracle.find(x, y, grid, 2)
+        ctx = hough.HoughContext(grid, max_hits=x.size)
+        _assert_same(_gpu_find(ctx, x, y, 2), ref, name)
+
+
 @pytest.mark.parametrize("dims", [(1, 3, 1), (1, 37, 13), (1, 5, 2), (3, 11, 6), (5, 33, 10), (2, 200, 64)])
 def test_odd_small_grids(dims):
     n_d0, n_phi, n_kappa = dims
@@ -448,3 +473,14 @@ def test_division_fast_path_equals_the_operator():
         assert bad == 0, f"{bad} mismatches of {used}"
         total += used
     assert total > 100_000_000
+
+
+def test_throughput_probes_report_plausible_rates():
+    """The roofline probes run and land within the chip's nominal limits."""
+    _dev()
+    lds, valu = hough.diag_rates()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    # at most 64 dword atomics and 64 lanes per CU per clock at <= 2.6 GHz
+    assert 0 < lds <= cus * 64 * 2.6e9
+    assert 0 < valu <= cus * 64 * 2.6e9
+    print(f"[probe] lds {lds / 1e12:.2f} T/s, valu {valu / 1e12:.2f} T/s on {cus} CUs", flush=True)
