@@ -52,6 +52,9 @@ def parse_args():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-events", type=int, default=64)
     ap.add_argument("--skip-per-event", action="store_true", help="skip the per-event-launch comparison")
+    ap.add_argument("--serve-rates", default="1000,5000,20000",
+                    help="offered rates (events/s) of the served stream; empty to skip")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="offered seconds of arrivals per rate")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -148,6 +151,64 @@ def per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off, eve
             "closed_loop_p50_ms": float(np.percentile(lat_ms, 50)),
             "closed_loop_p99_ms": float(np.percentile(lat_ms, 99)),
             "closed_loop_events": len(lat)}
+
+
+def served_stream(args, hough, synth, batch, log_fn):
+    """Open-loop served stream: Poisson arrivals of 80 % batch-workload 2D and
+    20 % displaced 3D events at each offered rate, through the library's
+    server (continuous batching, 2 lanes per grid, 2 ms deadline)."""
+    rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
+    if not rates:
+        return None
+    pool2 = batch.events
+    pool3 = [synth.gen_config_event(3, i) for i in range(32)]
+    grids = [synth.CONFIGS[4].grid, synth.CONFIGS[3].grid]
+    thr = [synth.CONFIGS[4].threshold, synth.CONFIGS[3].threshold]
+    srv = hough.Server(grids, thr, lanes=2, batch_events=[64, 8], batch_hits=[1 << 22, 1 << 19], deadline_ms=2.0,
+                       queue_limit=4096, keep_candidates=False)
+    out = []
+    try:
+        for rate in rates:
+            n = max(200, int(rate * args.serve_seconds))
+            rng = np.random.default_rng(np.random.SeedSequence([synth.BASE_SEED + 5, int(rate)]))
+            kind = (rng.uniform(size=n) < 0.2).astype(np.int32)
+            pick = [pool3[rng.integers(len(pool3))] if k else pool2[rng.integers(len(pool2))] for k in kind]
+            hit_off = np.zeros(n + 1, np.int64)
+            hit_off[1:] = np.cumsum([ev.n_hits for ev in pick])
+            x = np.concatenate([ev.x for ev in pick])
+            y = np.concatenate([ev.y for ev in pick])
+            arrivals = synth.poisson_arrivals(rate, n, stream=1)
+            log_fn(f"served stream: {n} events at {rate:.0f}/s")
+            status = {}
+            import threading
+            th = threading.Thread(target=lambda: status.update(s=srv.replay(arrivals, kind, hit_off, x, y)))
+            t_start = srv.clock()
+            th.start()
+            res = []
+            t_wall = time.time()
+            while th.is_alive() or len(res) < n:
+                res += srv.poll(wait_ms=20, cand_cap=0)
+                if not th.is_alive():
+                    accepted = int((status["s"] == 0).sum())
+                    if len(res) >= accepted:
+                        break
+                if time.time() - t_wall > 60 + 2 * args.serve_seconds:
+                    raise RuntimeError(f"served stream at {rate}/s: {len(res)} of {n} events returned in time")
+            th.join()
+            ok = [r for r in res if r["status"] == 0]
+            lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
+            t_end = max(r["t_done"] for r in ok)
+            span = t_end - t_start
+            refused = int((status["s"] != 0).sum())
+            votes = sum(int(r["n_votes"]) for r in ok)
+            out.append({"offered_per_s": rate, "events": n, "completed": len(ok), "refused": refused,
+                        "achieved_events_per_s": len(ok) / span, "votes_per_s": votes / span,
+                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                        "mean_batch_events": float(np.mean([r["batch_events"] for r in ok])),
+                        "share_3d": float(kind.mean())})
+    finally:
+        srv.close()
+    return out
 
 
 def main():
@@ -248,6 +309,9 @@ def main():
         del src, dst
 
     line_extra = {}
+    served = served_stream(args, hough, synth, batch, log)
+    if served is not None:
+        line_extra["served"] = served
     if not args.skip_per_event:
         line_extra["per_event_launch"] = per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off,
                                                    events_per_s)

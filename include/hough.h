@@ -61,7 +61,8 @@ typedef enum {
     HOUGH_OK = 0,
     HOUGH_EINVAL = -1,   /* invalid argument; nothing was enqueued */
     HOUGH_ENOMEM = -2,   /* workspace allocation failed (context creation only) */
-    HOUGH_EDEVICE = -3   /* a HIP runtime call failed; see hough_last_error() */
+    HOUGH_EDEVICE = -3,  /* a HIP runtime call failed; see hough_last_error() */
+    HOUGH_EBUSY = -4     /* the server's pending queue is full; the event was not taken */
 } hough_status;
 
 typedef enum {
@@ -162,6 +163,35 @@ hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32
 hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows, int32_t *threads,
                               int32_t *split);
 
+/* Autotuner (launch shapes only; results never depend on them).  Times every
+ * supported shape of `which` on the caller's resident hits and keeps the
+ * fastest on the context:
+ *   which 1: whole hough_event_batch calls (tile rows x workgroup size), with
+ *            the arguments of hough_event_batch (acc may be NULL);
+ *   which 0: hough_vote of event 0 (hits [hit_off[0], hit_off[1])) into acc
+ *            (required), over tile rows x workgroup size x hit split.
+ * Each shape runs reps + 1 times (the first warms up); the median decides.
+ * The candidates, counts and accumulators written are those of the last run,
+ * exactly as the plain calls write them.  With a cache path (else
+ * $HOUGH_TUNE_CACHE, else none) the winner is appended there as one JSON line
+ * keyed by device, grid dimensions, accumulator type, which and
+ * ceil(log2(hits)); hough_ctx_create applies the entry nearest to its
+ * max_hits.  best_ms (nullable) receives the winner's median time.
+ * Synchronous.  EINVAL as for the timed call, reps outside [1, 1000], or an
+ * unwritable cache file. */
+hough_status hough_autotune(hough_ctx *ctx, int32_t which, int32_t n_events, const int64_t *hit_off,
+                            const float *x, const float *y, int32_t threshold, void *acc,
+                            hough_cand *cands, const int64_t *cand_off, int32_t *n_found, int32_t reps,
+                            const char *cache_path, void *stream, float *best_ms);
+
+/* Host-only cache query (no device needed): the shape recorded for device tag
+ * `device` (e.g. "gfx950/256"), the grid's dimensions and accumulator type,
+ * `which` and the hit bucket nearest to ceil(log2(hits)).  *found = 0 when the
+ * file or an entry is missing.  Only the grid's sizes and acc_type are read. */
+hough_status hough_tune_lookup(const char *cache_path, const char *device, const hough_grid *grid,
+                               int32_t which, int64_t hits, int32_t *found, int32_t *rows,
+                               int32_t *threads, int32_t *split);
+
 /* Timing mode (for benchmarks and profiling; results are unchanged).  When
  * enabled, hough_event_batch enqueues its kernels directly on the stream
  * instead of replaying a graph and records HIP events around the whole batch
@@ -170,6 +200,74 @@ hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows
  * batch). */
 hough_status hough_set_timing(hough_ctx *ctx, int32_t enable);
 hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms);
+
+/* ------------------------------------------------------------------------
+ * Served stream (a trigger-farm node; Sections 1-2: events arrive
+ * continuously; Section 4: they are independent).  A server owns, per grid
+ * and per lane, a context, a stream and device-resident hit and candidate
+ * pools, and batches continuously: a free lane takes the events waiting for
+ * its grid as one hough_event_batch call while other lanes' batches run.
+ * Results are the ones hough_vote + hough_peaks give each event alone.
+ * ------------------------------------------------------------------------ */
+typedef struct hough_server hough_server;
+
+typedef struct {
+    int32_t n_grids;                 /* 1..8 */
+    const hough_grid *grids;         /* [n_grids]; tables must outlive the server */
+    const int32_t *thresholds;       /* [n_grids] peak thresholds */
+    int32_t lanes;                   /* batches in flight per grid (default 2, at most 8) */
+    const int32_t *batch_events;     /* [n_grids] event slots per batch, or NULL (64) */
+    const int64_t *batch_hits;       /* [n_grids] hit pool per lane, or NULL (1<<22) */
+    const int64_t *event_candidates; /* [n_grids] candidates kept per event, or NULL (the grid's bound) */
+    double deadline_ms;              /* longest wait to fill a batch while others run (default 2) */
+    int32_t queue_limit;             /* pending events before submit refuses (default 4096) */
+    int32_t keep_candidates;         /* 0: results carry counts only */
+    const char *tune_cache;          /* passed to every lane's context */
+} hough_server_opts;
+
+typedef struct {
+    int64_t tag;                     /* the caller's tag from submit */
+    int32_t grid;
+    int32_t status;                  /* HOUGH_OK, or HOUGH_EDEVICE if its batch failed */
+    int32_t n_hits;
+    int32_t n_found;                 /* full candidate count */
+    int32_t n_stored;                /* candidates copied to the poll buffer */
+    int32_t batch_events;            /* events in the batch it ran in */
+    uint64_t n_votes;
+    int64_t cand_offset;             /* first candidate in the poll buffer */
+    double t_submit, t_launch, t_done;   /* seconds on the server clock */
+} hough_served;
+
+/* Create a server on the current device (allocates every pool; starts a
+ * dispatcher thread and one completion thread per lane).  EINVAL for bad
+ * options, ENOMEM when the pools do not fit. */
+hough_status hough_server_create(hough_server **server, const hough_server_opts *opts);
+/* Launch what is still pending, wait for every batch and free the server. */
+void hough_server_destroy(hough_server *server);
+/* Seconds since the server was created (the clock of every time stamp). */
+double hough_server_clock(const hough_server *server);
+/* Hand one event to the server: x, y are host fp32 arrays, copied before the
+ * call returns.  t_submit: its arrival time on the server clock, or < 0 for
+ * now (latency is measured from it).  EINVAL: bad grid or pointers, or an
+ * event that can never be admitted (more hits than a lane's pool, or more
+ * than 65535 for a uint16 grid); EBUSY: the pending queue is full. */
+hough_status hough_server_submit(hough_server *server, int64_t tag, int32_t grid, const float *x,
+                                 const float *y, int32_t n_hits, double t_submit);
+/* Open-loop replay: submit event i (hits [hit_off[i], hit_off[i+1]) of x, y,
+ * grid grid[i]) at arrival_s[i] seconds after the call starts, stamping that
+ * scheduled time as its submit time, and write each submit's status to
+ * status[i].  Returns when all are submitted; poll concurrently. */
+hough_status hough_server_replay(hough_server *server, int32_t n, const double *arrival_s,
+                                 const int32_t *grid, const int64_t *hit_off, const float *x,
+                                 const float *y, int32_t *status);
+/* Take up to max_out finished events (waiting up to wait_ms for the first),
+ * copying their candidates back to back into cand_buf[cand_cap].  EDEVICE
+ * if a batch failed on the device (the failed events carry that status). */
+hough_status hough_server_poll(hough_server *server, hough_served *out, int32_t max_out,
+                               hough_cand *cand_buf, int64_t cand_cap, int32_t *n_out, int32_t wait_ms);
+/* Pending events, events refused so far and lanes with a batch in flight. */
+hough_status hough_server_stats(hough_server *server, int64_t *pending, int64_t *refused,
+                                int32_t *busy_lanes);
 
 /* Diagnostic: on the current device, compare the vote's division fast path
  * (the correctly rounded fp32 quotient with its reciprocal refinement done

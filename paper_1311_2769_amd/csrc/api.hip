@@ -291,9 +291,17 @@ DevDesc device_descriptors(const hough_ctx *ctx) {
     return d;
 }
 
-// Hit counts are rounded up to this granularity in the captured graphs (the
-// exact count is read on the device).
+// Hit counts are rounded up to a power of two (at least kHitBucket) in the
+// captured graphs -- the exact count is read on the device -- so a context
+// needs at most a few graphs whatever its batches hold.
 constexpr int64_t kHitBucket = 1 << 16;
+
+int64_t hit_bucket(int64_t hits) {
+    int64_t b = kHitBucket;
+    while (b < hits)
+        b <<= 1;
+    return b;
+}
 
 
 // The launch sequence of one batch (after the descriptor upload): reset,
@@ -339,6 +347,10 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
 
 }  // namespace
 
+void set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
+
+void ctx_grid(const hough_ctx *ctx, hough_grid *out) { *out = ctx->grid; }
+
 extern "C" {
 
 const char *hough_version(void) { return "hough-mi355x 0.2"; }
@@ -349,6 +361,7 @@ const char *hough_status_str(hough_status s) {
         case HOUGH_EINVAL: return "invalid argument";
         case HOUGH_ENOMEM: return "out of device memory";
         case HOUGH_EDEVICE: return "HIP runtime error";
+        case HOUGH_EBUSY: return "busy: the server's queue is full";
     }
     return "unknown status";
 }
@@ -422,6 +435,25 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         return HOUGH_EINVAL;   // a kappa row too long for a 32-row LDS tile
     }
     c->persistent_groups = cus * 2;
+    // Tuned shapes for this device, grid and size, if the cache has them.
+    if (const char *cache = tune_cache_path(o.tune_cache)) {
+        TuneEntry key;
+        key.device = device_tag(c->device);
+        key.n_d0 = grid->n_d0;
+        key.n_phi = grid->n_phi;
+        key.n_kappa = grid->n_kappa;
+        key.acc = grid->acc_type;
+        key.hits_log2 = tune_hits_log2(o.max_hits);
+        for (int which = 0; which < 2; ++which) {
+            key.which = which;
+            TuneEntry e;
+            if (!tune_lookup(cache, key, &e))
+                continue;
+            const VoteShape s{e.rows, e.threads, which == 1 ? 1 : e.split};
+            if (vote_shape_supported(s, u16, g.row_dwords))
+                (which == 0 ? c->shape_single : c->shape_batch) = s;
+        }
+    }
     c->cull_ok = grid->n_phi <= 32768 && table_is_bin_centres(grid);
 
     // Sort workspace sized for every first-pass layout: peak blocks, and
@@ -639,7 +671,7 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
     if (st != HOUGH_OK)
         return st;
 
-    const int64_t bucket = (hit_off[n_events] + kHitBucket - 1) / kHitBucket * kHitBucket;
+    const int64_t bucket = hit_bucket(hit_off[n_events]);
     GraphKey key{x, y, acc, cands, n_found, n_votes, threshold, bucket};
     hipGraphExec_t exec = nullptr;
     for (auto &ge : ctx->graphs)

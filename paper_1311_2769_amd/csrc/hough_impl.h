@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "hough.h"
 
@@ -171,4 +172,32 @@ hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_
                         int32_t threshold, const SortWork &w, hipStream_t stream);
 hipError_t launch_sort(const SortWork &w, int32_t n_events, hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// Launch-shape cache (tune.hip).
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    std::string device;   // architecture / compute units, e.g. "gfx950/256"
+    int n_d0 = 0, n_phi = 0, n_kappa = 0;
+    int acc = 0;          // hough_acc_type
+    int which = 0;        // 0 single event, 1 batch
+    int hits_log2 = 0;    // hit count rounded up to a power of two
+    int rows = 0, threads = 0, split = 1;
+    double ms = 0.0;
+};
+int tune_hits_log2(int64_t hits);
+bool tune_parse(const char *line, TuneEntry *e);
+std::string tune_format(const TuneEntry &e);
+// Entry of key (device, grid, acc, which) nearest to key.hits_log2; false if none.
+bool tune_lookup(const char *path, const TuneEntry &key, TuneEntry *out);
+bool tune_append(const char *path, const TuneEntry &e);
+std::string device_tag(int device);
+// The explicit path, else $HOUGH_TUNE_CACHE, else nullptr.
+const char *tune_cache_path(const char *opt);
+
 }  // namespace hough
+
+// The grid a context was created for (api.hip).
+void ctx_grid(const hough_ctx *ctx, hough_grid *out);
+// Set this thread's hough_last_error() text (api.hip).
+void set_last_error(const char *msg);
+

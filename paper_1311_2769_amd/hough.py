@@ -26,6 +26,9 @@ SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
     "hough_vote_batch",
     "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
+    "hough_autotune", "hough_tune_lookup",
+    "hough_server_create", "hough_server_destroy", "hough_server_clock", "hough_server_submit",
+    "hough_server_replay", "hough_server_poll", "hough_server_stats",
     "hough_selftest_divide", "hough_diag_rates", "hough_status_str", "hough_last_error", "hough_version",
 )
 
@@ -48,6 +51,21 @@ class _Grid(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("max_events", ctypes.c_int32), ("max_hits", ctypes.c_int64), ("tune_cache", ctypes.c_char_p)]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("n_grids", ctypes.c_int32), ("grids", ctypes.c_void_p), ("thresholds", ctypes.c_void_p),
+                ("lanes", ctypes.c_int32), ("batch_events", ctypes.c_void_p), ("batch_hits", ctypes.c_void_p),
+                ("event_candidates", ctypes.c_void_p), ("deadline_ms", ctypes.c_double),
+                ("queue_limit", ctypes.c_int32), ("keep_candidates", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+class _Served(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("grid", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("n_hits", ctypes.c_int32), ("n_found", ctypes.c_int32), ("n_stored", ctypes.c_int32),
+                ("batch_events", ctypes.c_int32), ("n_votes", ctypes.c_uint64), ("cand_offset", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 _LIB = None
@@ -86,6 +104,27 @@ def load(path: str = LIB_PATH):
     lib.hough_set_timing.argtypes = [vp, i32]
     lib.hough_get_timing.restype = i32
     lib.hough_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+    lib.hough_autotune.restype = i32
+    lib.hough_autotune.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp, i32, ctypes.c_char_p, vp,
+                                   ctypes.POINTER(ctypes.c_float)]
+    lib.hough_tune_lookup.restype = i32
+    lib.hough_tune_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_Grid), i32, i64,
+                                      ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32)]
+    lib.hough_server_create.restype = i32
+    lib.hough_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_ServerOpts)]
+    lib.hough_server_destroy.restype = None
+    lib.hough_server_destroy.argtypes = [vp]
+    lib.hough_server_clock.restype = ctypes.c_double
+    lib.hough_server_clock.argtypes = [vp]
+    lib.hough_server_submit.restype = i32
+    lib.hough_server_submit.argtypes = [vp, i64, i32, vp, vp, i32, ctypes.c_double]
+    lib.hough_server_replay.restype = i32
+    lib.hough_server_replay.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hough_server_poll.restype = i32
+    lib.hough_server_poll.argtypes = [vp, ctypes.POINTER(_Served), i32, vp, i64, ctypes.POINTER(i32), i32]
+    lib.hough_server_stats.restype = i32
+    lib.hough_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.hough_diag_rates.restype = i32
     lib.hough_diag_rates.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.hough_selftest_divide.restype = i32
@@ -258,6 +297,32 @@ class HoughContext:
     def set_launch(self, which, rows, threads, split=1):
         _check(self.lib.hough_set_launch(self.handle, which, rows, threads, split), "hough_set_launch")
 
+    def autotune(self, which, hit_off, x, y, threshold=1, *, acc=None, cand_off=None, cands=None,
+                 n_found=None, reps=5, cache=None, stream=None):
+        """Time the launch shapes of `which` (0 single-event vote of event 0,
+        1 whole batch) on these resident hits, keep the fastest on this
+        context and, with a cache path (or $HOUGH_TUNE_CACHE), record it.
+        Returns (rows, threads, split, best_ms)."""
+        hit_off = np.ascontiguousarray(hit_off, dtype=np.int64)
+        n_events = hit_off.shape[0] - 1
+        if which == 0 and acc is None:
+            acc = self.new_acc()
+        if which == 1:
+            if cand_off is None:
+                cand_off = np.arange(n_events + 1, dtype=np.int64) * self.spec.max_candidates()
+            cand_off = np.ascontiguousarray(cand_off, dtype=np.int64)
+            if cands is None:
+                cands = torch.empty((max(int(cand_off[-1]), 1), 2), dtype=torch.int32, device=self.device)
+            if n_found is None:
+                n_found = torch.empty(n_events, dtype=torch.int32, device=self.device)
+        best = ctypes.c_float()
+        _check(self.lib.hough_autotune(
+            self.handle, int(which), n_events, hit_off.ctypes.data_as(ctypes.c_void_p), _ptr(x), _ptr(y),
+            int(threshold), _ptr(acc), _ptr(cands),
+            None if cand_off is None else cand_off.ctypes.data_as(ctypes.c_void_p), _ptr(n_found), int(reps),
+            cache.encode() if cache else None, _stream_handle(stream), ctypes.byref(best)), "hough_autotune")
+        return self.get_launch(which) + (best.value,)
+
     def set_timing(self, enable: bool):
         _check(self.lib.hough_set_timing(self.handle, 1 if enable else 0), "hough_set_timing")
 
@@ -298,9 +363,136 @@ def cands_to_numpy(out, n_found, cap=None):
     return c[:, 0].astype(np.int64), c[:, 1].astype(np.int64), n
 
 
+def tune_lookup(cache, device, grid, which, hits):
+    """Host-only: the (rows, threads, split) a tuning cache records for this
+    device tag, grid and hit count, or None."""
+    lib = load()
+    spec = grid if isinstance(grid, GridSpec) else GridSpec.from_grid(grid)
+    g = _Grid(spec.n_d0, spec.n_phi, spec.n_kappa, spec.kappa_min, spec.kappa_scale, None, None, None,
+              ACC_U16 if spec.acc_u16 else ACC_I32)
+    found, r, t, sp = (ctypes.c_int32() for _ in range(4))
+    _check(lib.hough_tune_lookup(cache.encode() if cache else None, device.encode(), ctypes.byref(g), int(which),
+                                 int(hits), ctypes.byref(found), ctypes.byref(r), ctypes.byref(t),
+                                 ctypes.byref(sp)), "hough_tune_lookup")
+    return (r.value, t.value, sp.value) if found.value else None
+
+
 def diag_rates():
     """(LDS atomic adds/s, plain fp32 VALU ops/s) measured on the current device."""
     lib = load()
     a, v = ctypes.c_double(), ctypes.c_double()
     _check(lib.hough_diag_rates(ctypes.byref(a), ctypes.byref(v)), "hough_diag_rates")
     return a.value, v.value
+
+
+HOUGH_EBUSY = -4
+
+
+class Server:
+    """The served stream (a trigger-farm node) of libhough: continuous
+    batching over per-grid lanes with device-resident pools.  Events are host
+    fp32 arrays; results come back through poll()."""
+
+    def __init__(self, grids, thresholds, *, device="cuda", lanes=2, batch_events=None, batch_hits=None,
+                 event_candidates=None, deadline_ms=2.0, queue_limit=4096, keep_candidates=True,
+                 tune_cache=None):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.specs = [g if isinstance(g, GridSpec) else GridSpec.from_grid(g) for g in grids]
+        n = len(self.specs)
+        self._tables = []
+        structs = (_Grid * n)()
+        for i, sp in enumerate(self.specs):
+            c = torch.from_numpy(sp.cos_phi.copy()).to(self.device)
+            sn = torch.from_numpy(sp.sin_phi.copy()).to(self.device)
+            d0 = None if sp.d0 is None else torch.from_numpy(sp.d0.copy()).to(self.device)
+            self._tables.append((c, sn, d0))
+            structs[i] = _Grid(sp.n_d0, sp.n_phi, sp.n_kappa, sp.kappa_min, sp.kappa_scale, c.data_ptr(),
+                               sn.data_ptr(), None if d0 is None else d0.data_ptr(),
+                               ACC_U16 if sp.acc_u16 else ACC_I32)
+        self._keep = [structs]
+        thr = (ctypes.c_int32 * n)(*[int(t) for t in thresholds])
+
+        def arr(vals, ct):
+            if vals is None:
+                return None
+            a = (ct * n)(*[int(v) for v in vals])
+            self._keep.append(a)
+            return ctypes.cast(a, ctypes.c_void_p)
+
+        opts = _ServerOpts(n, ctypes.cast(structs, ctypes.c_void_p), ctypes.cast(thr, ctypes.c_void_p), int(lanes),
+                           arr(batch_events, ctypes.c_int32), arr(batch_hits, ctypes.c_int64),
+                           arr(event_candidates, ctypes.c_int64), float(deadline_ms), int(queue_limit),
+                           1 if keep_candidates else 0, tune_cache.encode() if tune_cache else None)
+        self._keep.append(thr)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.hough_server_create(ctypes.byref(h), ctypes.byref(opts)), "hough_server_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.hough_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self):
+        return self.lib.hough_server_clock(self.handle)
+
+    def submit(self, tag, grid, x, y, t_submit=-1.0):
+        """Hand over one event (host arrays).  False when the queue is full."""
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        st = self.lib.hough_server_submit(self.handle, int(tag), int(grid), x.ctypes.data_as(ctypes.c_void_p),
+                                          y.ctypes.data_as(ctypes.c_void_p), int(x.size), float(t_submit))
+        if st == HOUGH_EBUSY:
+            return False
+        _check(st, "hough_server_submit")
+        return True
+
+    def replay(self, arrival_s, grid, hit_off, x, y):
+        """Open-loop replay (blocks until every event is submitted; poll from
+        another thread meanwhile).  Returns the submit status of each event."""
+        arrival_s = np.ascontiguousarray(arrival_s, np.float64)
+        grid = np.ascontiguousarray(grid, np.int32)
+        hit_off = np.ascontiguousarray(hit_off, np.int64)
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        n = arrival_s.size
+        status = np.zeros(n, np.int32)
+        vp = ctypes.c_void_p
+        _check(self.lib.hough_server_replay(self.handle, n, arrival_s.ctypes.data_as(vp), grid.ctypes.data_as(vp),
+                                            hit_off.ctypes.data_as(vp), x.ctypes.data_as(vp),
+                                            y.ctypes.data_as(vp), status.ctypes.data_as(vp)),
+               "hough_server_replay")
+        return status
+
+    def poll(self, max_out=4096, cand_cap=1 << 22, wait_ms=0):
+        """Finished events: a list of dicts (tag, grid, status, n_hits,
+        n_found, n_votes, batch_events, t_submit, t_launch, t_done and the
+        candidates as an int32 [n, 2] array of (votes, cell))."""
+        out = (_Served * max_out)()
+        buf = np.empty((max(cand_cap, 1), 2), np.int32)
+        n = ctypes.c_int32()
+        st = self.lib.hough_server_poll(self.handle, out, max_out, buf.ctypes.data_as(ctypes.c_void_p),
+                                        int(cand_cap), ctypes.byref(n), int(wait_ms))
+        res = []
+        for k in range(n.value):
+            r = out[k]
+            res.append({"tag": r.tag, "grid": r.grid, "status": r.status, "n_hits": r.n_hits,
+                        "n_found": r.n_found, "n_votes": r.n_votes, "batch_events": r.batch_events,
+                        "t_submit": r.t_submit, "t_launch": r.t_launch, "t_done": r.t_done,
+                        "cands": buf[r.cand_offset:r.cand_offset + r.n_stored].copy()})
+        _check(st, "hough_server_poll")
+        return res
+
+    def stats(self):
+        p, r, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(self.lib.hough_server_stats(self.handle, ctypes.byref(p), ctypes.byref(r), ctypes.byref(b)),
+               "hough_server_stats")
+        return {"pending": p.value, "refused": r.value, "busy_lanes": b.value}

@@ -484,3 +484,32 @@ def test_throughput_probes_report_plausible_rates():
     assert 0 < lds <= cus * 64 * 2.6e9
     assert 0 < valu <= cus * 64 * 2.6e9
     print(f"[probe] lds {lds / 1e12:.2f} T/s, valu {valu / 1e12:.2f} T/s on {cus} CUs", flush=True)
+
+
+def test_autotuner_picks_a_shape_records_it_and_changes_no_result(tmp_path):
+    b = synth.gen_batch(4, 6)
+    g = synth.GRID_2D
+    dev = _dev()
+    x, y = _t(b.x), _t(b.y)
+    cache = str(tmp_path / "tune.jsonl")
+    base = _batch_results(hough.HoughContext(g, max_events=6, max_hits=b.n_hits), b, 7)
+    ctx = hough.HoughContext(g, max_events=6, max_hits=b.n_hits)
+    rows, threads, split, ms = ctx.autotune(1, b.hit_off, x, y, 7, reps=2, cache=cache)
+    assert ms > 0 and split == 1 and (rows, threads) in {(r, t) for r in (32, 64) for t in (256, 512, 1024)}
+    tuned = _batch_results(ctx, b, 7)
+    for e in range(6):
+        assert tuned[e][:2] == base[e][:2]
+        np.testing.assert_array_equal(tuned[e][3], base[e][3])
+    # single-event vote of event 0
+    acc = ctx.new_acc()
+    r0, t0, s0, ms0 = ctx.autotune(0, b.hit_off[:2], x, y, acc=acc, reps=2, cache=cache)
+    ev = b.events[0]
+    ra, rnv, _, _, _ = oracle.find(ev.x, ev.y, g, 7)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(hough.acc_to_numpy(acc, ctx.spec).reshape(-1), ra.reshape(-1))
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 2
+    # a new context created with the cache starts from the tuned shapes
+    fresh = hough.HoughContext(g, max_events=6, max_hits=b.n_hits, tune_cache=cache)
+    assert fresh.get_launch(1) == (rows, threads, 1)
+    assert fresh.get_launch(0) == (r0, t0, s0)
