@@ -55,6 +55,7 @@ def parse_args():
     ap.add_argument("--serve-rates", default="1000,5000,20000",
                     help="offered rates (events/s) of the served stream; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="offered seconds of arrivals per rate")
+    ap.add_argument("--serve-max-events", type=int, default=20000, help="cap on arrivals per rate")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -187,8 +188,13 @@ def served_stream(args, hough, synth, batch, log_fn):
     rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
     if not rates:
         return None
-    pool2 = batch.events
-    pool3 = [synth.gen_config_event(3, i) for i in range(32)]
+    pool = list(batch.events) + [synth.gen_config_event(3, i) for i in range(32)]
+    n2 = batch.n_events
+    pool_grid = np.array([0] * n2 + [1] * (len(pool) - n2), np.int32)
+    pool_off = np.zeros(len(pool) + 1, np.int64)
+    pool_off[1:] = np.cumsum([ev.n_hits for ev in pool])
+    pool_x = np.concatenate([ev.x for ev in pool])
+    pool_y = np.concatenate([ev.y for ev in pool])
     grids = [synth.CONFIGS[4].grid, synth.CONFIGS[3].grid]
     thr = [synth.CONFIGS[4].threshold, synth.CONFIGS[3].threshold]
     srv = hough.Server(grids, thr, lanes=2, batch_events=[64, 8], batch_hits=[1 << 22, 1 << 19], deadline_ms=2.0,
@@ -196,19 +202,17 @@ def served_stream(args, hough, synth, batch, log_fn):
     out = []
     try:
         for rate in rates:
-            n = max(200, int(rate * args.serve_seconds))
+            n = max(200, min(int(rate * args.serve_seconds), args.serve_max_events))
             rng = np.random.default_rng(np.random.SeedSequence([synth.BASE_SEED + 5, int(rate)]))
             kind = (rng.uniform(size=n) < 0.2).astype(np.int32)
-            pick = [pool3[rng.integers(len(pool3))] if k else pool2[rng.integers(len(pool2))] for k in kind]
-            hit_off = np.zeros(n + 1, np.int64)
-            hit_off[1:] = np.cumsum([ev.n_hits for ev in pick])
-            x = np.concatenate([ev.x for ev in pick])
-            y = np.concatenate([ev.y for ev in pick])
+            pick = np.where(kind == 1, n2 + rng.integers(0, len(pool) - n2, size=n),
+                            rng.integers(0, n2, size=n)).astype(np.int32)
             arrivals = synth.poisson_arrivals(rate, n, stream=1)
             log_fn(f"served stream: {n} events at {rate:.0f}/s")
             status = {}
             import threading
-            th = threading.Thread(target=lambda: status.update(s=srv.replay(arrivals, kind, hit_off, x, y)))
+            th = threading.Thread(target=lambda: status.update(
+                s=srv.replay(arrivals, pick, pool_grid, pool_off, pool_x, pool_y)))
             t_start = srv.clock()
             th.start()
             res = []

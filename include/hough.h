@@ -253,13 +253,16 @@ double hough_server_clock(const hough_server *server);
  * than 65535 for a uint16 grid); EBUSY: the pending queue is full. */
 hough_status hough_server_submit(hough_server *server, int64_t tag, int32_t grid, const float *x,
                                  const float *y, int32_t n_hits, double t_submit);
-/* Open-loop replay: submit event i (hits [hit_off[i], hit_off[i+1]) of x, y,
- * grid grid[i]) at arrival_s[i] seconds after the call starts, stamping that
- * scheduled time as its submit time, and write each submit's status to
- * status[i].  Returns when all are submitted; poll concurrently. */
+/* Open-loop replay from a pool of events: arrival i is pool event pick[i]
+ * (hits [pool_hit_off[k], pool_hit_off[k+1]) of pool_x, pool_y, grid
+ * pool_grid[k]), submitted with tag i at arrival_s[i] seconds after the call
+ * starts and stamped with that scheduled time.  Writes each submit's status
+ * to status[i] and returns when all are submitted; poll concurrently.
+ * EINVAL: null arrays, arrivals out of order, pick outside the pool. */
 hough_status hough_server_replay(hough_server *server, int32_t n, const double *arrival_s,
-                                 const int32_t *grid, const int64_t *hit_off, const float *x,
-                                 const float *y, int32_t *status);
+                                 const int32_t *pick, int32_t n_pool, const int32_t *pool_grid,
+                                 const int64_t *pool_hit_off, const float *pool_x, const float *pool_y,
+                                 int32_t *status);
 /* Take up to max_out finished events (waiting up to wait_ms for the first),
  * copying their candidates back to back into cand_buf[cand_cap].  EDEVICE
  * if a batch failed on the device (the failed events carry that status). */

@@ -106,8 +106,11 @@ struct VoteInputs {
 };
 
 // A tile range packs first | count << 16 (tile indices of one d0 slice,
-// cyclic); count 0 is empty and kAllTiles covers every tile.
-constexpr uint32_t kAllTiles = 0xffffu << 16;
+// cyclic; 15-bit count); count 0 is empty and kAllTiles covers every tile.
+// Bit 31 of a hit's second range is kFastDiv: every phi0 row of that (hit,
+// d0 slice) has its 3D quotient operands in the range of vote_math.h.
+constexpr uint32_t kAllTiles = 0x7fffu << 16;
+constexpr uint32_t kFastDiv = 1u << 31;
 
 // Tile geometry of a vote launch: tile t of a slice owns phi0 rows
 // [t*stride, min((t+1)*stride, n_phi)); with halo it also votes the row

@@ -451,12 +451,17 @@ hough_status hough_server_submit(hough_server *s, int64_t tag, int32_t grid, con
     return HOUGH_OK;
 }
 
-hough_status hough_server_replay(hough_server *s, int32_t n, const double *arrival_s, const int32_t *grid,
-                                 const int64_t *hit_off, const float *x, const float *y, int32_t *status) {
-    if (!s || n < 0 || (n > 0 && (!arrival_s || !grid || !hit_off || !status)))
+hough_status hough_server_replay(hough_server *s, int32_t n, const double *arrival_s, const int32_t *pick,
+                                 int32_t n_pool, const int32_t *pool_grid, const int64_t *pool_hit_off,
+                                 const float *pool_x, const float *pool_y, int32_t *status) {
+    if (!s || n < 0 || n_pool < 0 || (n > 0 && (!arrival_s || !pick || !status || n_pool == 0)) ||
+        (n_pool > 0 && (!pool_grid || !pool_hit_off)))
         return HOUGH_EINVAL;
+    for (int32_t k = 0; k < n_pool; ++k)
+        if (pool_hit_off[k + 1] < pool_hit_off[k])
+            return HOUGH_EINVAL;
     for (int32_t i = 0; i < n; ++i)
-        if (hit_off[i + 1] < hit_off[i] || (i > 0 && arrival_s[i] < arrival_s[i - 1]))
+        if (pick[i] < 0 || pick[i] >= n_pool || (i > 0 && arrival_s[i] < arrival_s[i - 1]))
             return HOUGH_EINVAL;
     const double base = s->now();
     for (int32_t i = 0; i < n; ++i) {
@@ -466,8 +471,10 @@ hough_status hough_server_replay(hough_server *s, int32_t n, const double *arriv
             if (left > 2e-4)
                 std::this_thread::sleep_for(std::chrono::duration<double>(left - 1e-4));
         }
-        const int64_t a = hit_off[i];
-        status[i] = hough_server_submit(s, i, grid[i], x + a, y + a, static_cast<int32_t>(hit_off[i + 1] - a), due);
+        const int32_t k = pick[i];
+        const int64_t a = pool_hit_off[k];
+        status[i] = hough_server_submit(s, i, pool_grid[k], pool_x + a, pool_y + a,
+                                        static_cast<int32_t>(pool_hit_off[k + 1] - a), due);
     }
     return HOUGH_OK;
 }

@@ -120,7 +120,7 @@ def load(path: str = LIB_PATH):
     lib.hough_server_submit.restype = i32
     lib.hough_server_submit.argtypes = [vp, i64, i32, vp, vp, i32, ctypes.c_double]
     lib.hough_server_replay.restype = i32
-    lib.hough_server_replay.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hough_server_replay.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hough_server_poll.restype = i32
     lib.hough_server_poll.argtypes = [vp, ctypes.POINTER(_Served), i32, vp, i64, ctypes.POINTER(i32), i32]
     lib.hough_server_stats.restype = i32
@@ -455,20 +455,23 @@ class Server:
         _check(st, "hough_server_submit")
         return True
 
-    def replay(self, arrival_s, grid, hit_off, x, y):
-        """Open-loop replay (blocks until every event is submitted; poll from
-        another thread meanwhile).  Returns the submit status of each event."""
+    def replay(self, arrival_s, pick, pool_grid, pool_hit_off, pool_x, pool_y):
+        """Open-loop replay: arrival i is pool event pick[i], submitted at
+        arrival_s[i] seconds from now (blocks until every event is submitted;
+        poll from another thread meanwhile).  Returns each submit's status."""
         arrival_s = np.ascontiguousarray(arrival_s, np.float64)
-        grid = np.ascontiguousarray(grid, np.int32)
-        hit_off = np.ascontiguousarray(hit_off, np.int64)
-        x = np.ascontiguousarray(x, np.float32)
-        y = np.ascontiguousarray(y, np.float32)
+        pick = np.ascontiguousarray(pick, np.int32)
+        pool_grid = np.ascontiguousarray(pool_grid, np.int32)
+        pool_hit_off = np.ascontiguousarray(pool_hit_off, np.int64)
+        pool_x = np.ascontiguousarray(pool_x, np.float32)
+        pool_y = np.ascontiguousarray(pool_y, np.float32)
         n = arrival_s.size
         status = np.zeros(n, np.int32)
         vp = ctypes.c_void_p
-        _check(self.lib.hough_server_replay(self.handle, n, arrival_s.ctypes.data_as(vp), grid.ctypes.data_as(vp),
-                                            hit_off.ctypes.data_as(vp), x.ctypes.data_as(vp),
-                                            y.ctypes.data_as(vp), status.ctypes.data_as(vp)),
+        _check(self.lib.hough_server_replay(self.handle, n, arrival_s.ctypes.data_as(vp), pick.ctypes.data_as(vp),
+                                            pool_grid.size, pool_grid.ctypes.data_as(vp),
+                                            pool_hit_off.ctypes.data_as(vp), pool_x.ctypes.data_as(vp),
+                                            pool_y.ctypes.data_as(vp), status.ctypes.data_as(vp)),
                "hough_server_replay")
         return status
 

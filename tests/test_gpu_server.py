@@ -66,7 +66,8 @@ def test_results_match_each_event_alone():
     grid_idx = np.array([g for g, _ in evs], np.int32)
     arrivals = np.arange(len(evs)) * 20e-6               # a burst: later events find the lanes busy
     status = {}
-    t = threading.Thread(target=lambda: status.update(s=srv.replay(arrivals, grid_idx, hit_off, x, y)))
+    pick = np.arange(len(evs), dtype=np.int32)
+    t = threading.Thread(target=lambda: status.update(s=srv.replay(arrivals, pick, grid_idx, hit_off, x, y)))
     t.start()
     got = _collect(srv, len(evs))
     t.join()
