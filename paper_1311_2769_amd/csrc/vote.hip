@@ -580,16 +580,21 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
 // the fp32 curvature kappa_c lies within K(1 + 2^-19).  kappa_c rounds
 // num_c / den_c, where num_c = 2(u_c - d) to 2^-24 relative, u_c = y c - x s to
 // r 2^-20 absolute (fp32 products, and fp32 cos/sin of the bin centre), and
-// den_c equals r^2 - 2 d u_c + d^2 to 2^-21 (r + |d|)^2 absolute.  When
-// |r - |d|| >= 0.1 (r + |d|) the exact denominator is at least (r - |d|)^2, so
-// kappa(u_c) = 2(u_c - d)/(r^2 + d^2 - 2 d u_c) is within relative 5e-5 of
-// kappa_c and |kappa(u_c)| <= K' = K (1 + 1e-3).  kappa(u) is monotone in u, so
-// u_c lies between u(-K') and u(K') with u(k) = (k (r^2 + d^2) + 2 d) /
-// (2 (1 + k d)), and r sin(phi_h - phi0) lies in that interval widened by
-// r 1e-5.  The two phi0 arcs that satisfy this, widened by 1e-5 rad and one
-// row on each side, hold every row that can receive the hit's votes.  Hits
-// that are not finite, sit within 1e-15 of the origin or beyond 1e15, or fail
-// the conditioning test get the full circle.  The phi0 table must hold the bin
+// den_c equals r^2 - 2 d u_c + d^2 to 2^-21 (r + |d|)^2 absolute.  The exact
+// denominator |h - P0|^2 is at least (r - |d|)^2, so when
+// |r - |d|| >= 0.03 (r + |d|) its relative error is at most 2^-21 / 0.03^2 <
+// 5.3e-4, kappa(u_c) = 2(u_c - d)/(r^2 + d^2 - 2 d u_c) is within relative
+// 5.4e-4 of kappa_c, and |kappa(u_c)| <= K' = K (1 + 1e-3).  On |u| <= r the
+// function kappa(u) is continuous and monotone (its derivative has the sign
+// of r^2 - d^2; its pole (r^2 + d^2) / (2 d) lies at least 0.0018 r beyond
+// |u| = r under the same condition), and its inverse
+// u(k) = (k (r^2 + d^2) + 2 d) / (2 (1 + k d)) is continuous on [-K', K']
+// when K' |d| < 1, so u_c lies between u(-K') and u(K') and r sin(phi_h -
+// phi0) lies in that interval widened by r 1e-5.  The two phi0 arcs that
+// satisfy this, widened by 1e-5 rad and one row on each side, hold every row
+// that can receive the hit's votes.  Hits that are not finite, sit within
+// 1e-15 of the origin or beyond 1e15, fail the conditioning test or have
+// K' |d| >= 1 get the full circle.  The phi0 table must hold the bin
 // centres (j + 1/2) 2 pi / n_phi (checked when the context is created;
 // otherwise no ranges are used).
 //
@@ -617,20 +622,21 @@ struct PrepArgs {
 };
 
 // 3D quotient range (every phi0 row of one hit and d0 slice): with a phi0
-// table of bin centres, r in [2^-10, 2^10], d = 0 or |d| in [2^-20, 2^10] and
-// |r - |d|| >= 0.1 (r + |d|):
-//   den = |h - P0|^2 up to fp32 rounding (relative 2^-21 of (r + |d|)^2) lies
-//   in [(r - |d|)^2, (r + |d|)^2], i.e. within [0.01 (r + |d|)^2 (1 - 2^-20),
-//   2^22 (1 + 2^-20)] subset of [2^-30, 2^30];
+// table of bin centres, r in [2^-8, 2^10], d = 0 or |d| in [2^-20, 2^10] and
+// |r - |d|| >= 0.03 (r + |d|):
+//   den = |h - P0|^2 up to fp32 rounding (2^-21 (r + |d|)^2 absolute) lies in
+//   [(r - |d|)^2, (r + |d|)^2] widened by that, i.e. within
+//   [0.0009 (r + |d|)^2 (1 - 2^-10), 2^22 (1 + 2^-20)], a subset of
+//   [2^-27, 2^23] and so of [2^-30, 2^30];
 //   num = 2 (u - d) with |u| <= r (1 + 1e-6): |num| <= 2^12; a nonzero u - d
 //   is at least 2^-45 (d = 0: u >= 2^-54 as in the 2D case; |d| >= 2^-20:
 //   either |u| < |d| / 2 and |u - d| > 2^-21, or both magnitudes are at
 //   least 2^-21 and the difference is a nonzero multiple of 2^-45), so every
 //   nonzero numerator is in [2^-60, 2^30]; a zero numerator moves no vote.
 __device__ __forceinline__ bool fast_div_3d(double r, double d, double ad) {
-    const bool r_ok = r >= 0x1.0p-10 && r <= 0x1.0p10;
+    const bool r_ok = r >= 0x1.0p-8 && r <= 0x1.0p10;
     const bool d_ok = d == 0.0 || (ad >= 0x1.0p-20 && ad <= 0x1.0p10);
-    return r_ok && d_ok && fabs(r - ad) >= 0.1 * (r + ad);
+    return r_ok && d_ok && fabs(r - ad) >= 0.03 * (r + ad);
 }
 
 __device__ __forceinline__ uint32_t pack_arc(double phi_a, double phi_b, int n) {
@@ -704,7 +710,7 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     const double ad = fabs(d);
     const double K = p.kabs * (1.0 + 1e-3);
     const bool finite_in = isfinite(X) && isfinite(Y) && isfinite(d);
-    if (finite_in && r > 1e-15 && r < 1e15 && ad < 1e15 && fabs(r - ad) >= 0.1 * (r + ad) && K * ad < 0.5) {
+    if (finite_in && r > 1e-15 && r < 1e15 && ad < 1e15 && fabs(r - ad) >= 0.03 * (r + ad) && K * ad < 1.0) {
         const double rr = r * r + d * d;
         const double u1 = (-K * rr + 2.0 * d) / (2.0 * (1.0 - K * d));
         const double u2 = (K * rr + 2.0 * d) / (2.0 * (1.0 + K * d));

@@ -10,12 +10,12 @@ shared cos/sin tables of the phi0 bin centres) that both sides take as inputs.
 from .grids import Grid, make_grid, GRID_2D_SMALL, GRID_2D, GRID_3D
 from .events import (
     Event, Batch, gen_config_event, gen_batch, gen_tracks_event,
-    track_hits, LAYERS_CM, BASE_SEED,
+    track_hits, LAYERS_CM, BASE_SEED, pack_events, poisson_arrivals,
 )
 from .configs import CONFIGS, WorkloadConfig
 
 __all__ = [
     "Grid", "make_grid", "GRID_2D_SMALL", "GRID_2D", "GRID_3D",
     "Event", "Batch", "gen_config_event", "gen_batch", "gen_tracks_event",
-    "track_hits", "LAYERS_CM", "BASE_SEED", "CONFIGS", "WorkloadConfig",
+    "track_hits", "LAYERS_CM", "BASE_SEED", "pack_events", "poisson_arrivals", "CONFIGS", "WorkloadConfig",
 ]

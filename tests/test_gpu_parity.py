@@ -366,8 +366,12 @@ def test_culling_stress_displaced_hits_near_the_d0_circles():
     rng = np.random.default_rng(77)
     grid = synth.GRID_3D
     d0 = np.abs(grid.d0.astype(np.float64))
+    # a band around |r - |d0|| = 0.03 (r + |d0|), the conditioning limit of the arcs, and radii
+    # around 2^-8, the lower limit of the 3D hoist-free division
+    band = rng.choice(d0, 1000) * (1 + rng.choice([-1.0, 1.0], 1000) * rng.uniform(0.05, 0.15, 1000))
     r = np.concatenate([rng.choice(d0, 3000) + rng.normal(0, 0.05, 3000),
                         rng.uniform(0.01, 120, 3000), rng.choice(d0, 500) * (1 + rng.normal(0, 1e-4, 500)),
+                        band, 2.0 ** rng.uniform(-9, -7, 200),
                         10.0 ** rng.uniform(-20, 20, 200)])
     phi = np.concatenate([rng.uniform(0, 2 * math.pi, r.size - 400),
                           (np.arange(400) % 512 + rng.choice([0.0, 0.5], 400)) * 2 * math.pi / 512])
