@@ -429,8 +429,8 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->shape_single = VoteShape{32, 512, u16 ? 1 : 4};
     c->shape_batch = VoteShape{32, 512, 1};
-    if (!vote_shape_supported(c->shape_single, u16, g.row_dwords) ||
-        !vote_shape_supported(c->shape_batch, u16, g.row_dwords)) {
+    if (!vote_shape_supported(c->shape_single, u16, g.n_kappa) ||
+        !vote_shape_supported(c->shape_batch, u16, g.n_kappa)) {
         delete c;
         return HOUGH_EINVAL;   // a kappa row too long for a 32-row LDS tile
     }
@@ -450,7 +450,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
             if (!tune_lookup(cache, key, &e))
                 continue;
             const VoteShape s{e.rows, e.threads, which == 1 ? 1 : e.split};
-            if (vote_shape_supported(s, u16, g.row_dwords))
+            if (vote_shape_supported(s, u16, g.n_kappa))
                 (which == 0 ? c->shape_single : c->shape_batch) = s;
         }
     }
@@ -533,7 +533,7 @@ hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32
     VoteShape s{rows, threads, split};
     if (which == 1 && split != 1)
         return HOUGH_EINVAL;
-    if (!vote_shape_supported(s, ctx->u16, ctx->g.row_dwords))
+    if (!vote_shape_supported(s, ctx->u16, ctx->g.n_kappa))
         return HOUGH_EINVAL;
     if (which == 1 && std::max(batch_tiles_per_event(ctx, s, true), batch_tiles_per_event(ctx, s, false)) *
                               static_cast<int64_t>(ctx->max_events) > ctx->max_items)

@@ -131,8 +131,8 @@ struct VoteShape {
 // ---------------------------------------------------------------------------
 // Launchers (return hipSuccess or the first launch error).
 // ---------------------------------------------------------------------------
-bool vote_shape_supported(const VoteShape &s, bool u16, int32_t row_dwords);
-size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords);
+bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa);
+size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa);
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
 TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused);
 int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);

@@ -1,5 +1,5 @@
-// Device helpers shared by the peak search kernels: the asymmetric local
-// maximum test and ordered compaction of survivors into a staging list.
+// Device helpers shared by the peak search kernels: wavefront reductions and
+// the publication of an ordered staging list for the candidate sort.
 #pragma once
 
 #include "hough_impl.h"
@@ -7,6 +7,17 @@
 namespace hough {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load and store of the wavefront; the kernels here
+// exchange data between threads through LDS alone (their global results are
+// read by later kernels), so waiting for global memory at each barrier would
+// only expose its latency -- and cancel the loads issued ahead of time.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Number of set bits of `mask` in lanes below this one.
 __device__ __forceinline__ int rank_below(uint64_t mask) {
@@ -35,7 +46,7 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-// Shared-memory scratch of one compaction pass.
+// Shared-memory scratch of one ordered compaction.
 template <int NT>
 struct CompactScratch {
     uint32_t hist[kDigits];
@@ -43,76 +54,6 @@ struct CompactScratch {
     uint32_t red_min[NT / 64];
     uint32_t red_max[NT / 64];
 };
-
-// Local-maximum test of a 2D cell (phi0 row r of an LDS tile whose rows
-// r-1 and r+1 are present, kappa bin k): negative offsets need v > w,
-// positive ones v >= w; kappa neighbours outside [0, nk) are ignored.
-__device__ __forceinline__ bool is_peak_2d(const int32_t *row, int stride, int nk, int k, int32_t v) {
-    const int32_t *up = row - stride;
-    const int32_t *dn = row + stride;
-    bool ok = true;
-    if (k > 0)
-        ok = ok && v > up[k - 1] && v >= dn[k - 1] && v > row[k - 1];
-    ok = ok && v > up[k] && v >= dn[k];
-    if (k + 1 < nk)
-        ok = ok && v > up[k + 1] && v >= dn[k + 1] && v >= row[k + 1];
-    return ok;
-}
-
-// Scan `n_cells` cells of an LDS tile in order, keep those `test` accepts and
-// append them, in that order, to `out`.  Also accumulates the lowest sort
-// digit histogram in sc.hist (zeroed by the caller) and the smallest and
-// largest sort key.  Returns the number kept (uniform across the block).
-// `test(idx, &v, &cell)` evaluates cell idx.
-template <int NT, typename Test>
-__device__ int compact_ordered(int n_cells, Test test, Cand *out, CompactScratch<NT> &sc, uint32_t *kmin_out,
-                               uint32_t *kmax_out) {
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6;
-    uint32_t kmin = 0xffffffffu, kmax = 0u;
-    int base = 0;
-    for (int r0 = 0; r0 < n_cells; r0 += NT) {
-        const int idx = r0 + tid;
-        int32_t v = 0, cell = 0;
-        const bool keep = idx < n_cells && test(idx, &v, &cell);
-        const uint64_t m = __ballot(keep);
-        if (lane_id() == 0)
-            sc.wave_cnt[wave] = __popcll(m);
-        __syncthreads();
-        int pre = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < NT / 64; ++w) {
-            const int c = sc.wave_cnt[w];
-            pre += w < wave ? c : 0;
-            total += c;
-        }
-        if (keep) {
-            out[base + pre + rank_below(m)] = Cand{v, cell};
-            const uint32_t key = sort_key(v);
-            atomicAdd(&sc.hist[key & 0xffu], 1u);
-            kmin = min(kmin, key);
-            kmax = max(kmax, key);
-        }
-        base += total;
-        __syncthreads();
-    }
-    kmin = wave_min_u32(kmin);
-    kmax = wave_max_u32(kmax);
-    if (lane_id() == 0) {
-        sc.red_min[wave] = kmin;
-        sc.red_max[wave] = kmax;
-    }
-    __syncthreads();
-    uint32_t mn = 0xffffffffu, mx = 0u;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) {
-        mn = min(mn, sc.red_min[w]);
-        mx = max(mx, sc.red_max[w]);
-    }
-    *kmin_out = mn;
-    *kmax_out = mx;
-    return base;
-}
 
 // Publish one staging list (block): its count, its key range and its digit
 // histogram.  With one list per first-pass chunk the histogram row is

@@ -1,11 +1,18 @@
 // Peak search and candidate ordering for gfx950.
 //
 // Section 3: after voting, local maxima of the parameter space are the track
-// candidates.  A block stages kPeakRows phi0 rows of one d0 slice plus a
-// one-row halo on each side (phi0 wraps) -- and the same rows of the
-// neighbouring d0 slices in 3D -- in LDS, applies the threshold and the
-// asymmetric 3x3(x3) local-maximum test of hough.h, and compacts the
-// survivors in ascending cell order into its own staging list.
+// candidates.  A block owns a band of kPeakRows phi0 rows and walks
+// kPeakSlices consecutive d0 slices of it, keeping three slices (d0 l-1, l,
+// l+1) of the band plus a one-row halo on each side (phi0 wraps) in an LDS
+// ring, so each slice is read from memory about (kPeakSlices + 2) /
+// kPeakSlices times.  uint16 cells are unpacked to int32; every staged row is
+// padded with one INT_MIN column on each side, which stands for the kappa
+// neighbours outside the grid (never larger than a cell).  For slice l the
+// asymmetric 3x3(x3) test of hough.h is branch-free: the cell must exceed the
+// maximum of its lexicographically earlier neighbours -- the whole slice
+// below, the row above, the cell to its left -- and reach the maximum of the
+// later ones.  Survivors of each (slice, band) are compacted in ascending
+// cell order into that pair's staging list.
 //
 // Ordering (votes descending, then cell ascending) is a stable LSD radix sort
 // on key = 0x7fffffff - votes with 8-bit digits.  Staging lists are already
@@ -17,6 +24,8 @@
 // digits in which an event's keys actually differ are sorted; the last pass
 // writes straight into the caller's candidate array, clipped at its
 // capacity.
+#include <climits>
+
 #include "hough_impl.h"
 #include "peak_tile.h"
 
@@ -32,96 +41,243 @@ struct PeakArgs {
 };
 
 constexpr int kPeakThreads = 256;
+constexpr int kPeakWaves = kPeakThreads / 64;
 constexpr int kHaloRows = kPeakRows + 2;
+constexpr int kPeakSlices = 8;
+constexpr int kPrefetch = 8;                              // dwords per thread per load round
+constexpr int kMaxSegs = 64;                              // (row, kappa chunk) pairs per band
 
-// LDS layout: [slice 0..2][row 0..kHaloRows-1][n_kappa] int32 (2D: one slice).
+__device__ __forceinline__ int32_t max3i(int32_t a, int32_t b, int32_t c) { return max(max(a, b), c); }
+
+struct PeakScratch {
+    uint32_t hist[kDigits];
+    int32_t seg_cnt[kMaxSegs][kPeakWaves];   // survivors per (row, kappa chunk) and wavefront
+    uint32_t red_min[kPeakWaves];
+    uint32_t red_max[kPeakWaves];
+};
+
+// LDS: a ring of 4 slices (2D: 1) x kHaloRows rows x (n_kappa + 2) int32.
+// The slice after next is loaded into registers while the current slice is
+// tested and stored into the ring afterwards, so its memory latency overlaps
+// the test.
 template <bool U16>
 __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
-    extern __shared__ int32_t tile[];
-    __shared__ CompactScratch<kPeakThreads> sc;
+    extern __shared__ int32_t ring[];
+    __shared__ PeakScratch sc;
 
     const GridArgs &g = a.g;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int e = blockIdx.y;
-    const int b = blockIdx.x;
     if (a.w.n_events_dev && e >= *a.w.n_events_dev)
         return;
-    const int l = b / a.blocks_per_slice;
-    const int j0 = (b - l * a.blocks_per_slice) * kPeakRows;
+    const int bps = a.blocks_per_slice;
+    const int rb = blockIdx.x % bps;
+    const int l0 = (blockIdx.x / bps) * kPeakSlices;
+    const int l1 = min(g.n_d0, l0 + kPeakSlices);
+    const int j0 = rb * kPeakRows;
     const int rows_here = min(kPeakRows, g.n_phi - j0);
     const int nk = g.n_kappa;
-    const int slice_cells = kHaloRows * nk;
-    const bool has_lo = l > 0;
-    const bool has_hi = l + 1 < g.n_d0;
-    const bool three = g.n_d0 > 1;   // 2D grids stage only the middle slice
-
-    for (int i = tid; i < kDigits; i += kPeakThreads)
-        sc.hist[i] = 0u;
-
-    // Stage the rows j0-1 .. j0+rows_here of slices l-1, l, l+1.
+    const int W = nk + 2;
+    const int plane = kHaloRows * W;
+    const bool three = g.n_d0 > 1;
+    const int rd = g.row_dwords;
+    const int n_words = (rows_here + 2) * rd;             // staged dwords of one slice
     const uint32_t *acc_e = a.acc + static_cast<int64_t>(e) * g.acc_dwords;
-    for (int sl = 0; sl < 3; ++sl) {
-        const int ll = l + sl - 1;
-        if (ll < 0 || ll >= g.n_d0)
-            continue;
-        int32_t *base = tile + (three ? sl : 0) * slice_cells;
-        const int n_words = (rows_here + 2) * g.row_dwords;
-        for (int i = tid; i < n_words; i += kPeakThreads) {
-            const int rr = i / g.row_dwords;
-            const int wd = i - rr * g.row_dwords;
-            int j = j0 + rr - 1;
-            if (j < 0)
-                j += g.n_phi;
-            if (j >= g.n_phi)
-                j -= g.n_phi;
-            const uint32_t v = acc_e[(static_cast<int64_t>(ll) * g.n_phi + j) * g.row_dwords + wd];
-            int32_t *dst = base + rr * nk;
-            if constexpr (U16) {
-                dst[2 * wd] = static_cast<int32_t>(v & 0xffffu);
-                dst[2 * wd + 1] = static_cast<int32_t>(v >> 16);
-            } else {
-                dst[wd] = static_cast<int32_t>(v);
-            }
-        }
-    }
-    __syncthreads();
+    auto slot = [&](int ll) { return ring + (three ? (ll & 3) : 0) * plane; };
 
-    const int32_t *mid = tile + (three ? slice_cells : 0);
-    const int32_t thr = a.threshold;
-    const int64_t cell_base = static_cast<int64_t>(l) * g.n_phi * nk;
-    auto test = [&](int idx, int32_t *v, int32_t *cell) {
-        const int jr = idx / nk;
-        const int k = idx - jr * nk;
-        const int32_t *row = mid + (jr + 1) * nk;
-        const int32_t val = row[k];
-        if (val < thr || !is_peak_2d(row, nk, nk, k, val))
-            return false;
-        // d0 neighbours: the slice below is entirely "earlier" (v > w), the
-        // slice above entirely "later" (v >= w).
-        for (int od = -1; od <= 1; od += 2) {
-            if ((od < 0 && !has_lo) || (od > 0 && !has_hi))
-                continue;
-            const int32_t *sl = tile + (od + 1) * slice_cells + jr * nk;   // row jr-1 of that slice
-            for (int op = 0; op < 3; ++op) {
-                const int32_t *rw = sl + op * nk;
-                for (int ok = -1; ok <= 1; ++ok) {
-                    const int kk = k + ok;
-                    if (kk < 0 || kk >= nk)
-                        continue;
-                    const int32_t w = rw[kk];
-                    if (od < 0 ? !(val > w) : !(val >= w))
-                        return false;
+    // Staged dword i = tid + kPeakThreads*m of a band is (row rr, dword wd)
+    // with i = rr*rd + wd; positions advance without dividing.
+    const int dr = kPeakThreads / rd;
+    const int dw = kPeakThreads - dr * rd;
+    const int rr_first = tid / rd;
+    const int wd_first = tid - rr_first * rd;
+    auto advance = [&](int &rr, int &wd) {
+        wd += dw;
+        rr += dr;
+        if (wd >= rd) {
+            wd -= rd;
+            ++rr;
+        }
+    };
+    // One load round of kPrefetch dwords per thread, from position (rr, wd).
+    uint32_t pv[kPrefetch];
+    auto issue = [&](int ll, int rr, int wd) {
+        const uint32_t *src = acc_e + static_cast<int64_t>(ll) * g.n_phi * rd;
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            pv[q] = 0u;
+            if (rr < rows_here + 2) {
+                int j = j0 + rr - 1;
+                j += j < 0 ? g.n_phi : 0;
+                j -= j >= g.n_phi ? g.n_phi : 0;
+                pv[q] = src[static_cast<int64_t>(j) * rd + wd];
+            }
+            advance(rr, wd);
+        }
+    };
+    auto commit = [&](int ll, int rr, int wd) {
+        int32_t *p = slot(ll);
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            if (rr < rows_here + 2) {
+                int32_t *dst = p + rr * W + 1;
+                if constexpr (U16) {
+                    dst[2 * wd] = static_cast<int32_t>(pv[q] & 0xffffu);
+                    dst[2 * wd + 1] = static_cast<int32_t>(pv[q] >> 16);
+                } else {
+                    dst[wd] = static_cast<int32_t>(pv[q]);
                 }
             }
+            advance(rr, wd);
         }
-        *v = val;
-        *cell = static_cast<int32_t>(cell_base + static_cast<int64_t>(j0 + jr) * nk + k);
-        return true;
     };
-    Cand *out = a.w.s0.stage + (static_cast<int64_t>(e) * a.w.s0.n_blocks0 + b) * a.w.s0.cap0;
-    uint32_t kmin, kmax;
-    const int count = compact_ordered<kPeakThreads>(rows_here * nk, test, out, sc, &kmin, &kmax);
-    publish_block<kPeakThreads>(a.w, e, b, count, sc, kmin, kmax);
+    auto pad = [&](int ll) {
+        int32_t *p = slot(ll);
+        for (int rr = tid; rr < kHaloRows; rr += kPeakThreads) {
+            p[rr * W] = INT_MIN;
+            p[rr * W + nk + 1] = INT_MIN;
+        }
+    };
+    auto load = [&](int ll) {
+        int rr = rr_first, wd = wd_first;
+        for (int c0 = 0; c0 < n_words; c0 += kPrefetch * kPeakThreads) {
+            issue(ll, rr, wd);
+            commit(ll, rr, wd);
+            for (int q = 0; q < kPrefetch; ++q)
+                advance(rr, wd);
+        }
+        pad(ll);
+    };
+    // The slice after next can stay in registers across the test when it fits one round.
+    const bool overlap = three && n_words <= kPrefetch * kPeakThreads;
+
+    if (three && l0 > 0)
+        load(l0 - 1);
+    load(l0);
+    if (three && l0 + 1 < g.n_d0)
+        load(l0 + 1);
+    const int32_t thr = a.threshold;
+    // rows_here * ceil(nk / kPeakThreads) segments <= kMaxSegs (checked on the host)
+    for (int l = l0; l < l1; ++l) {
+        const bool next2 = three && l + 2 < g.n_d0 && l + 2 <= l1;   // needed by this block's last step
+        if (next2 && overlap)
+            issue(l + 2, rr_first, wd_first);
+        for (int i = tid; i < kDigits; i += kPeakThreads)
+            sc.hist[i] = 0u;
+        lds_barrier();
+        const bool has_lo = three && l > 0;
+        const bool has_hi = three && l + 1 < g.n_d0;
+        const int32_t *mid = slot(l);
+        const int32_t *lo = slot(has_lo ? l - 1 : l);
+        const int32_t *hi = slot(has_hi ? l + 1 : l);
+
+        // Test of cell (row jr of the band, kappa k); cells in ascending
+        // order are the segments (jr, kappa chunk) in turn.
+        auto test = [&](int jr, int k, int32_t *v_out) {
+            if (k >= nk)
+                return false;
+            const int at = (jr + 1) * W + k + 1;
+            const int32_t *m = mid + at;
+            const int32_t v = m[0];
+            int32_t before = max(max3i(m[-W - 1], m[-W], m[-W + 1]), m[-1]);
+            int32_t after = max(max3i(m[W - 1], m[W], m[W + 1]), m[1]);
+            if (has_lo) {
+                const int32_t *q = lo + at;
+                before = max(before, max3i(max3i(q[-W - 1], q[-W], q[-W + 1]), max3i(q[-1], q[0], q[1]),
+                                           max3i(q[W - 1], q[W], q[W + 1])));
+            }
+            if (has_hi) {
+                const int32_t *q = hi + at;
+                after = max(after, max3i(max3i(q[-W - 1], q[-W], q[-W + 1]), max3i(q[-1], q[0], q[1]),
+                                         max3i(q[W - 1], q[W], q[W + 1])));
+            }
+            *v_out = v;
+            return v >= thr && v > before && v >= after;
+        };
+        // pass 1: survivors per segment and wavefront
+        uint64_t keep_bits = 0;
+        for (int jr = 0, s = 0; jr < rows_here; ++jr) {
+            for (int k0 = 0; k0 < nk; k0 += kPeakThreads, ++s) {
+                int32_t v;
+                const bool keep = test(jr, k0 + tid, &v);
+                keep_bits |= static_cast<uint64_t>(keep) << s;
+                const uint64_t msk = __ballot(keep);
+                if (lane == 0)
+                    sc.seg_cnt[s][wave] = __popcll(msk);
+            }
+        }
+        // Slice l+2 goes into the slot slice l-2 held (read last in the
+        // previous step); stored now, before this step's candidate stores
+        // queue behind its loads.
+        if (next2) {
+            if (overlap) {
+                commit(l + 2, rr_first, wd_first);
+                pad(l + 2);
+            } else {
+                load(l + 2);
+            }
+        }
+        lds_barrier();
+        // pass 2: write survivors in cell order
+        Cand *out = a.w.s0.stage + (static_cast<int64_t>(e) * a.w.s0.n_blocks0 + l * bps + rb) * a.w.s0.cap0;
+        const int64_t cell_base = (static_cast<int64_t>(l) * g.n_phi + j0) * nk;
+        uint32_t kmin = 0xffffffffu, kmax = 0u;
+        int base = 0;
+        for (int jr = 0, s = 0; jr < rows_here; ++jr) {
+            for (int k0 = 0; k0 < nk; k0 += kPeakThreads, ++s) {
+                int pre = 0, total = 0;
+#pragma unroll
+                for (int w2 = 0; w2 < kPeakWaves; ++w2) {
+                    const int c = sc.seg_cnt[s][w2];
+                    pre += w2 < wave ? c : 0;
+                    total += c;
+                }
+                const bool keep = (keep_bits >> s) & 1u;
+                const uint64_t msk = __ballot(keep);
+                if (keep) {
+                    const int k = k0 + tid;
+                    const int32_t v = mid[(jr + 1) * W + k + 1];
+                    out[base + pre + rank_below(msk)] = Cand{v, static_cast<int32_t>(cell_base + jr * nk + k)};
+                    const uint32_t key = sort_key(v);
+                    atomicAdd(&sc.hist[key & 0xffu], 1u);
+                    kmin = min(kmin, key);
+                    kmax = max(kmax, key);
+                }
+                base += total;
+            }
+        }
+        kmin = wave_min_u32(kmin);
+        kmax = wave_max_u32(kmax);
+        if (lane == 0) {
+            sc.red_min[wave] = kmin;
+            sc.red_max[wave] = kmax;
+        }
+        lds_barrier();
+        uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+        for (int w2 = 0; w2 < kPeakWaves; ++w2) {
+            mn = min(mn, sc.red_min[w2]);
+            mx = max(mx, sc.red_max[w2]);
+        }
+        if (tid == 0) {
+            a.w.s0.cnt0[static_cast<int64_t>(e) * a.w.s0.n_blocks0 + l * bps + rb] = base;
+            if (base > 0) {
+                atomicMin(&a.w.state[e].key_min, mn);
+                atomicMax(&a.w.state[e].key_max, mx);
+            }
+        }
+        const int chunk = (l * bps + rb) / a.w.s0.cb;
+        uint32_t *hrow = a.w.hist + (static_cast<int64_t>(e) * a.w.hist_chunks + chunk) * kDigits;
+        for (int i = tid; i < kDigits; i += kPeakThreads) {
+            if (a.w.s0.cb == 1)
+                hrow[i] = sc.hist[i];
+            else if (sc.hist[i])
+                atomicAdd(&hrow[i], sc.hist[i]);
+        }
+        lds_barrier();   // the histogram and the ring are reused
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -293,7 +449,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int p
         for (int b0 = 0; b0 < count; b0 += kSortThreads) {
             for (int i = t; i < kWaves * kDigits; i += kSortThreads)
                 (&wcnt[0][0])[i] = 0u;
-            __syncthreads();
+            lds_barrier();
             const int i = b0 + t;
             const bool valid = i < count;
             Cand cd{0, 0};
@@ -312,7 +468,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int p
             const int rank = rank_below(peers);
             if (valid && rank == 0)
                 wcnt[wave][digit] = static_cast<uint32_t>(__popcll(peers));
-            __syncthreads();
+            lds_barrier();
             if (valid) {
                 uint32_t pre = run[digit];
                 for (int w2 = 0; w2 < wave; ++w2)
@@ -321,14 +477,14 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int p
                 if (pos < limit)
                     dst[pos] = cd;
             }
-            __syncthreads();
+            lds_barrier();
             for (int dd = t; dd < kDigits; dd += kSortThreads) {
                 uint32_t add = 0;
                 for (int w2 = 0; w2 < kWaves; ++w2)
                     add += wcnt[w2][dd];
                 run[dd] += add;
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
 }
@@ -365,13 +521,16 @@ hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_
         if (e != hipSuccess)
             return e;
     }
-    const size_t lds = static_cast<size_t>(g.n_d0 > 1 ? 3 : 1) * kHaloRows * g.n_kappa * sizeof(int32_t);
+    if (kPeakRows * ((g.n_kappa + kPeakThreads - 1) / kPeakThreads) > kMaxSegs)
+        return hipErrorInvalidValue;   // more kappa bins than one band's survivor bookkeeping holds
+    const size_t lds = static_cast<size_t>(g.n_d0 > 1 ? 4 : 1) * kHaloRows * (g.n_kappa + 2) * sizeof(int32_t);
     const void *fn = u16 ? reinterpret_cast<const void *>(peak_kernel<true>)
                          : reinterpret_cast<const void *>(peak_kernel<false>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess)
         return e;
-    dim3 grid(static_cast<unsigned>(peak_blocks_per_event(g)), static_cast<unsigned>(n_events));
+    const int32_t slice_chunks = (g.n_d0 + kPeakSlices - 1) / kPeakSlices;
+    dim3 grid(static_cast<unsigned>(a.blocks_per_slice * slice_chunks), static_cast<unsigned>(n_events));
     if (u16)
         hipLaunchKernelGGL(peak_kernel<true>, grid, dim3(kPeakThreads), lds, stream, a);
     else

@@ -50,10 +50,10 @@
 // no-ops when every operand is in the range of vote_math.h (rcp, two
 // refinement FMAs, then quot_apply): 8 instead of 11 operations.
 //
-// uint16 accumulators are packed two cells per dword in LDS (even kappa bin in
-// the low half): a vote adds 1 or 0x10000 with one 32-bit LDS atomic.  The low
-// half can never carry into the high half because a cell receives at most one
-// vote per hit and u16 events hold at most 65535 hits.
+// uint16 accumulators count in int32 LDS cells like int32 ones and are packed
+// two cells per dword (even kappa bin in the low half) when the tile is
+// flushed; counts fit because a cell receives at most one vote per hit and
+// u16 events hold at most 65535 hits.
 //
 // Fused peak search (2D int32 batches).  Tiles then overlap by two rows: a
 // tile votes S interior rows plus one halo row on each side, finds the local
@@ -121,11 +121,6 @@ __device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <bool U16>
-__device__ __forceinline__ uint32_t cell_sum(uint32_t v) {
-    return U16 ? (v & 0xffffu) + (v >> 16) : v;
-}
-
 // Vote hits [h_begin, h_end) of event e into tile t of d0 slice l, then either
 // flush it (unfused) or search its interior rows for peaks (fused).
 template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
@@ -153,8 +148,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         len = min(ROWS, n_phi - first);
     }
 
-    // row_dwords kappa columns plus one spare column that takes the no-vote adds
-    for (int i = tid; i < (g.row_dwords + 1) * stride; i += NT)
+    // n_kappa columns plus one spare column that takes the no-vote adds
+    const int nk_cols = g.n_kappa;
+    for (int i = tid; i < (nk_cols + 1) * stride; i += NT)
         lds[i] = 0u;
     if constexpr (FUSED) {
         for (int i = tid; i < kDigits; i += NT)
@@ -194,7 +190,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const float dd = d * d;
     const float kmin = g.kappa_min;
     const float kscale = g.kappa_scale;
-    const int trash = U16 ? 2 * g.row_dwords : g.row_dwords;   // bin index of the spare column
+    const int trash = nk_cols;                                 // bin index of the spare column
     // ... held in a VGPR so that the select below is a single v_cndmask
     int trash_v;
     asm volatile("v_mov_b32 %0, %1" : "=v"(trash_v) : "s"(trash));
@@ -218,22 +214,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // instead, which changes no vote) or when a nonzero difference (at least
     // 2^-149) times kappa_scale rounds to zero, impossible for kappa_scale >= 1.
     const uint32_t lim_bits = __float_as_uint(nkf);
-    auto bin = [&](const float4 &h, int i, bool valid, auto fast, auto bits) -> int {
-        const float u = h.y * c[i] - h.x * s[i];
-        float kappa;
-        if constexpr (D3) {
-            const float num = 2.0f * (u - d);
-            const float den = (h.z - d2 * u) + dd;
-            if constexpr (decltype(fast)::value)
-                kappa = quot_apply(num, den, quot_recip(den));   // the operator's steps, scaling elided
-            else
-                kappa = num / den;
-        } else if constexpr (decltype(fast)::value) {
-            kappa = quot_apply(u, h.z, h.w);
-        } else {
-            kappa = (2.0f * u) / h.z;
-        }
-        const float kf = (kappa - kmin) * kscale;
+    auto bin_of = [&](float kf, int i, bool valid, auto bits) -> int {
         if constexpr (decltype(bits)::value) {
             const uint32_t b = valid ? __float_as_uint(kf) : 0xffffffffu;
             return static_cast<int>(__uint_as_float(min(b, lim_bits)));
@@ -242,12 +223,32 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             return ok ? static_cast<int>(kf) : trash_v;
         }
     };
-    auto vote = [&](int kk, int i) {
-        if constexpr (U16)
-            lds_add(&lds[(kk >> 1) * stride + rowoff[i]], 1u << ((kk & 1) << 4));
-        else
-            lds_add(&lds[kk * stride + rowoff[i]], 1u);
+    auto bin = [&](const float4 &h, int i, bool valid, auto fast, auto bits) -> int {
+        const float u = h.y * c[i] - h.x * s[i];
+        float kappa;
+        if constexpr (D3) {
+            const float den = (h.z - d2 * u) + dd;
+            if constexpr (decltype(fast)::value) {
+                // In range, 2(u - d) / den = 2 ((u - d) / den) exactly (scaling a
+                // normal number by 2 is exact, so the correctly rounded
+                // quotients agree), and kappa - kappa_min = fma(2, q, -kappa_min)
+                // with its one rounding (2q is exact).  The quotient runs the
+                // operator's own steps with operand scaling elided.
+                const float q = quot_apply(u - d, den, quot_recip(den));
+                const float kf = __builtin_fmaf(2.0f, q, -kmin) * kscale;
+                return bin_of(kf, i, valid, bits);
+            } else {
+                kappa = (2.0f * (u - d)) / den;
+            }
+        } else if constexpr (decltype(fast)::value) {
+            kappa = quot_apply(u, h.z, h.w);
+        } else {
+            kappa = (2.0f * u) / h.z;
+        }
+        const float kf = (kappa - kmin) * kscale;
+        return bin_of(kf, i, valid, bits);
     };
+    auto vote = [&](int kk, int i) { lds_add(&lds[kk * stride + rowoff[i]], 1u); };
     // Evaluate and vote two hits of this lane group (valid: the hit exists).
     auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast, auto bits) {
         int ka[RPT], kb[RPT];
@@ -324,7 +325,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     int carry = 0;                               // fast hits carried into this block
     float4 carry_v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // this thread's carried hit (tid < carry)
     for (int64_t b0 = h_begin; b0 < h_end; b0 += kHitBlock, parity ^= 1) {
-        __syncthreads();                         // the previous block is fully evaluated
+        lds_barrier();                         // the previous block is fully evaluated
         if (tid < carry)
             ts.hits[tid] = carry_v;
 #pragma unroll
@@ -346,7 +347,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             else if (keep)
                 ts.hits[SLOW_END - 1 - (bs + rank_below(ms))] = ph[q];
         }
-        __syncthreads();
+        lds_barrier();
         const int n_fast = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][0]);   // with the carried hits
         const int n_slow = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][1]);
         const bool last = b0 + kHitBlock >= h_end;
@@ -362,7 +363,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         sweep(SLOW_END - n_slow, SLOW_END, std::false_type{});
         carry = carry_next;
     }
-    __syncthreads();
+    lds_barrier();
 
     const int rd = g.row_dwords;
     unsigned long long votes = 0;
@@ -439,7 +440,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         // exclusive offsets in cell order: (row, segment) pairs row-major
         const int order = rr * SEGS + seg;
         ts.cnt[order] = mine;
-        __syncthreads();
+        lds_barrier();
         const int v_in = ts.cnt[tid];
         int incl = v_in;
 #pragma unroll
@@ -450,7 +451,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         }
         if (lane == 63)
             ts.wave_tot[wave] = incl;
-        __syncthreads();
+        lds_barrier();
         int wpre = 0, total = 0;
 #pragma unroll
         for (int wv = 0; wv < NW; ++wv) {
@@ -458,9 +459,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             wpre += wv < wave ? c0 : 0;
             total += c0;
         }
-        __syncthreads();
+        lds_barrier();
         ts.cnt[tid] = wpre + incl - v_in;
-        __syncthreads();
+        lds_barrier();
         // pass 2: write in cell order, histogram the first sort digit
         Cand *out = a.w.s0.stage + (static_cast<int64_t>(e) * a.w.s0.n_blocks0 + t) * a.w.s0.cap0;
         uint32_t kmin_key = 0xffffffffu, kmax_key = 0u;
@@ -491,7 +492,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             ts.sc.red_min[wave] = kmin_key;
             ts.sc.red_max[wave] = kmax_key;
         }
-        __syncthreads();
+        lds_barrier();
         uint32_t mn = 0xffffffffu, mx = 0u;
 #pragma unroll
         for (int wv = 0; wv < NW; ++wv) {
@@ -506,8 +507,16 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         if (rr < len) {
             uint32_t *dst = acc_event + (static_cast<int64_t>(l) * n_phi + first + rr) * rd;
             for (int wd = w_lo; wd < w_hi; ++wd) {
-                const uint32_t v = lds[wd * stride + rr];
-                votes += cell_sum<U16>(v);
+                uint32_t v;
+                if constexpr (U16) {
+                    const uint32_t lo = lds[(2 * wd) * stride + rr];
+                    const uint32_t hi = lds[(2 * wd + 1) * stride + rr];
+                    votes += lo + hi;
+                    v = lo | (hi << 16);
+                } else {
+                    v = lds[wd * stride + rr];
+                    votes += v;
+                }
                 if (!atomic_flush)
                     dst[wd] = v;
                 else if (v)
@@ -519,7 +528,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         const unsigned long long wsum = wave_sum_u64(votes);
         if (lane == 0)
             ts.red[wave] = wsum;
-        __syncthreads();
+        lds_barrier();
         if (tid == 0) {
             unsigned long long tot = 0;
             for (int wv = 0; wv < NW; ++wv)
@@ -528,7 +537,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
                 atomicAdd(n_votes, tot);
         }
     }
-    __syncthreads();   // the LDS tile and scratch are reused by the next item
+    lds_barrier();   // the LDS tile and scratch are reused by the next item
 }
 
 template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
@@ -554,9 +563,9 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
         if (a.work_counter) {
             if (threadIdx.x == 0)
                 ts.next_item = atomicAdd(a.work_counter, 1);
-            __syncthreads();
+            lds_barrier();
             it = ts.next_item;
-            __syncthreads();
+            lds_barrier();
         }
         if (it >= n_items)
             return;
@@ -616,6 +625,7 @@ struct PrepArgs {
     int64_t range_stride;
     const float *d0;            // nullptr for 2D
     int32_t n_phi;
+    int32_t n_d0;
     int32_t tiles, tile_stride, halo;
     int32_t div_fast;
     double kabs;
@@ -682,15 +692,17 @@ __device__ __forceinline__ uint32_t tile_range(uint32_t arc, const PrepArgs &p) 
     return static_cast<uint32_t>(lo) | (static_cast<uint32_t>(cnt) << 16);
 }
 
+constexpr int kPrepSlices = 8;   // d0 slices per hit_prep thread (per-hit terms computed once)
+
 __global__ void hit_prep_kernel(PrepArgs p) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int l = blockIdx.y;
     const int64_t n = p.n_hits_dev ? *p.n_hits_dev : p.n_hits;
     if (i >= n)
         return;
     const float xf = p.x[i];
     const float yf = p.y[i];
-    if (l == 0) {
+    const int l_begin = blockIdx.y * kPrepSlices;
+    if (l_begin == 0) {
         const float r2 = xf * xf + yf * yf;
         float4 rec = make_float4(xf, yf, r2, 0.0f);
         if (p.div_fast && p.d0 == nullptr) {
@@ -704,32 +716,35 @@ __global__ void hit_prep_kernel(PrepArgs p) {
         return;
     const double X = xf;
     const double Y = yf;
-    uint2 out = make_uint2(kAllTiles, 0u);
     const double r = sqrt(X * X + Y * Y);
-    const double d = p.d0 ? static_cast<double>(p.d0[l]) : 0.0;
-    const double ad = fabs(d);
+    const double ph = atan2(Y, X);
     const double K = p.kabs * (1.0 + 1e-3);
-    const bool finite_in = isfinite(X) && isfinite(Y) && isfinite(d);
-    if (finite_in && r > 1e-15 && r < 1e15 && ad < 1e15 && fabs(r - ad) >= 0.03 * (r + ad) && K * ad < 1.0) {
-        const double rr = r * r + d * d;
-        const double u1 = (-K * rr + 2.0 * d) / (2.0 * (1.0 - K * d));
-        const double u2 = (K * rr + 2.0 * d) / (2.0 * (1.0 + K * d));
-        const double slo = (fmin(u1, u2) - r * 1e-5) / r;
-        const double shi = (fmax(u1, u2) + r * 1e-5) / r;
-        if (slo > 1.0 || shi < -1.0) {
-            out = make_uint2(0u, 0u);
-        } else if (!(slo <= -1.0 && shi >= 1.0)) {
-            const double alo = asin(fmax(slo, -1.0));
-            const double ahi = asin(fmin(shi, 1.0));
-            const double ph = atan2(Y, X);
-            const double pi = 3.141592653589793;
-            out = make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi), p),
-                             tile_range(pack_arc(ph - pi + alo, ph - pi + ahi, p.n_phi), p));
+    const int l_end = min(l_begin + kPrepSlices, p.d0 ? p.n_d0 : 1);
+    for (int l = l_begin; l < l_end; ++l) {
+        uint2 out = make_uint2(kAllTiles, 0u);
+        const double d = p.d0 ? static_cast<double>(p.d0[l]) : 0.0;
+        const double ad = fabs(d);
+        const bool finite_in = isfinite(X) && isfinite(Y) && isfinite(d);
+        if (finite_in && r > 1e-15 && r < 1e15 && ad < 1e15 && fabs(r - ad) >= 0.03 * (r + ad) && K * ad < 1.0) {
+            const double rr = r * r + d * d;
+            const double u1 = (-K * rr + 2.0 * d) / (2.0 * (1.0 - K * d));
+            const double u2 = (K * rr + 2.0 * d) / (2.0 * (1.0 + K * d));
+            const double slo = (fmin(u1, u2) - r * 1e-5) / r;
+            const double shi = (fmax(u1, u2) + r * 1e-5) / r;
+            if (slo > 1.0 || shi < -1.0) {
+                out = make_uint2(0u, 0u);
+            } else if (!(slo <= -1.0 && shi >= 1.0)) {
+                const double alo = asin(fmax(slo, -1.0));
+                const double ahi = asin(fmin(shi, 1.0));
+                const double pi = 3.141592653589793;
+                out = make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi), p),
+                                 tile_range(pack_arc(ph - pi + alo, ph - pi + ahi, p.n_phi), p));
+            }
+            if (p.d0 && p.div_fast && fast_div_3d(r, d, ad))
+                out.y |= kFastDiv;
         }
-        if (p.d0 && p.div_fast && fast_div_3d(r, d, ad))
-            out.y |= kFastDiv;
+        p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = out;
     }
-    p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = out;
 }
 
 __global__ void prep_kernel(EventState *state, int32_t n_events, unsigned long long *n_votes) {
@@ -799,7 +814,7 @@ hipError_t launch_vote(const VoteArgs &a, bool u16, bool fused, const VoteShape 
     VoteFn fn = pick_vote(u16, a.g.d0 != nullptr, fused, s.rows, s.threads);
     if (!fn)
         return hipErrorInvalidValue;
-    const size_t lds = vote_lds_bytes(s, a.g.row_dwords);
+    const size_t lds = vote_lds_bytes(s, a.g.n_kappa);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess)
@@ -832,18 +847,18 @@ TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused) {
     return tg;
 }
 
-size_t vote_lds_bytes(const VoteShape &s, int32_t row_dwords) {
-    // kappa-major tile: row_dwords columns of `rows` dwords, plus the spare column
-    return (static_cast<size_t>(row_dwords) + 1) * static_cast<size_t>(s.rows) * sizeof(uint32_t);
+size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa) {
+    // kappa-major int32 tile: n_kappa columns of `rows` dwords, plus the spare column
+    return (static_cast<size_t>(n_kappa) + 1) * static_cast<size_t>(s.rows) * sizeof(uint32_t);
 }
 
-bool vote_shape_supported(const VoteShape &s, bool u16, int32_t row_dwords) {
+bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa) {
     if (!pick_vote(u16, false, false, s.rows, s.threads))
         return false;
     if (s.split < 1 || s.split > 64)
         return false;
     // dynamic tile + static scratch (staged hits, compaction and reductions)
-    return vote_lds_bytes(s, row_dwords) + sizeof(TileScratch<1024>) <= 160u * 1024u;
+    return vote_lds_bytes(s, n_kappa) + sizeof(TileScratch<1024>) <= 160u * 1024u;
 }
 
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused) {
@@ -871,6 +886,7 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     p.range_stride = range_stride;
     p.d0 = g.d0;
     p.n_phi = g.n_phi;
+    p.n_d0 = g.n_d0;
     p.tiles = tg.tiles;
     p.tile_stride = tg.stride;
     p.halo = tg.halo;
@@ -879,7 +895,8 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     const double kmax = static_cast<double>(g.kappa_min) + static_cast<double>(g.n_kappa) / g.kappa_scale;
     p.kabs = fmax(fabs(kmin), fabs(kmax));
     const unsigned blocks = static_cast<unsigned>((n_hits + 255) / 256);
-    hipLaunchKernelGGL(hit_prep_kernel, dim3(blocks, ranges ? g.n_d0 : 1), dim3(256), 0, stream, p);
+    const unsigned groups = ranges ? static_cast<unsigned>((g.n_d0 + kPrepSlices - 1) / kPrepSlices) : 1u;
+    hipLaunchKernelGGL(hit_prep_kernel, dim3(blocks, groups), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 

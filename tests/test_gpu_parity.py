@@ -166,7 +166,7 @@ def test_odd_small_grids(dims):
         try:
             ctx.set_launch(0, rows, threads, split)
         except hough.HoughError:
-            assert rows * (ctx.spec.n_kappa // (2 if ctx.spec.acc_u16 else 1)) * 4 > 120000
+            assert rows * (ctx.spec.n_kappa + 1) * 4 > 120000
             continue
         _assert_same(_gpu_find(ctx, ev.x, ev.y, 2), ref, f"grid {dims} rows {rows}")
 
