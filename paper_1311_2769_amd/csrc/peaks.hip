@@ -51,12 +51,13 @@ __device__ __forceinline__ int32_t max3i(int32_t a, int32_t b, int32_t c) { retu
 
 struct PeakScratch {
     uint32_t hist[kDigits];
-    int32_t seg_cnt[kMaxSegs][kPeakWaves];   // survivors per (row, kappa chunk) and wavefront
+    uint64_t seg_mask[kMaxSegs][kPeakWaves];   // survivor lanes per (row, kappa chunk) and wavefront
     uint32_t red_min[kPeakWaves];
     uint32_t red_max[kPeakWaves];
 };
 
-// LDS: a ring of 4 slices (2D: 1) x kHaloRows rows x (n_kappa + 2) int32.
+// LDS: a ring of 4 slices (2D: 1) x kHaloRows rows x (n_kappa + 2) int32,
+// then two dwords per thread that take the stores of positions past the band.
 // The slice after next is loaded into registers while the current slice is
 // tested and stored into the ring afterwards, so its memory latency overlaps
 // the test.
@@ -88,7 +89,9 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
     auto slot = [&](int ll) { return ring + (three ? (ll & 3) : 0) * plane; };
 
     // Staged dword i = tid + kPeakThreads*m of a band is (row rr, dword wd)
-    // with i = rr*rd + wd; positions advance without dividing.
+    // with i = rr*rd + wd.  For the first load round (all of it when the band
+    // fits one round) each thread's global and LDS offsets are the same for
+    // every slice, so they are computed once.
     const int dr = kPeakThreads / rd;
     const int dw = kPeakThreads - dr * rd;
     const int rr_first = tid / rd;
@@ -101,36 +104,43 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
             ++rr;
         }
     };
-    // One load round of kPrefetch dwords per thread, from position (rr, wd).
-    uint32_t pv[kPrefetch];
-    auto issue = [&](int ll, int rr, int wd) {
-        const uint32_t *src = acc_e + static_cast<int64_t>(ll) * g.n_phi * rd;
+    // Positions past the band load dword 0 of the slice and store into this
+    // thread's own two dwords after the ring, so the rounds need no branches.
+    int32_t goff[kPrefetch];   // dword offset inside a slice
+    int32_t loff[kPrefetch];   // LDS offset of the first staged cell, from the ring base
+    const int slot_words = (three ? 4 : 1) * plane;
+    {
+        int rr = rr_first, wd = wd_first;
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q) {
-            pv[q] = 0u;
-            if (rr < rows_here + 2) {
-                int j = j0 + rr - 1;
-                j += j < 0 ? g.n_phi : 0;
-                j -= j >= g.n_phi ? g.n_phi : 0;
-                pv[q] = src[static_cast<int64_t>(j) * rd + wd];
-            }
+            int j = j0 + rr - 1;
+            j += j < 0 ? g.n_phi : 0;
+            j -= j >= g.n_phi ? g.n_phi : 0;
+            const bool in = rr < rows_here + 2;
+            goff[q] = in ? j * rd + wd : 0;
+            loff[q] = in ? rr * W + 1 + (U16 ? 2 * wd : wd) : -1;
             advance(rr, wd);
         }
+    }
+    int32_t *const dummy = ring + slot_words + 2 * tid;
+    uint32_t pv[kPrefetch];
+    auto issue_first = [&](int ll) {
+        const uint32_t *src = acc_e + static_cast<int64_t>(ll) * g.n_phi * rd;
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q)
+            pv[q] = src[goff[q]];
     };
-    auto commit = [&](int ll, int rr, int wd) {
+    auto commit_first = [&](int ll) {
         int32_t *p = slot(ll);
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q) {
-            if (rr < rows_here + 2) {
-                int32_t *dst = p + rr * W + 1;
-                if constexpr (U16) {
-                    dst[2 * wd] = static_cast<int32_t>(pv[q] & 0xffffu);
-                    dst[2 * wd + 1] = static_cast<int32_t>(pv[q] >> 16);
-                } else {
-                    dst[wd] = static_cast<int32_t>(pv[q]);
-                }
+            int32_t *d = loff[q] >= 0 ? p + loff[q] : dummy;
+            if constexpr (U16) {
+                d[0] = static_cast<int32_t>(pv[q] & 0xffffu);
+                d[1] = static_cast<int32_t>(pv[q] >> 16);
+            } else {
+                d[0] = static_cast<int32_t>(pv[q]);
             }
-            advance(rr, wd);
         }
     };
     auto pad = [&](int ll) {
@@ -141,12 +151,31 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
         }
     };
     auto load = [&](int ll) {
+        issue_first(ll);
+        commit_first(ll);
+        // rounds after the first
         int rr = rr_first, wd = wd_first;
-        for (int c0 = 0; c0 < n_words; c0 += kPrefetch * kPeakThreads) {
-            issue(ll, rr, wd);
-            commit(ll, rr, wd);
-            for (int q = 0; q < kPrefetch; ++q)
+        for (int q = 0; q < kPrefetch; ++q)
+            advance(rr, wd);
+        for (int c0 = kPrefetch * kPeakThreads; c0 < n_words; c0 += kPrefetch * kPeakThreads) {
+            const uint32_t *src = acc_e + static_cast<int64_t>(ll) * g.n_phi * rd;
+            int32_t *p = slot(ll);
+            for (int q = 0; q < kPrefetch; ++q) {
+                if (rr < rows_here + 2) {
+                    int j = j0 + rr - 1;
+                    j += j < 0 ? g.n_phi : 0;
+                    j -= j >= g.n_phi ? g.n_phi : 0;
+                    const uint32_t v = src[static_cast<int64_t>(j) * rd + wd];
+                    int32_t *dst = p + rr * W + 1;
+                    if constexpr (U16) {
+                        dst[2 * wd] = static_cast<int32_t>(v & 0xffffu);
+                        dst[2 * wd + 1] = static_cast<int32_t>(v >> 16);
+                    } else {
+                        dst[wd] = static_cast<int32_t>(v);
+                    }
+                }
                 advance(rr, wd);
+            }
         }
         pad(ll);
     };
@@ -163,7 +192,7 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
     for (int l = l0; l < l1; ++l) {
         const bool next2 = three && l + 2 < g.n_d0 && l + 2 <= l1;   // needed by this block's last step
         if (next2 && overlap)
-            issue(l + 2, rr_first, wd_first);
+            issue_first(l + 2);
         for (int i = tid; i < kDigits; i += kPeakThreads)
             sc.hist[i] = 0u;
         lds_barrier();
@@ -196,16 +225,25 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
             *v_out = v;
             return v >= thr && v > before && v >= after;
         };
-        // pass 1: survivors per segment and wavefront
-        uint64_t keep_bits = 0;
-        for (int jr = 0, s = 0; jr < rows_here; ++jr) {
-            for (int k0 = 0; k0 < nk; k0 += kPeakThreads, ++s) {
-                int32_t v;
-                const bool keep = test(jr, k0 + tid, &v);
-                keep_bits |= static_cast<uint64_t>(keep) << s;
-                const uint64_t msk = __ballot(keep);
-                if (lane == 0)
-                    sc.seg_cnt[s][wave] = __popcll(msk);
+        // pass 1: survivor lanes per segment and wavefront (every lane writes
+        // the same mask).  One kappa chunk per row (n_kappa <= the block
+        // size) unrolls over the rows, so their LDS reads overlap.
+        if (nk <= kPeakThreads) {
+#pragma unroll
+            for (int jr = 0; jr < kPeakRows; ++jr) {
+                if (jr < rows_here) {
+                    int32_t v;
+                    const bool keep = test(jr, tid, &v);
+                    sc.seg_mask[jr][wave] = __ballot(keep);
+                }
+            }
+        } else {
+            for (int jr = 0, s = 0; jr < rows_here; ++jr) {
+                for (int k0 = 0; k0 < nk; k0 += kPeakThreads, ++s) {
+                    int32_t v;
+                    const bool keep = test(jr, k0 + tid, &v);
+                    sc.seg_mask[s][wave] = __ballot(keep);
+                }
             }
         }
         // Slice l+2 goes into the slot slice l-2 held (read last in the
@@ -213,7 +251,7 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
         // queue behind its loads.
         if (next2) {
             if (overlap) {
-                commit(l + 2, rr_first, wd_first);
+                commit_first(l + 2);
                 pad(l + 2);
             } else {
                 load(l + 2);
@@ -230,12 +268,12 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
                 int pre = 0, total = 0;
 #pragma unroll
                 for (int w2 = 0; w2 < kPeakWaves; ++w2) {
-                    const int c = sc.seg_cnt[s][w2];
+                    const int c = __popcll(sc.seg_mask[s][w2]);
                     pre += w2 < wave ? c : 0;
                     total += c;
                 }
-                const bool keep = (keep_bits >> s) & 1u;
-                const uint64_t msk = __ballot(keep);
+                const uint64_t msk = sc.seg_mask[s][wave];
+                const bool keep = (msk >> lane) & 1u;
                 if (keep) {
                     const int k = k0 + tid;
                     const int32_t v = mid[(jr + 1) * W + k + 1];
@@ -523,7 +561,8 @@ hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_
     }
     if (kPeakRows * ((g.n_kappa + kPeakThreads - 1) / kPeakThreads) > kMaxSegs)
         return hipErrorInvalidValue;   // more kappa bins than one band's survivor bookkeeping holds
-    const size_t lds = static_cast<size_t>(g.n_d0 > 1 ? 4 : 1) * kHaloRows * (g.n_kappa + 2) * sizeof(int32_t);
+    const size_t lds = (static_cast<size_t>(g.n_d0 > 1 ? 4 : 1) * kHaloRows * (g.n_kappa + 2) + 2 * kPeakThreads) *
+                       sizeof(int32_t);
     const void *fn = u16 ? reinterpret_cast<const void *>(peak_kernel<true>)
                          : reinterpret_cast<const void *>(peak_kernel<false>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
