@@ -280,6 +280,14 @@ hough_status hough_server_stats(hough_server *server, int64_t *pending, int64_t 
  * 16-byte device buffer; synchronous. */
 hough_status hough_selftest_divide(int64_t n, uint64_t seed, uint64_t *mismatches, uint64_t *checked);
 
+/* Diagnostic: on the current device, the largest absolute error (radians) of
+ * the fp32 angle functions that bound the culling arcs (the hit angle atan2f
+ * over hits with r in [2^-30, 2^30], and asinf over [-1, 1] with extra
+ * arguments near +-1) against fp64, over n pseudo-random arguments.  The arcs
+ * are widened by 1e-4 rad, which assumes both errors stay below 1e-6.
+ * Allocates and frees an 8-byte device buffer; synchronous. */
+hough_status hough_selftest_angles(int64_t n, uint64_t seed, float *max_err_atan2, float *max_err_asin);
+
 /* Diagnostics (measurement only; no part of the method).  Saturating probes
  * on the current device: the rate of conflict-free, no-return 32-bit LDS
  * atomic adds (the vote's one memory operation) and of plain fp32 VALU

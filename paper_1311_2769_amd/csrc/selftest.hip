@@ -1,15 +1,20 @@
-// Device self-test of the vote's division fast path (vote_math.h): over n
-// pseudo-random operand pairs drawn across the whole range where the fast
-// path is used, the hoisted-reciprocal sequence must equal the division
-// operator bit for bit.
+// Device self-tests.
+//  - The vote's division fast path (vote_math.h): over n pseudo-random operand
+//    pairs drawn across the whole range where the fast path is used, the
+//    hoisted-reciprocal sequence must equal the division operator bit for bit.
+//  - The angle functions of the culling arcs (arc_math.h): their largest
+//    absolute error against fp64 over n pseudo-random arguments from their
+//    whole domain in hit_prep_kernel.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "hough.h"
 #include "vote_math.h"
+#include "arc_math.h"
 
 namespace {
 
@@ -58,6 +63,43 @@ __global__ void divide_check_kernel(int64_t n, uint64_t seed, unsigned long long
         atomicAdd(used, nused);
 }
 
+
+__device__ __forceinline__ void max_err(unsigned *slot, double err) {
+    // non-negative floats order like their bit patterns
+    const float e = static_cast<float>(err);
+    atomicMax(slot, __float_as_uint(e != e ? INFINITY : e));
+}
+
+__global__ void angle_check_kernel(int64_t n, uint64_t seed, unsigned *worst) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    double e_atan = 0.0, e_asin = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t h1 = mix64(seed + 3 * static_cast<uint64_t>(i));
+        const uint64_t h2 = mix64(seed + 3 * static_cast<uint64_t>(i) + 1);
+        const uint64_t h3 = mix64(seed + 3 * static_cast<uint64_t>(i) + 2);
+        // hit coordinates: r in [2^-30, 2^30], either coordinate may be 0
+        float x = draw(h1, -31, 29);
+        float y = draw(h2, -31, 29);
+        const uint32_t k = static_cast<uint32_t>(h3) & 63u;
+        if (k == 0)
+            x = 0.0f;
+        else if (k == 1)
+            y = 0.0f;
+        else if (k < 8)
+            y = x * (1.0f + static_cast<float>(k) * 1e-7f);   // near the diagonals
+        const double ref_a = atan2(static_cast<double>(y), static_cast<double>(x));
+        e_atan = fmax(e_atan, fabs(static_cast<double>(hough::hit_angle(x, y)) - ref_a));
+        // sine bounds: uniform in [-1, 1], or within 2^-k of +-1
+        float s = static_cast<float>(static_cast<int64_t>(h3 >> 40) - (1ll << 23)) * 0x1.0p-23f;
+        if (((h3 >> 8) & 3u) == 0)
+            s = copysignf(1.0f - ldexpf(1.0f, -static_cast<int>((h3 >> 10) % 25u)), s);
+        s = fminf(fmaxf(s, -1.0f), 1.0f);
+        e_asin = fmax(e_asin, fabs(static_cast<double>(hough::arc_asin(s)) - asin(static_cast<double>(s))));
+    }
+    max_err(worst, e_atan);
+    max_err(worst + 1, e_asin);
+}
+
 }  // namespace
 
 extern "C" hough_status hough_selftest_divide(int64_t n, uint64_t seed, uint64_t *mismatches, uint64_t *checked) {
@@ -80,5 +122,29 @@ extern "C" hough_status hough_selftest_divide(int64_t n, uint64_t seed, uint64_t
     *mismatches = h[0];
     if (checked)
         *checked = h[1];
+    return st;
+}
+
+extern "C" hough_status hough_selftest_angles(int64_t n, uint64_t seed, float *max_err_atan2, float *max_err_asin) {
+    if (n < 0 || !max_err_atan2 || !max_err_asin)
+        return HOUGH_EINVAL;
+    unsigned *d = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&d), 2 * sizeof(unsigned)) != hipSuccess)
+        return HOUGH_ENOMEM;
+    hough_status st = HOUGH_OK;
+    unsigned h[2] = {0u, 0u};
+    if (hipMemset(d, 0, 2 * sizeof(unsigned)) != hipSuccess)
+        st = HOUGH_EDEVICE;
+    if (st == HOUGH_OK) {
+        hipLaunchKernelGGL(angle_check_kernel, dim3(2048), dim3(256), 0, 0, n, seed, d);
+        if (hipGetLastError() != hipSuccess || hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+            st = HOUGH_EDEVICE;
+    }
+    (void)hipFree(d);
+    float a, b;
+    memcpy(&a, &h[0], sizeof a);
+    memcpy(&b, &h[1], sizeof b);
+    *max_err_atan2 = a;
+    *max_err_asin = b;
     return st;
 }

@@ -67,6 +67,7 @@
 #include "hough_impl.h"
 #include "peak_tile.h"
 #include "vote_math.h"
+#include "arc_math.h"
 
 namespace hough {
 namespace {
@@ -585,27 +586,42 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
 // Per-hit preparation: the hit record, and the two phi0 arcs per d0 slice
 // where a hit may vote, as ranges of tiles.
 //
-// Bound used (angles in radians, K = max |kappa edge|).  If a vote is cast,
-// the fp32 curvature kappa_c lies within K(1 + 2^-19).  kappa_c rounds
-// num_c / den_c, where num_c = 2(u_c - d) to 2^-24 relative, u_c = y c - x s to
-// r 2^-20 absolute (fp32 products, and fp32 cos/sin of the bin centre), and
-// den_c equals r^2 - 2 d u_c + d^2 to 2^-21 (r + |d|)^2 absolute.  The exact
-// denominator |h - P0|^2 is at least (r - |d|)^2, so when
+// Bound used (angles in radians, K' = max |kappa edge| (1 + 1e-3)).  If a vote
+// is cast, the fp32 curvature kappa_c lies within max |kappa edge| (1 + 2^-19).
+// kappa_c rounds num_c / den_c, where num_c = 2(u_c - d) to 2^-24 relative,
+// u_c = y c - x s to r 2^-20 absolute (fp32 products, and fp32 cos/sin of the
+// bin centre), and den_c equals r^2 - 2 d u_c + d^2 to 2^-21 (r + |d|)^2
+// absolute.  The exact denominator |h - P0|^2 is at least (r - |d|)^2, so when
 // |r - |d|| >= 0.03 (r + |d|) its relative error is at most 2^-21 / 0.03^2 <
 // 5.3e-4, kappa(u_c) = 2(u_c - d)/(r^2 + d^2 - 2 d u_c) is within relative
-// 5.4e-4 of kappa_c, and |kappa(u_c)| <= K' = K (1 + 1e-3).  On |u| <= r the
-// function kappa(u) is continuous and monotone (its derivative has the sign
-// of r^2 - d^2; its pole (r^2 + d^2) / (2 d) lies at least 0.0018 r beyond
+// 5.4e-4 of kappa_c, and |kappa(u_c)| <= K'.  On |u| <= r the function
+// kappa(u) is continuous and monotone (its derivative has the sign of
+// r^2 - d^2; its pole (r^2 + d^2) / (2 d) lies at least 0.0018 r beyond
 // |u| = r under the same condition), and its inverse
-// u(k) = (k (r^2 + d^2) + 2 d) / (2 (1 + k d)) is continuous on [-K', K']
-// when K' |d| < 1, so u_c lies between u(-K') and u(K') and r sin(phi_h -
-// phi0) lies in that interval widened by r 1e-5.  The two phi0 arcs that
-// satisfy this, widened by 1e-5 rad and one row on each side, hold every row
-// that can receive the hit's votes.  Hits that are not finite, sit within
-// 1e-15 of the origin or beyond 1e15, fail the conditioning test or have
-// K' |d| >= 1 get the full circle.  The phi0 table must hold the bin
-// centres (j + 1/2) 2 pi / n_phi (checked when the context is created;
-// otherwise no ranges are used).
+// u(k) = (k (r^2 + d^2) + 2 d) / (2 (1 + k d)) is continuous and monotone on
+// [-K', K'] when K' |d| < 1, so u_c lies between u(-K') and u(K') and
+// sin(phi_h - phi0) lies between s(-K') and s(K'), s(k) = u(k) / r, widened
+// by 1e-5.
+//
+// hit_prep_kernel evaluates s(-+K) in fp32 as (2d -+ K rr) (1/(2r)) / (1 -+ K d)
+// with K = K' rounded up to fp32 (a larger K only widens the interval),
+// rr = r2 + d^2, r = sqrt(r2) and the reciprocals from arc_rcp.  One rounding
+// per operation (2^-24 relative, 2^-23 for arc_rcp, 3 2^-24 for r) bounds the
+// error of either end by (K rr + 2|d|) (1/r) w^2 17 2^-25, w = 1 / (1 - K|d|);
+// the interval is widened by 1e-5 + 2^-18 (K rr + 2|d|) (1/r) w^2, more than
+// four times that on top of the 1e-5.  The fp32 tests r in [2^-30, 2^30],
+// |d| <= 2^30, |r - |d|| >= 0.0301 (r + |d|) and K |d| <= 0.99 imply the real
+// conditions above; a hit or slice that fails them, or whose ends are not
+// finite, gets the full circle.
+//
+// The arcs of phi0 whose sine lies in the widened interval (from
+// phi_h = hit_angle(x, y) and arc_asin of its clamped ends) are widened by
+// kArcTol = 1e-4 rad, which covers the library angle error (at most
+// kArcAngleErrMax each, checked by hough_selftest_angles), the fp32 angle
+// sums (|angle| <= 2.5 pi) and the fp32 scaling to rows, and then by one row
+// on each side.  The phi0 table must hold the bin centres
+// (j + 1/2) 2 pi / n_phi (checked when the context is created; otherwise no
+// ranges are used).
 //
 // An arc of rows (start, length; length 0: empty, n_phi: the full circle) is
 // turned into the cyclic range of tiles that vote any of its rows: the tile
@@ -627,8 +643,9 @@ struct PrepArgs {
     int32_t n_phi;
     int32_t n_d0;
     int32_t tiles, tile_stride, halo;
+    uint32_t stride_magic;      // ceil(2^32 / tile_stride), 0 when tile_stride == 1
     int32_t div_fast;
-    double kabs;
+    float kabs;                 // K' rounded up to fp32 (may be +inf)
 };
 
 // 3D quotient range (every phi0 row of one hit and d0 slice): with a phi0
@@ -643,25 +660,29 @@ struct PrepArgs {
 //   either |u| < |d| / 2 and |u - d| > 2^-21, or both magnitudes are at
 //   least 2^-21 and the difference is a nonzero multiple of 2^-45), so every
 //   nonzero numerator is in [2^-60, 2^30]; a zero numerator moves no vote.
-__device__ __forceinline__ bool fast_div_3d(double r, double d, double ad) {
-    const bool r_ok = r >= 0x1.0p-8 && r <= 0x1.0p10;
-    const bool d_ok = d == 0.0 || (ad >= 0x1.0p-20 && ad <= 0x1.0p10);
-    return r_ok && d_ok && fabs(r - ad) >= 0.03 * (r + ad);
+// The test takes the fp32 r (within 3 2^-24 relative of the real one) with
+// bounds pulled in by 2^-20 and the stricter 0.0301, so it implies the above.
+__device__ __forceinline__ bool fast_div_3d(float r, float d, float ad) {
+    const bool r_ok = r >= 0x1.00001p-8f && r <= 0x1.ffffep9f;
+    const bool d_ok = d == 0.0f || (ad >= 0x1.0p-20f && ad <= 0x1.0p10f);
+    return r_ok && d_ok && fabsf(r - ad) >= 0.0301f * (r + ad);
 }
 
-__device__ __forceinline__ uint32_t pack_arc(double phi_a, double phi_b, int n) {
-    const double dphi = 6.283185307179586 / n;
-    const double tol = 1e-5;
-    const double lo = ceil((phi_a - tol) / dphi - 0.5) - 1.0;
-    const double hi = floor((phi_b + tol) / dphi - 0.5) + 1.0;
+// Rows whose centres (j + 1/2) 2 pi / n lie in [phi_a, phi_b], widened by
+// kArcTol and one row on each side; sc = n / (2 pi) in fp32.
+__device__ __forceinline__ uint32_t pack_arc(float phi_a, float phi_b, int n, float sc) {
+    const float lo = ceilf((phi_a - kArcTol) * sc - 0.5f) - 1.0f;
+    const float hi = floorf((phi_b + kArcTol) * sc - 0.5f) + 1.0f;
     if (hi < lo)
         return 0u;
-    const double rows = hi - lo + 1.0;
-    if (rows >= n)
+    const float rows = hi - lo + 1.0f;
+    if (rows >= static_cast<float>(n))
         return static_cast<uint32_t>(n) << 16;
-    double start = fmod(lo, static_cast<double>(n));
-    if (start < 0)
+    int start = static_cast<int>(lo);          // |lo| <= 1.25 n + 2
+    while (start < 0)
         start += n;
+    while (start >= n)
+        start -= n;
     return static_cast<uint32_t>(start) | (static_cast<uint32_t>(rows) << 16);
 }
 
@@ -677,10 +698,10 @@ __device__ __forceinline__ uint32_t tile_range(uint32_t arc, const PrepArgs &p) 
     const int start = static_cast<int>(arc & 0xffffu);
     const int end_u = start + len - 1;                 // unwrapped, < 2n
     const int end = end_u >= n ? end_u - n : end_u;
-    int lo = start / S;
+    int lo = p.stride_magic ? div_small(start, p.stride_magic) : start;
     if (p.halo && start == lo * S)
         lo -= 1;                                       // the tile before votes it as its upper halo
-    const int oe = end / S;
+    const int oe = p.stride_magic ? div_small(end, p.stride_magic) : end;
     int hi = (end_u >= n ? T : 0) + oe;
     if (p.halo && end == oe * S + min(S, n - oe * S) - 1)
         hi += 1;                                       // the tile after votes it as its lower halo
@@ -701,9 +722,9 @@ __global__ void hit_prep_kernel(PrepArgs p) {
         return;
     const float xf = p.x[i];
     const float yf = p.y[i];
+    const float r2 = xf * xf + yf * yf;
     const int l_begin = blockIdx.y * kPrepSlices;
     if (l_begin == 0) {
-        const float r2 = xf * xf + yf * yf;
         float4 rec = make_float4(xf, yf, r2, 0.0f);
         if (p.div_fast && p.d0 == nullptr) {
             const float half = 0.5f * r2;
@@ -714,35 +735,44 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     }
     if (!p.ranges)
         return;
-    const double X = xf;
-    const double Y = yf;
-    const double r = sqrt(X * X + Y * Y);
-    const double ph = atan2(Y, X);
-    const double K = p.kabs * (1.0 + 1e-3);
+    const float r = sqrtf(r2);
+    const bool r_ok = r >= 0x1.0p-30f && r <= 0x1.0p30f;     // false for NaN
+    const float inv_r = arc_rcp(r_ok ? r : 1.0f);
+    const float half_inv_r = 0.5f * inv_r;
+    const float ph = hit_angle(xf, yf);
+    const float K = p.kabs;
+    const float sc = static_cast<float>(p.n_phi) * 0.159154943f;
+    const float pi = 3.14159274f;
     const int l_end = min(l_begin + kPrepSlices, p.d0 ? p.n_d0 : 1);
     for (int l = l_begin; l < l_end; ++l) {
         uint2 out = make_uint2(kAllTiles, 0u);
-        const double d = p.d0 ? static_cast<double>(p.d0[l]) : 0.0;
-        const double ad = fabs(d);
-        const bool finite_in = isfinite(X) && isfinite(Y) && isfinite(d);
-        if (finite_in && r > 1e-15 && r < 1e15 && ad < 1e15 && fabs(r - ad) >= 0.03 * (r + ad) && K * ad < 1.0) {
-            const double rr = r * r + d * d;
-            const double u1 = (-K * rr + 2.0 * d) / (2.0 * (1.0 - K * d));
-            const double u2 = (K * rr + 2.0 * d) / (2.0 * (1.0 + K * d));
-            const double slo = (fmin(u1, u2) - r * 1e-5) / r;
-            const double shi = (fmax(u1, u2) + r * 1e-5) / r;
-            if (slo > 1.0 || shi < -1.0) {
+        const float d = p.d0 ? p.d0[l] : 0.0f;
+        const float ad = fabsf(d);
+        const float kd = K * ad;
+        if (r_ok && ad <= 0x1.0p30f && fabsf(r - ad) >= 0.0301f * (r + ad) && kd <= 0.99f) {
+            const float rr = r2 + d * d;
+            const float a = K * rr;
+            const float b = 2.0f * d;
+            const float s1 = (b - a) * half_inv_r * arc_rcp(1.0f - K * d);
+            const float s2 = (b + a) * half_inv_r * arc_rcp(1.0f + K * d);
+            const float w = arc_rcp(1.0f - kd);
+            const float m = 1e-5f + 0x1.0p-18f * (a + 2.0f * ad) * inv_r * w * w;
+            const float slo = fminf(s1, s2) - m;
+            const float shi = fmaxf(s1, s2) + m;
+            if (!(isfinite(slo) && isfinite(shi))) {
+                // full circle
+            } else if (slo > 1.0f || shi < -1.0f) {
                 out = make_uint2(0u, 0u);
-            } else if (!(slo <= -1.0 && shi >= 1.0)) {
-                const double alo = asin(fmax(slo, -1.0));
-                const double ahi = asin(fmin(shi, 1.0));
-                const double pi = 3.141592653589793;
-                out = make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi), p),
-                                 tile_range(pack_arc(ph - pi + alo, ph - pi + ahi, p.n_phi), p));
+            } else if (!(slo <= -1.0f && shi >= 1.0f)) {
+                const float alo = arc_asin(fmaxf(slo, -1.0f));
+                const float ahi = arc_asin(fminf(shi, 1.0f));
+                const float pm = ph - pi;
+                out = make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi, sc), p),
+                                 tile_range(pack_arc(pm + alo, pm + ahi, p.n_phi, sc), p));
             }
-            if (p.d0 && p.div_fast && fast_div_3d(r, d, ad))
-                out.y |= kFastDiv;
         }
+        if (p.d0 && p.div_fast && fast_div_3d(r, d, ad))
+            out.y |= kFastDiv;
         p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = out;
     }
 }
@@ -893,7 +923,14 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     p.div_fast = div_fast ? 1 : 0;
     const double kmin = g.kappa_min;
     const double kmax = static_cast<double>(g.kappa_min) + static_cast<double>(g.n_kappa) / g.kappa_scale;
-    p.kabs = fmax(fabs(kmin), fabs(kmax));
+    const double K = fmax(fabs(kmin), fabs(kmax)) * (1.0 + 1e-3);
+    float Kf = static_cast<float>(K);
+    if (static_cast<double>(Kf) < K)
+        Kf = nextafterf(Kf, INFINITY);
+    p.kabs = std::isnan(K) ? INFINITY : Kf;
+    p.stride_magic = tg.stride > 1
+        ? static_cast<uint32_t>(((1ull << 32) + static_cast<uint64_t>(tg.stride) - 1) / static_cast<uint64_t>(tg.stride))
+        : 0u;
     const unsigned blocks = static_cast<unsigned>((n_hits + 255) / 256);
     const unsigned groups = ranges ? static_cast<unsigned>((g.n_d0 + kPrepSlices - 1) / kPrepSlices) : 1u;
     hipLaunchKernelGGL(hit_prep_kernel, dim3(blocks, groups), dim3(256), 0, stream, p);

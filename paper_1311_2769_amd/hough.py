@@ -29,7 +29,7 @@ SYMBOLS = (
     "hough_autotune", "hough_tune_lookup",
     "hough_server_create", "hough_server_destroy", "hough_server_clock", "hough_server_submit",
     "hough_server_replay", "hough_server_poll", "hough_server_stats",
-    "hough_selftest_divide", "hough_diag_rates", "hough_status_str", "hough_last_error", "hough_version",
+    "hough_selftest_divide", "hough_selftest_angles", "hough_diag_rates", "hough_status_str", "hough_last_error", "hough_version",
 )
 
 
@@ -130,6 +130,9 @@ def load(path: str = LIB_PATH):
     lib.hough_selftest_divide.restype = i32
     lib.hough_selftest_divide.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64)]
+    lib.hough_selftest_angles.restype = i32
+    lib.hough_selftest_angles.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float)]
     lib.hough_status_str.restype = ctypes.c_char_p
     lib.hough_status_str.argtypes = [i32]
     lib.hough_last_error.restype = ctypes.c_char_p
@@ -346,6 +349,15 @@ def selftest_divide(n: int, seed: int = 1):
     _check(lib.hough_selftest_divide(int(n), int(seed), ctypes.byref(bad), ctypes.byref(used)),
            "hough_selftest_divide")
     return bad.value, used.value
+
+
+def selftest_angles(n: int, seed: int = 1):
+    """(max |atan2f - atan2|, max |asinf - asin|) in radians over n device draws."""
+    lib = load()
+    ea, es = ctypes.c_float(), ctypes.c_float()
+    _check(lib.hough_selftest_angles(int(n), int(seed), ctypes.byref(ea), ctypes.byref(es)),
+           "hough_selftest_angles")
+    return ea.value, es.value
 
 
 def acc_to_numpy(acc, spec: GridSpec):

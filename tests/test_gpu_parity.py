@@ -479,6 +479,17 @@ def test_division_fast_path_equals_the_operator():
     assert total > 100_000_000
 
 
+def test_culling_angle_functions_stay_within_their_budget():
+    """The fp32 angle functions behind the culling arcs err by at most 1e-6 rad,
+    so the 1e-4 rad widening of every arc covers them many times over."""
+    _dev()
+    for seed in (1, 2):
+        e_atan, e_asin = hough.selftest_angles(50_000_000, seed)
+        print(f"[angles] seed {seed}: atan2f {e_atan:.3g} rad, asinf {e_asin:.3g} rad", flush=True)
+        assert 0.0 < e_atan <= 1e-6
+        assert 0.0 < e_asin <= 1e-6
+
+
 def test_throughput_probes_report_plausible_rates():
     """The roofline probes run and land within the chip's nominal limits."""
     _dev()
