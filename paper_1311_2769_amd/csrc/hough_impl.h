@@ -167,7 +167,6 @@ hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const Vote
                              unsigned long long *n_votes, const SortWork *w, int32_t threshold,
                              hipStream_t stream);
 
-constexpr int kPeakRows = 8;          // phi0 rows per peak-search block
 int32_t peak_blocks_per_event(const GridArgs &g);
 int32_t peak_block_cap(const GridArgs &g);
 int32_t peak_blocks_per_chunk(const GridArgs &g);

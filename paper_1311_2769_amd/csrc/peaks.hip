@@ -1,18 +1,29 @@
 // Peak search and candidate ordering for gfx950.
 //
 // Section 3: after voting, local maxima of the parameter space are the track
-// candidates.  A block owns a band of kPeakRows phi0 rows and walks
-// kPeakSlices consecutive d0 slices of it, keeping three slices (d0 l-1, l,
-// l+1) of the band plus a one-row halo on each side (phi0 wraps) in an LDS
-// ring, so each slice is read from memory about (kPeakSlices + 2) /
-// kPeakSlices times.  uint16 cells are unpacked to int32; every staged row is
-// padded with one INT_MIN column on each side, which stands for the kappa
-// neighbours outside the grid (never larger than a cell).  For slice l the
-// asymmetric 3x3(x3) test of hough.h is branch-free: the cell must exceed the
-// maximum of its lexicographically earlier neighbours -- the whole slice
-// below, the row above, the cell to its left -- and reach the maximum of the
-// later ones.  Survivors of each (slice, band) are compacted in ascending
-// cell order into that pair's staging list.
+// candidates.  Each wavefront owns a strip of one d0 slice -- whole phi0 rows
+// when a row is at most 64 lanes of 4 dwords, else 64 lanes' worth of one
+// row -- and walks kPeakSlices consecutive d0 slices of it.  A lane holds 4
+// consecutive dwords of a row (8 uint16 or 4 int32 cells) and loads them, for
+// rows j-1, j, j+1 (phi0 wraps), straight from memory, one slice ahead of the
+// test; kappa neighbours across lanes come from lane shifts (from memory at a
+// wavefront boundary inside a row), and cells outside the kappa or d0 range
+// count as INT_MIN, which never blocks a cell.
+//
+// The asymmetric 3x3(x3) test of hough.h is separable: with A = the maximum of
+// a cell and its two kappa neighbours in one row and B = the maximum of A over
+// rows j-1, j, j+1 (the 3x3 square of one slice), a cell passes when it
+// reaches the threshold, exceeds max(B of slice l-1, A of row j-1, its left
+// neighbour) and reaches max(B of slice l+1, A of row j+1, its right
+// neighbour).  B of each slice is computed once and kept in registers for the
+// two slices that use it, so a cell costs about ten VALU operations and no
+// LDS reads.
+//
+// Four wavefronts form a block; the survivors of one block and slice are one
+// staging list in ascending cell order (lane order within a wavefront, then
+// wavefront order), placed after one LDS exchange of wavefront counts.  Their
+// first-digit histogram is counted in LDS and the event's key range is
+// published once per block.
 //
 // Ordering (votes descending, then cell ascending) is a stable LSD radix sort
 // on key = 0x7fffffff - votes with 8-bit digits.  Staging lists are already
@@ -24,6 +35,7 @@
 // digits in which an event's keys actually differ are sorted; the last pass
 // writes straight into the caller's candidate array, clipped at its
 // capacity.
+#include <algorithm>
 #include <climits>
 
 #include "hough_impl.h"
@@ -32,39 +44,79 @@
 namespace hough {
 namespace {
 
+constexpr int kPeakThreads = 256;
+constexpr int kPeakWaves = kPeakThreads / 64;
+constexpr int kPeakSlices = 8;     // d0 slices walked per block (at most)
+constexpr size_t kPeakLdsBudget = 40 * 1024;   // staged lists and histograms per block
+
+// Strips of one d0 slice.  A phi0 row is lpr lanes of 4 dwords (the last lane
+// of a row may hold fewer).  lpr <= 64: a wavefront holds rpw = 64 / lpr whole
+// rows; lpr > 64: a row is wpr wavefronts.
+struct PeakLayout {
+    int32_t lpr;
+    int32_t rpw;             // 0 when lpr > 64
+    int32_t wpr;             // 0 when lpr <= 64
+    int32_t strips;          // wavefront strips per slice
+    int32_t bands;           // blocks per slice (kPeakWaves consecutive strips)
+    int32_t rows_per_band;   // phi0 rows one band can touch
+};
+
+PeakLayout peak_layout(const GridArgs &g) {
+    PeakLayout p{};
+    p.lpr = (g.row_dwords + 3) / 4;
+    if (p.lpr <= 64) {
+        p.rpw = 64 / p.lpr;
+        p.strips = (g.n_phi + p.rpw - 1) / p.rpw;
+        p.rows_per_band = kPeakWaves * p.rpw;
+    } else {
+        p.wpr = (p.lpr + 63) / 64;
+        p.strips = g.n_phi * p.wpr;
+        if (p.wpr % kPeakWaves == 0)
+            p.rows_per_band = 1;
+        else if (kPeakWaves % p.wpr == 0)
+            p.rows_per_band = kPeakWaves / p.wpr;
+        else
+            p.rows_per_band = (kPeakWaves + p.wpr - 1) / p.wpr + 1;
+    }
+    p.bands = (p.strips + kPeakWaves - 1) / kPeakWaves;
+    return p;
+}
+
 struct PeakArgs {
     GridArgs g;
     const uint32_t *acc;     // dwords, events back to back
     int32_t threshold;
-    int32_t blocks_per_slice;
+    int32_t lpr, rpw, wpr, bands;
+    int32_t slices;          // d0 slices walked per block
     SortWork w;
 };
 
-constexpr int kPeakThreads = 256;
-constexpr int kPeakWaves = kPeakThreads / 64;
-constexpr int kHaloRows = kPeakRows + 2;
-constexpr int kPeakSlices = 8;
-constexpr int kPrefetch = 8;                              // dwords per thread per load round
-constexpr int kMaxSegs = 64;                              // (row, kappa chunk) pairs per band
-
 __device__ __forceinline__ int32_t max3i(int32_t a, int32_t b, int32_t c) { return max(max(a, b), c); }
 
-struct PeakScratch {
-    uint32_t hist[kDigits];
-    uint64_t seg_mask[kMaxSegs][kPeakWaves];   // survivor lanes per (row, kappa chunk) and wavefront
-    uint32_t red_min[kPeakWaves];
-    uint32_t red_max[kPeakWaves];
+// One slice as seen by a lane: its cells of row j with their outer kappa
+// neighbours, A of rows j-1 and j+1, and B.
+template <int CPL>
+struct SliceView {
+    int32_t v[CPL];
+    int32_t left, right;
+    int32_t au[CPL], ad[CPL], b[CPL];
 };
 
-// LDS: a ring of 4 slices (2D: 1) x kHaloRows rows x (n_kappa + 2) int32,
-// then two dwords per thread that take the stores of positions past the band.
-// The slice after next is loaded into registers while the current slice is
-// tested and stored into the ring afterwards, so its memory latency overlaps
-// the test.
-template <bool U16>
+template <bool U16, bool VEC>
 __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
-    extern __shared__ int32_t ring[];
-    __shared__ PeakScratch sc;
+    constexpr int CPL = U16 ? 8 : 4;
+    // LDS: per walked slice a 256-bin histogram, a count and a candidate list
+    // of cap0 entries; global stores wait until the walk is done, so the only
+    // memory operations in the walk are the slice loads.
+    extern __shared__ uint32_t dyn[];
+    __shared__ int32_t wcnt[2][kPeakWaves];
+    __shared__ uint32_t wmin[2][kPeakWaves];
+    __shared__ uint32_t wmax[2][kPeakWaves];
+    __shared__ int32_t scnt[kPeakSlices];
+    const int S = a.slices;
+    const int cap0 = a.w.s0.cap0;
+    uint32_t *const hist = dyn;                                          // [S][kDigits]
+    Cand *const cands = reinterpret_cast<Cand *>(dyn + S * kDigits);     // [S][cap0]
 
     const GridArgs &g = a.g;
     const int tid = threadIdx.x;
@@ -73,248 +125,236 @@ __global__ __launch_bounds__(kPeakThreads) void peak_kernel(PeakArgs a) {
     const int e = blockIdx.y;
     if (a.w.n_events_dev && e >= *a.w.n_events_dev)
         return;
-    const int bps = a.blocks_per_slice;
-    const int rb = blockIdx.x % bps;
-    const int l0 = (blockIdx.x / bps) * kPeakSlices;
-    const int l1 = min(g.n_d0, l0 + kPeakSlices);
-    const int j0 = rb * kPeakRows;
-    const int rows_here = min(kPeakRows, g.n_phi - j0);
+    const int band = blockIdx.x % a.bands;
+    const int l0 = (blockIdx.x / a.bands) * a.slices;
+    const int l1 = min(g.n_d0, l0 + a.slices);
+    const int n_phi = g.n_phi;
     const int nk = g.n_kappa;
-    const int W = nk + 2;
-    const int plane = kHaloRows * W;
-    const bool three = g.n_d0 > 1;
     const int rd = g.row_dwords;
-    const int n_words = (rows_here + 2) * rd;             // staged dwords of one slice
-    const uint32_t *acc_e = a.acc + static_cast<int64_t>(e) * g.acc_dwords;
-    auto slot = [&](int ll) { return ring + (three ? (ll & 3) : 0) * plane; };
-
-    // Staged dword i = tid + kPeakThreads*m of a band is (row rr, dword wd)
-    // with i = rr*rd + wd.  For the first load round (all of it when the band
-    // fits one round) each thread's global and LDS offsets are the same for
-    // every slice, so they are computed once.
-    const int dr = kPeakThreads / rd;
-    const int dw = kPeakThreads - dr * rd;
-    const int rr_first = tid / rd;
-    const int wd_first = tid - rr_first * rd;
-    auto advance = [&](int &rr, int &wd) {
-        wd += dw;
-        rr += dr;
-        if (wd >= rd) {
-            wd -= rd;
-            ++rr;
-        }
-    };
-    // Positions past the band load dword 0 of the slice and store into this
-    // thread's own two dwords after the ring, so the rounds need no branches.
-    int32_t goff[kPrefetch];   // dword offset inside a slice
-    int32_t loff[kPrefetch];   // LDS offset of the first staged cell, from the ring base
-    const int slot_words = (three ? 4 : 1) * plane;
-    {
-        int rr = rr_first, wd = wd_first;
-#pragma unroll
-        for (int q = 0; q < kPrefetch; ++q) {
-            int j = j0 + rr - 1;
-            j += j < 0 ? g.n_phi : 0;
-            j -= j >= g.n_phi ? g.n_phi : 0;
-            const bool in = rr < rows_here + 2;
-            goff[q] = in ? j * rd + wd : 0;
-            loff[q] = in ? rr * W + 1 + (U16 ? 2 * wd : wd) : -1;
-            advance(rr, wd);
-        }
+    const int lpr = a.lpr;
+    const int strip = band * kPeakWaves + wave;
+    int j, ri;
+    bool active;
+    if (a.rpw > 0) {
+        const int ro = lane / lpr;
+        ri = lane - ro * lpr;
+        j = strip * a.rpw + ro;
+        active = ro < a.rpw && j < n_phi;
+    } else {
+        j = strip / a.wpr;
+        ri = (strip - j * a.wpr) * 64 + lane;
+        active = j < n_phi && ri < lpr;
     }
-    int32_t *const dummy = ring + slot_words + 2 * tid;
-    uint32_t pv[kPrefetch];
-    auto issue_first = [&](int ll) {
-        const uint32_t *src = acc_e + static_cast<int64_t>(ll) * g.n_phi * rd;
+    const int dw0 = ri * 4;
+    const int ndw = active ? min(4, rd - dw0) : 0;
+    const int jj = active ? j : 0;
+    const int jm = jj == 0 ? n_phi - 1 : jj - 1;
+    const int jp = jj + 1 == n_phi ? 0 : jj + 1;
+    const int roff[3] = {jm * rd + dw0, jj * rd + dw0, jp * rd + dw0};
+    const bool row_first = ri == 0;
+    const bool row_last = ri == lpr - 1;
+    // neighbour dwords in another wavefront of the same row
+    const bool left_mem = active && !row_first && a.wpr > 0 && lane == 0;
+    const bool right_mem = active && !row_last && a.wpr > 0 && lane == 63;
+    const uint32_t *acc_e = a.acc + static_cast<int64_t>(e) * g.acc_dwords;
+    const int64_t plane = static_cast<int64_t>(n_phi) * rd;
+
+    auto load = [&](int ll, uint32_t (&r)[3][4], uint32_t (&x)[3][2]) {
+        const uint32_t *p = acc_e + static_cast<int64_t>(ll) * plane;
 #pragma unroll
-        for (int q = 0; q < kPrefetch; ++q)
-            pv[q] = src[goff[q]];
+        for (int q = 0; q < 3; ++q) {
+            if constexpr (VEC) {
+                uint4 d = make_uint4(0u, 0u, 0u, 0u);
+                if (active)
+                    d = *reinterpret_cast<const uint4 *>(p + roff[q]);
+                r[q][0] = d.x;
+                r[q][1] = d.y;
+                r[q][2] = d.z;
+                r[q][3] = d.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    r[q][k] = k < ndw ? p[roff[q] + k] : 0u;
+            }
+            x[q][0] = left_mem ? p[roff[q] - 1] : 0u;
+            x[q][1] = right_mem ? p[roff[q] + 4] : 0u;
+        }
     };
-    auto commit_first = [&](int ll) {
-        int32_t *p = slot(ll);
+    // cells of one row with the kappa maxima A; returns the outer neighbours
+    auto row = [&](const uint32_t (&d)[4], const uint32_t (&x)[2], int32_t (&c)[CPL], int32_t (&m)[CPL],
+                   int32_t &left, int32_t &right) {
 #pragma unroll
-        for (int q = 0; q < kPrefetch; ++q) {
-            int32_t *d = loff[q] >= 0 ? p + loff[q] : dummy;
+        for (int k = 0; k < 4; ++k) {
             if constexpr (U16) {
-                d[0] = static_cast<int32_t>(pv[q] & 0xffffu);
-                d[1] = static_cast<int32_t>(pv[q] >> 16);
+                c[2 * k] = k < ndw ? static_cast<int32_t>(d[k] & 0xffffu) : INT_MIN;
+                c[2 * k + 1] = k < ndw ? static_cast<int32_t>(d[k] >> 16) : INT_MIN;
             } else {
-                d[0] = static_cast<int32_t>(pv[q]);
+                c[k] = k < ndw ? static_cast<int32_t>(d[k]) : INT_MIN;
             }
         }
-    };
-    auto pad = [&](int ll) {
-        int32_t *p = slot(ll);
-        for (int rr = tid; rr < kHaloRows; rr += kPeakThreads) {
-            p[rr * W] = INT_MIN;
-            p[rr * W + nk + 1] = INT_MIN;
-        }
-    };
-    auto load = [&](int ll) {
-        issue_first(ll);
-        commit_first(ll);
-        // rounds after the first
-        int rr = rr_first, wd = wd_first;
-        for (int q = 0; q < kPrefetch; ++q)
-            advance(rr, wd);
-        for (int c0 = kPrefetch * kPeakThreads; c0 < n_words; c0 += kPrefetch * kPeakThreads) {
-            const uint32_t *src = acc_e + static_cast<int64_t>(ll) * g.n_phi * rd;
-            int32_t *p = slot(ll);
-            for (int q = 0; q < kPrefetch; ++q) {
-                if (rr < rows_here + 2) {
-                    int j = j0 + rr - 1;
-                    j += j < 0 ? g.n_phi : 0;
-                    j -= j >= g.n_phi ? g.n_phi : 0;
-                    const uint32_t v = src[static_cast<int64_t>(j) * rd + wd];
-                    int32_t *dst = p + rr * W + 1;
-                    if constexpr (U16) {
-                        dst[2 * wd] = static_cast<int32_t>(v & 0xffffu);
-                        dst[2 * wd + 1] = static_cast<int32_t>(v >> 16);
-                    } else {
-                        dst[wd] = static_cast<int32_t>(v);
-                    }
-                }
-                advance(rr, wd);
-            }
-        }
-        pad(ll);
-    };
-    // The slice after next can stay in registers across the test when it fits one round.
-    const bool overlap = three && n_words <= kPrefetch * kPeakThreads;
-
-    if (three && l0 > 0)
-        load(l0 - 1);
-    load(l0);
-    if (three && l0 + 1 < g.n_d0)
-        load(l0 + 1);
-    const int32_t thr = a.threshold;
-    // rows_here * ceil(nk / kPeakThreads) segments <= kMaxSegs (checked on the host)
-    for (int l = l0; l < l1; ++l) {
-        const bool next2 = three && l + 2 < g.n_d0 && l + 2 <= l1;   // needed by this block's last step
-        if (next2 && overlap)
-            issue_first(l + 2);
-        for (int i = tid; i < kDigits; i += kPeakThreads)
-            sc.hist[i] = 0u;
-        lds_barrier();
-        const bool has_lo = three && l > 0;
-        const bool has_hi = three && l + 1 < g.n_d0;
-        const int32_t *mid = slot(l);
-        const int32_t *lo = slot(has_lo ? l - 1 : l);
-        const int32_t *hi = slot(has_hi ? l + 1 : l);
-
-        // Test of cell (row jr of the band, kappa k); cells in ascending
-        // order are the segments (jr, kappa chunk) in turn.
-        auto test = [&](int jr, int k, int32_t *v_out) {
-            if (k >= nk)
-                return false;
-            const int at = (jr + 1) * W + k + 1;
-            const int32_t *m = mid + at;
-            const int32_t v = m[0];
-            int32_t before = max(max3i(m[-W - 1], m[-W], m[-W + 1]), m[-1]);
-            int32_t after = max(max3i(m[W - 1], m[W], m[W + 1]), m[1]);
-            if (has_lo) {
-                const int32_t *q = lo + at;
-                before = max(before, max3i(max3i(q[-W - 1], q[-W], q[-W + 1]), max3i(q[-1], q[0], q[1]),
-                                           max3i(q[W - 1], q[W], q[W + 1])));
-            }
-            if (has_hi) {
-                const int32_t *q = hi + at;
-                after = max(after, max3i(max3i(q[-W - 1], q[-W], q[-W + 1]), max3i(q[-1], q[0], q[1]),
-                                         max3i(q[W - 1], q[W], q[W + 1])));
-            }
-            *v_out = v;
-            return v >= thr && v > before && v >= after;
-        };
-        // pass 1: survivor lanes per segment and wavefront (every lane writes
-        // the same mask).  One kappa chunk per row (n_kappa <= the block
-        // size) unrolls over the rows, so their LDS reads overlap.
-        if (nk <= kPeakThreads) {
+        left = __shfl_up(c[CPL - 1], 1);
+        right = __shfl_down(c[0], 1);
+        if (row_first)
+            left = INT_MIN;
+        else if (left_mem)
+            left = U16 ? static_cast<int32_t>(x[0] >> 16) : static_cast<int32_t>(x[0]);
+        if (row_last)
+            right = INT_MIN;
+        else if (right_mem)
+            right = U16 ? static_cast<int32_t>(x[1] & 0xffffu) : static_cast<int32_t>(x[1]);
 #pragma unroll
-            for (int jr = 0; jr < kPeakRows; ++jr) {
-                if (jr < rows_here) {
-                    int32_t v;
-                    const bool keep = test(jr, tid, &v);
-                    sc.seg_mask[jr][wave] = __ballot(keep);
-                }
-            }
+        for (int i = 0; i < CPL; ++i)
+            m[i] = max3i(i == 0 ? left : c[i - 1], c[i], i == CPL - 1 ? right : c[i + 1]);
+    };
+    auto view = [&](const uint32_t (&r)[3][4], const uint32_t (&x)[3][2], SliceView<CPL> &s) {
+        int32_t cu[CPL], cd[CPL], am[CPL];
+        int32_t lu, ru, ld, rdn;
+        row(r[0], x[0], cu, s.au, lu, ru);
+        row(r[1], x[1], s.v, am, s.left, s.right);
+        row(r[2], x[2], cd, s.ad, ld, rdn);
+#pragma unroll
+        for (int i = 0; i < CPL; ++i)
+            s.b[i] = max3i(s.au[i], am[i], s.ad[i]);
+    };
+
+    uint32_t raw[3][4], rx[3][2];
+    int32_t pb[CPL];                // B of slice l - 1
+    SliceView<CPL> cur;
+    {
+        uint32_t r0[3][4], x0[3][2], r1[3][4], x1[3][2];
+        const bool has_prev = l0 > 0;
+        if (has_prev)
+            load(l0 - 1, r0, x0);
+        load(l0, r1, x1);
+        if (l0 + 1 < g.n_d0)
+            load(l0 + 1, raw, rx);
+        if (has_prev) {
+            SliceView<CPL> p;
+            view(r0, x0, p);
+#pragma unroll
+            for (int i = 0; i < CPL; ++i)
+                pb[i] = p.b[i];
         } else {
-            for (int jr = 0, s = 0; jr < rows_here; ++jr) {
-                for (int k0 = 0; k0 < nk; k0 += kPeakThreads, ++s) {
-                    int32_t v;
-                    const bool keep = test(jr, k0 + tid, &v);
-                    sc.seg_mask[s][wave] = __ballot(keep);
-                }
-            }
-        }
-        // Slice l+2 goes into the slot slice l-2 held (read last in the
-        // previous step); stored now, before this step's candidate stores
-        // queue behind its loads.
-        if (next2) {
-            if (overlap) {
-                commit_first(l + 2);
-                pad(l + 2);
-            } else {
-                load(l + 2);
-            }
-        }
-        lds_barrier();
-        // pass 2: write survivors in cell order
-        Cand *out = a.w.s0.stage + (static_cast<int64_t>(e) * a.w.s0.n_blocks0 + l * bps + rb) * a.w.s0.cap0;
-        const int64_t cell_base = (static_cast<int64_t>(l) * g.n_phi + j0) * nk;
-        uint32_t kmin = 0xffffffffu, kmax = 0u;
-        int base = 0;
-        for (int jr = 0, s = 0; jr < rows_here; ++jr) {
-            for (int k0 = 0; k0 < nk; k0 += kPeakThreads, ++s) {
-                int pre = 0, total = 0;
 #pragma unroll
-                for (int w2 = 0; w2 < kPeakWaves; ++w2) {
-                    const int c = __popcll(sc.seg_mask[s][w2]);
-                    pre += w2 < wave ? c : 0;
-                    total += c;
-                }
-                const uint64_t msk = sc.seg_mask[s][wave];
-                const bool keep = (msk >> lane) & 1u;
-                if (keep) {
-                    const int k = k0 + tid;
-                    const int32_t v = mid[(jr + 1) * W + k + 1];
-                    out[base + pre + rank_below(msk)] = Cand{v, static_cast<int32_t>(cell_base + jr * nk + k)};
-                    const uint32_t key = sort_key(v);
-                    atomicAdd(&sc.hist[key & 0xffu], 1u);
-                    kmin = min(kmin, key);
-                    kmax = max(kmax, key);
-                }
-                base += total;
-            }
+            for (int i = 0; i < CPL; ++i)
+                pb[i] = INT_MIN;
         }
-        kmin = wave_min_u32(kmin);
-        kmax = wave_max_u32(kmax);
+        view(r1, x1, cur);
+    }
+    for (int i = tid; i < S * kDigits; i += kPeakThreads)
+        hist[i] = 0u;
+    lds_barrier();
+
+    const int32_t thr = a.threshold;
+    uint32_t run_min = 0xffffffffu, run_max = 0u;
+    for (int l = l0; l < l1; ++l) {
+        const int par = (l - l0) & 1;
+        SliceView<CPL> nxt;
+        if (l + 1 < g.n_d0) {
+            view(raw, rx, nxt);
+        } else {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i)
+                nxt.b[i] = INT_MIN;
+        }
+        if (l + 2 < g.n_d0 && l + 2 <= l1)
+            load(l + 2, raw, rx);
+
+        uint32_t mask = 0u;
+        int32_t vmax = INT_MIN, vmin = INT_MAX;
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            const int32_t v = cur.v[i];
+            const int32_t before = max3i(pb[i], cur.au[i], i == 0 ? cur.left : cur.v[i - 1]);
+            const int32_t after = max3i(nxt.b[i], cur.ad[i], i == CPL - 1 ? cur.right : cur.v[i + 1]);
+            const bool keep = v >= thr && v > before && v >= after;
+            mask |= keep ? (1u << i) : 0u;
+            vmax = keep ? max(vmax, v) : vmax;
+            vmin = keep ? min(vmin, v) : vmin;
+        }
+        // at most CPL / 2 survivors per lane: kappa neighbours cannot both pass
+        const int s = l - l0;
+        const int n = __popc(mask);
+        const uint64_t b0 = __ballot(n & 1);
+        const uint64_t b1 = __ballot(n & 2);
+        const uint64_t b2 = __ballot(n & 4);
+        const int pre = rank_below(b0) + 2 * rank_below(b1) + 4 * rank_below(b2);
+        const int tot = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+        // (every loop over a lane's cells is unrolled with constant indices:
+        // a register array indexed at run time costs a wait on the loads in
+        // flight)
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            if ((mask >> i) & 1u)
+                atomicAdd(&hist[s * kDigits + (sort_key(cur.v[i]) & 0xffu)], 1u);
+        }
+        const uint32_t kmn = wave_min_u32(mask ? sort_key(vmax) : 0xffffffffu);
+        const uint32_t kmx = wave_max_u32(mask ? sort_key(vmin) : 0u);
         if (lane == 0) {
-            sc.red_min[wave] = kmin;
-            sc.red_max[wave] = kmax;
+            wcnt[par][wave] = tot;
+            wmin[par][wave] = kmn;
+            wmax[par][wave] = kmx;
         }
         lds_barrier();
-        uint32_t mn = 0xffffffffu, mx = 0u;
+        int base = 0, all = 0;
+        uint32_t bmin = 0xffffffffu, bmax = 0u;
 #pragma unroll
         for (int w2 = 0; w2 < kPeakWaves; ++w2) {
-            mn = min(mn, sc.red_min[w2]);
-            mx = max(mx, sc.red_max[w2]);
+            const int c = wcnt[par][w2];
+            base += w2 < wave ? c : 0;
+            all += c;
+            bmin = min(bmin, wmin[par][w2]);
+            bmax = max(bmax, wmax[par][w2]);
         }
-        if (tid == 0) {
-            a.w.s0.cnt0[static_cast<int64_t>(e) * a.w.s0.n_blocks0 + l * bps + rb] = base;
-            if (base > 0) {
-                atomicMin(&a.w.state[e].key_min, mn);
-                atomicMax(&a.w.state[e].key_max, mx);
+        // A list never holds more than cap0 survivors (an independent set of
+        // the king's graph); the clamps only keep memory safe.
+        if (mask) {
+            Cand *out = cands + s * cap0;
+            const int32_t cell0 = (l * n_phi + j) * nk + ri * CPL;
+            int m = base + pre;
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) {
+                if ((mask >> i) & 1u) {
+                    if (m < cap0)
+                        out[m] = Cand{cur.v[i], cell0 + i};
+                    ++m;
+                }
             }
         }
-        const int chunk = (l * bps + rb) / a.w.s0.cb;
-        uint32_t *hrow = a.w.hist + (static_cast<int64_t>(e) * a.w.hist_chunks + chunk) * kDigits;
-        for (int i = tid; i < kDigits; i += kPeakThreads) {
-            if (a.w.s0.cb == 1)
-                hrow[i] = sc.hist[i];
-            else if (sc.hist[i])
-                atomicAdd(&hrow[i], sc.hist[i]);
+        if (tid == 0) {
+            scnt[s] = min(all, cap0);
+            run_min = min(run_min, bmin);
+            run_max = max(run_max, bmax);
         }
-        lds_barrier();   // the histogram and the ring are reused
+#pragma unroll
+        for (int i = 0; i < CPL; ++i)
+            pb[i] = cur.b[i];
+        cur = nxt;
+    }
+    lds_barrier();
+    // write out the walk: counts, lists and first-digit histograms
+    const int n_s = l1 - l0;
+    const int64_t n_blocks0 = a.w.s0.n_blocks0;
+    for (int s = 0; s < n_s; ++s) {
+        const int l = l0 + s;
+        const int64_t list = static_cast<int64_t>(e) * n_blocks0 + static_cast<int64_t>(l) * a.bands + band;
+        const int c = scnt[s];
+        if (tid == 0)
+            a.w.s0.cnt0[list] = c;
+        Cand *dst = a.w.s0.stage + list * cap0;
+        for (int i = tid; i < c; i += kPeakThreads)
+            dst[i] = cands[s * cap0 + i];
+        const int chunk = (l * a.bands + band) / a.w.s0.cb;
+        uint32_t *hrow = a.w.hist + (static_cast<int64_t>(e) * a.w.hist_chunks + chunk) * kDigits;
+        const uint32_t h = hist[s * kDigits + tid];
+        if (a.w.s0.cb == 1)
+            hrow[tid] = h;
+        else if (h)
+            atomicAdd(&hrow[tid], h);
+    }
+    if (tid == 0 && run_min <= run_max) {
+        atomicMin(&a.w.state[e].key_min, run_min);
+        atomicMax(&a.w.state[e].key_max, run_max);
     }
 }
 
@@ -530,13 +570,13 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int p
 }  // namespace
 
 int32_t peak_blocks_per_event(const GridArgs &g) {
-    return g.n_d0 * ((g.n_phi + kPeakRows - 1) / kPeakRows);
+    return g.n_d0 * peak_layout(g).bands;
 }
 
 int32_t peak_block_cap(const GridArgs &g) {
-    // Survivors of one block form an independent set of the king's graph on
-    // kPeakRows x n_kappa cells: at most ceil(rows/2) * ceil(n_kappa/2).
-    return ((kPeakRows + 1) / 2) * ((g.n_kappa + 1) / 2);
+    // Survivors of one block and slice form an independent set of the king's
+    // graph on the rows it touches: at most ceil(rows/2) * ceil(n_kappa/2).
+    return ((peak_layout(g).rows_per_band + 1) / 2) * ((g.n_kappa + 1) / 2);
 }
 
 int32_t peak_blocks_per_chunk(const GridArgs &g) {
@@ -547,11 +587,15 @@ int32_t peak_blocks_per_chunk(const GridArgs &g) {
 
 hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_t n_events,
                         int32_t threshold, const SortWork &w, hipStream_t stream) {
+    const PeakLayout lay = peak_layout(g);
     PeakArgs a{};
     a.g = g;
     a.acc = acc;
     a.threshold = threshold;
-    a.blocks_per_slice = (g.n_phi + kPeakRows - 1) / kPeakRows;
+    a.lpr = lay.lpr;
+    a.rpw = lay.rpw;
+    a.wpr = lay.wpr;
+    a.bands = lay.bands;
     a.w = w;
     if (w.s0.cb > 1) {
         // blocks add into shared first-pass histogram rows
@@ -559,21 +603,24 @@ hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_
         if (e != hipSuccess)
             return e;
     }
-    if (kPeakRows * ((g.n_kappa + kPeakThreads - 1) / kPeakThreads) > kMaxSegs)
-        return hipErrorInvalidValue;   // more kappa bins than one band's survivor bookkeeping holds
-    const size_t lds = (static_cast<size_t>(g.n_d0 > 1 ? 4 : 1) * kHaloRows * (g.n_kappa + 2) + 2 * kPeakThreads) *
-                       sizeof(int32_t);
-    const void *fn = u16 ? reinterpret_cast<const void *>(peak_kernel<true>)
-                         : reinterpret_cast<const void *>(peak_kernel<false>);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess)
-        return e;
-    const int32_t slice_chunks = (g.n_d0 + kPeakSlices - 1) / kPeakSlices;
-    dim3 grid(static_cast<unsigned>(a.blocks_per_slice * slice_chunks), static_cast<unsigned>(n_events));
+    // 16-byte row loads when every row starts on a 16-byte boundary
+    const bool vec = g.row_dwords % 4 == 0 && (reinterpret_cast<uintptr_t>(acc) & 15u) == 0;
+    // slices per block: as many as kPeakLdsBudget of staged lists allows (a
+    // list of a grid the vote accepts, n_kappa <= 1200 or so, is a few KB)
+    const size_t per_slice = kDigits * sizeof(uint32_t) + static_cast<size_t>(w.s0.cap0) * sizeof(Cand);
+    if (per_slice > kPeakLdsBudget)
+        return hipErrorInvalidValue;
+    a.slices = static_cast<int32_t>(std::min<size_t>(kPeakSlices, kPeakLdsBudget / per_slice));
+    const size_t lds = a.slices * per_slice;
+    const int32_t slice_chunks = (g.n_d0 + a.slices - 1) / a.slices;
+    dim3 grid(static_cast<unsigned>(lay.bands * slice_chunks), static_cast<unsigned>(n_events));
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(kPeakThreads), lds, stream, a);
+    };
     if (u16)
-        hipLaunchKernelGGL(peak_kernel<true>, grid, dim3(kPeakThreads), lds, stream, a);
+        vec ? go(peak_kernel<true, true>) : go(peak_kernel<true, false>);
     else
-        hipLaunchKernelGGL(peak_kernel<false>, grid, dim3(kPeakThreads), lds, stream, a);
+        vec ? go(peak_kernel<false, true>) : go(peak_kernel<false, false>);
     return hipGetLastError();
 }
 

@@ -230,6 +230,46 @@ def test_peaks_on_arbitrary_accumulators(shape, hi, signed):
         np.testing.assert_array_equal(v, rv)
 
 
+@pytest.mark.parametrize("shape,acc_type,offset", [
+    ((1, 6, 512), "i32", 0),       # a row is two wavefronts
+    ((1, 7, 640), "i32", 0),       # three wavefronts per row: blocks straddle rows
+    ((2, 5, 1024), "i32", 0),      # four wavefronts per row
+    ((1, 4, 900), "i32", 0),       # a partial fourth wavefront per row
+    ((3, 4, 1000), "u16", 0),      # 125 lanes per row
+    ((2, 9, 64), "i32", 1),        # accumulator not 16-byte aligned
+    ((4, 13, 256), "u16", 2),
+    ((3, 7, 6), "u16", 0),         # three dwords per row
+    ((11, 6, 16), "u16", 0),       # more d0 slices than one block walks
+    ((19, 5, 40), "i32", 0),
+])
+def test_peak_search_layouts(shape, acc_type, offset):
+    """Every lane and block layout of the peak search agrees with the oracle:
+    rows spanning several wavefronts, unaligned accumulators, partial lanes
+    and long d0 walks."""
+    n_d0, n_phi, n_kappa = shape
+    u16 = acc_type == "u16"
+    if n_d0 > 1:
+        grid = make_grid(n_phi, n_kappa, n_d0=n_d0, d0_range=(-1.0, 1.0), acc_type=acc_type)
+    else:
+        grid = make_grid(n_phi, n_kappa, acc_type=acc_type)
+    ctx = hough.HoughContext(grid)
+    rng = np.random.default_rng(n_d0 * 1000003 + n_phi * 1009 + n_kappa)
+    cells = n_d0 * n_phi * n_kappa
+    for hi, t in ((3, 1), (40, 20), (65535 if u16 else 100000, 5)):
+        a = rng.integers(0, hi + 1, size=shape).astype(np.int64)
+        host = a.astype(np.uint16).view(np.int16) if u16 else a.astype(np.int32)
+        buf = torch.zeros(cells + offset, dtype=torch.int16 if u16 else torch.int32, device=_dev())
+        buf[offset:] = torch.from_numpy(host.reshape(-1)).to(_dev())
+        out, nf = ctx.peaks(buf[offset:], t)
+        torch.cuda.synchronize()
+        v, c, n = hough.cands_to_numpy(out, nf.item())
+        rv, rc, rn = oracle.peaks(a, t)
+        print(f"[peaks] {shape} {acc_type} +{offset}: {rn} candidates at threshold {t}", flush=True)
+        assert n == rn
+        np.testing.assert_array_equal(c, rc)
+        np.testing.assert_array_equal(v, rv)
+
+
 def test_invalid_arguments_raise():
     ctx = hough.HoughContext(synth.GRID_2D_SMALL, max_hits=100)
     x = _t(np.zeros(101))
