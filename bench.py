@@ -52,10 +52,11 @@ def parse_args():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-events", type=int, default=64)
     ap.add_argument("--skip-per-event", action="store_true", help="skip the per-event-launch comparison")
+    ap.add_argument("--skip-3d", action="store_true", help="skip the displaced-vertex (3D) batch leg")
     ap.add_argument("--serve-rates", default="1000,5000,20000",
                     help="offered rates (events/s) of the served stream; empty to skip")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="offered seconds of arrivals per rate")
-    ap.add_argument("--serve-max-events", type=int, default=20000, help="cap on arrivals per rate")
+    ap.add_argument("--serve-events", type=int, default=20000, help="measured arrivals per rate")
+    ap.add_argument("--serve-warmup", type=int, default=1000, help="arrivals per rate before the measured ones")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -181,10 +182,54 @@ def per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off, eve
             "closed_loop_events": len(lat)}
 
 
+def displaced_3d(hough, torch, dev, synth, log_fn, n_events=8, reps=10):
+    """The displaced-vertex workload (35,000 hits, 64 d0 x 512 phi0 x 256
+    kappa uint16, threshold 5) as one batch of n_events through the same
+    graph path: ms per event for the whole batch and for its vote kernel."""
+    wc = synth.CONFIGS[3]
+    b = synth.pack_events([synth.gen_config_event(3, i) for i in range(n_events)])
+    x = torch.from_numpy(b.x).to(dev)
+    y = torch.from_numpy(b.y).to(dev)
+    ctx = hough.HoughContext(wc.grid, device=dev, max_events=n_events, max_hits=b.n_hits)
+    cap = ctx.spec.max_candidates()
+    cand_off = np.arange(n_events + 1, dtype=np.int64) * cap
+    cands = torch.empty((n_events * cap, 2), dtype=torch.int32, device=dev)
+    n_found = torch.empty(n_events, dtype=torch.int32, device=dev)
+    n_votes = torch.empty(n_events, dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.event_batch(b.hit_off, x, y, wc.threshold, cand_off=cand_off, cands=cands, n_found=n_found,
+                        n_votes=n_votes)
+
+    log_fn(f"displaced-vertex batch of {n_events}")
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.set_timing(True)
+    vote = []
+    for _ in range(4):
+        step()
+        vote.append(ctx.get_timing()[0])
+    ctx.set_timing(False)
+    evals = int(b.n_hits) * wc.grid.n_d0 * wc.grid.n_phi
+    return {"workload": "displaced_3d_35k_64x512x256_u16", "events": n_events, "hits": int(b.n_hits),
+            "ms_per_event": 1e3 * dt / n_events, "events_per_s": n_events / dt,
+            "vote_ms_per_event": float(np.mean(vote[1:])) / n_events,
+            "evaluations_per_s": evals / dt, "votes_per_event": int(n_votes.sum().item()) // n_events,
+            "candidates_per_event": int(n_found.sum().item()) // n_events}
+
+
 def served_stream(args, hough, synth, batch, log_fn):
     """Open-loop served stream: Poisson arrivals of 80 % batch-workload 2D and
     20 % displaced 3D events at each offered rate, through the library's
-    server (continuous batching, 2 lanes per grid, 2 ms deadline)."""
+    server (continuous batching, 2 lanes per grid, 2 ms deadline).  The first
+    serve_warmup arrivals of each rate are not measured; a deadline miss is a
+    measured event that waited longer than the deadline for its launch."""
     rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
     if not rates:
         return None
@@ -200,15 +245,17 @@ def served_stream(args, hough, synth, batch, log_fn):
     srv = hough.Server(grids, thr, lanes=2, batch_events=[64, 8], batch_hits=[1 << 22, 1 << 19], deadline_ms=2.0,
                        queue_limit=4096, keep_candidates=False)
     out = []
+    deadline_s = 2e-3
     try:
         for rate in rates:
-            n = max(200, min(int(rate * args.serve_seconds), args.serve_max_events))
+            warm = max(0, args.serve_warmup)
+            n = warm + max(1, args.serve_events)
             rng = np.random.default_rng(np.random.SeedSequence([synth.BASE_SEED + 5, int(rate)]))
             kind = (rng.uniform(size=n) < 0.2).astype(np.int32)
             pick = np.where(kind == 1, n2 + rng.integers(0, len(pool) - n2, size=n),
                             rng.integers(0, n2, size=n)).astype(np.int32)
             arrivals = synth.poisson_arrivals(rate, n, stream=1)
-            log_fn(f"served stream: {n} events at {rate:.0f}/s")
+            log_fn(f"served stream: {warm} + {n - warm} events at {rate:.0f}/s")
             status = {}
             import threading
             th = threading.Thread(target=lambda: status.update(
@@ -217,26 +264,30 @@ def served_stream(args, hough, synth, batch, log_fn):
             th.start()
             res = []
             t_wall = time.time()
+            limit = 60 + 3 * n / rate
             while th.is_alive() or len(res) < n:
                 res += srv.poll(wait_ms=20, cand_cap=0)
                 if not th.is_alive():
                     accepted = int((status["s"] == 0).sum())
                     if len(res) >= accepted:
                         break
-                if time.time() - t_wall > 60 + 2 * args.serve_seconds:
+                if time.time() - t_wall > limit:
                     raise RuntimeError(f"served stream at {rate}/s: {len(res)} of {n} events returned in time")
             th.join()
-            ok = [r for r in res if r["status"] == 0]
+            # statistics over the measured arrivals only (tag = arrival index)
+            ok = [r for r in res if r["status"] == 0 and r["tag"] >= warm]
             lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
-            t_end = max(r["t_done"] for r in ok)
-            span = t_end - t_start
-            refused = int((status["s"] != 0).sum())
+            wait = np.array([r["t_launch"] - r["t_submit"] for r in ok])
+            t_first = t_start + float(arrivals[warm])
+            span = max(r["t_done"] for r in ok) - t_first
+            refused = int((status["s"][warm:] != 0).sum())
             votes = sum(int(r["n_votes"]) for r in ok)
-            out.append({"offered_per_s": rate, "events": n, "completed": len(ok), "refused": refused,
+            out.append({"offered_per_s": rate, "warmup_events": warm, "events": n - warm, "completed": len(ok),
+                        "refused": refused, "deadline_misses": int((wait > deadline_s).sum()),
                         "achieved_events_per_s": len(ok) / span, "votes_per_s": votes / span,
                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                         "mean_batch_events": float(np.mean([r["batch_events"] for r in ok])),
-                        "share_3d": float(kind.mean())})
+                        "share_3d": float(kind[warm:].mean())})
     finally:
         srv.close()
     return out
@@ -340,6 +391,8 @@ def main():
         del src, dst
 
     line_extra = {}
+    if not args.skip_3d:
+        line_extra["displaced_3d"] = displaced_3d(hough, torch, dev, synth, log)
     served = served_stream(args, hough, synth, batch, log)
     if served is not None:
         line_extra["served"] = served
