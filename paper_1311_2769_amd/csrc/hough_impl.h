@@ -64,6 +64,7 @@ struct GridArgs {
     float kappa_min, kappa_scale;
     int32_t row_dwords;   // dwords per (d0, phi0) row in global memory
     int32_t bin_bits;     // kappa_scale >= 1 and kappa_min != +0: the vote's unsigned range test is exact
+    float near_lim;       // 3D: 0.5 - E of the one-reciprocal quotient (vote_near_limit), or -1: exact quotients only
     int64_t cells;        // cells per event
     int64_t acc_dwords;   // dwords per event accumulator
 };
@@ -133,6 +134,9 @@ struct VoteShape {
 // ---------------------------------------------------------------------------
 bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa);
 size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa);
+// 0.5 - E, where E bounds |kf0 - kf| on |kf| <= n_kappa + 2 for the 3D
+// one-reciprocal quotient (twice the derived error), or -1 when E > 1/64.
+float vote_near_limit(const GridArgs &g);
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
 TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused);
 int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);

@@ -61,7 +61,9 @@
 // order to its staging list; the accumulator need not reach HBM at all.
 #pragma clang fp contract(off)
 
+#include <algorithm>
 #include <climits>
+#include <cmath>
 #include <type_traits>
 
 #include "hough_impl.h"
@@ -249,14 +251,60 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         const float kf = (kappa - kmin) * kscale;
         return bin_of(kf, i, valid, bits);
     };
+    // 3D quotient by one reciprocal (fast hits, GridArgs::near_lim > 0).
+    // q0 = (u - d) * rcp(den) is within 2^-22 |q| of the correctly rounded
+    // quotient q (rcp is within 1 ulp); on |kf| <= n_kappa + 2 that puts the
+    // kf0 built from q0 within E of the exact kf, a grid constant the host
+    // derives (vote_near_limit) with a factor 2 to spare.  When kf0 is at
+    // least E from every integer, floor(kf0) = floor(kf), and the range test
+    // (its limits 0 and n_kappa are integers) decides alike; beyond the band
+    // kf0 and kf are both out of range.  Lanes whose kf0 is nearer an integer
+    // than E redo the quotient exactly, so every bin is the exact one.
+    const float near_lim = g.near_lim;
+    auto bin_approx = [&](const float4 &h, int i, bool valid, auto bits, float &num, float &den, bool &near) -> int {
+        const float u = h.y * c[i] - h.x * s[i];
+        num = u - d;
+        den = (h.z - d2 * u) + dd;
+        const float kf0 = kf_one_rcp(num, den, kmin, kscale);
+        near = kf_near_integer(kf0, near_lim);
+        return bin_of(kf0, i, valid, bits);
+    };
+    auto bin_exact = [&](float num, float den, int i, bool valid, auto bits) -> int {
+        return bin_of(kf_exact(num, den, kmin, kscale), i, valid, bits);
+    };
     auto vote = [&](int kk, int i) { lds_add(&lds[kk * stride + rowoff[i]], 1u); };
     // Evaluate and vote two hits of this lane group (valid: the hit exists).
+    // fast: 0 the division operator, 1 the hoisted exact quotient, 2 (3D) the
+    // one-reciprocal quotient with exact redos.
     auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast, auto bits) {
         int ka[RPT], kb[RPT];
+        if constexpr (D3 && decltype(fast)::value == 2) {
+            float na[RPT], da[RPT], nb[RPT], db[RPT];
+            bool fa[RPT], fb[RPT];
+            bool any_a = false, any_b = false;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            ka[i] = bin(ha, i, va, fast, bits);
-            kb[i] = bin(hb, i, vb, fast, bits);
+            for (int i = 0; i < RPT; ++i) {
+                ka[i] = bin_approx(ha, i, va, bits, na[i], da[i], fa[i]);
+                kb[i] = bin_approx(hb, i, vb, bits, nb[i], db[i], fb[i]);
+                any_a |= fa[i];
+                any_b |= fb[i];
+            }
+            // one wave-uniform branch for both hits, so their chains interleave
+            if (__ballot(any_a || any_b)) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    if (fa[i])
+                        ka[i] = bin_exact(na[i], da[i], i, va, bits);
+                    if (fb[i])
+                        kb[i] = bin_exact(nb[i], db[i], i, vb, bits);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                ka[i] = bin(ha, i, va, fast, bits);
+                kb[i] = bin(hb, i, vb, fast, bits);
+            }
         }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
@@ -360,7 +408,10 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             carry_v = ts.hits[whole + tid];      // nothing writes the staged hits until the next barrier
         if (!last)
             fetch(b0 + kHitBlock);
-        sweep(0, whole, std::true_type{});
+        if (D3 && near_lim > 0.0f)
+            sweep(0, whole, std::integral_constant<int, D3 ? 2 : 1>{});
+        else
+            sweep(0, whole, std::true_type{});
         sweep(SLOW_END - n_slow, SLOW_END, std::false_type{});
         carry = carry_next;
     }
@@ -889,6 +940,28 @@ bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa) {
         return false;
     // dynamic tile + static scratch (staged hits, compaction and reductions)
     return vote_lds_bytes(s, n_kappa) + sizeof(TileScratch<1024>) <= 160u * 1024u;
+}
+
+float vote_near_limit(const GridArgs &g) {
+    // Bound chain (one IEEE rounding per operation; ulp(x) = 2^(floor(log2 x) - 23)):
+    //   |kf| <= K = n_kappa + 2 gives |t| <= T = max(K, 2) / kappa_scale (1 + 2^-20)
+    //   for t = RN(2q - kappa_min), and |q| <= Q = (T + |kappa_min|) / 2 (1 + 2^-20);
+    //   |q0 - q| <= 2^-22 Q, so |t0 - t| <= 2^-21 Q + ulp(2T) and
+    //   |kf0 - kf| <= kappa_scale |t0 - t| (1 + 2^-20) + ulp(2K).
+    const double ks = g.kappa_scale;
+    const double km = std::fabs(static_cast<double>(g.kappa_min));
+    if (!(ks > 0.0) || !std::isfinite(ks) || !std::isfinite(km))
+        return -1.0f;
+    auto ulp = [](double x) { return std::ldexp(1.0, std::ilogb(x) - 23); };
+    const double K = static_cast<double>(g.n_kappa) + 2.0;
+    const double T = std::max(K, 2.0) / ks * (1.0 + 0x1.0p-20);
+    const double Q = (T + km) / 2.0 * (1.0 + 0x1.0p-20);
+    const double et = 0x1.0p-21 * Q + ulp(2.0 * T);
+    const double ekf = ks * et * (1.0 + 0x1.0p-20) + ulp(2.0 * K);
+    const double E = 2.0 * ekf;
+    if (!(E <= 1.0 / 64.0))
+        return -1.0f;
+    return static_cast<float>(0.5 - E);
 }
 
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused) {

@@ -60,4 +60,27 @@ __device__ __forceinline__ float quot_apply(float a, float b, float y) {
     return __builtin_fmaf(r1, y, q1);
 }
 
+// The 3D vote's fractional kappa bin from a quotient by one reciprocal:
+// kf0 = (2 (num * rcp(den)) - kappa_min) * kappa_scale, with the same two
+// roundings after the quotient as the exact kf.  num * rcp(den) is within
+// 2^-22 |q| of the correctly rounded quotient q (rcp is within 1 ulp) when
+// both operands are in the range above.
+__device__ __forceinline__ float kf_one_rcp(float num, float den, float kmin, float kscale) {
+    const float q0 = num * __builtin_amdgcn_rcpf(den);
+    return __builtin_fmaf(2.0f, q0, -kmin) * kscale;
+}
+
+// The exact kf from the correctly rounded quotient (the division operator's
+// own steps, valid in the same range).
+__device__ __forceinline__ float kf_exact(float num, float den, float kmin, float kscale) {
+    const float q = quot_apply(num, den, quot_recip(den));
+    return __builtin_fmaf(2.0f, q, -kmin) * kscale;
+}
+
+// kf0 lies within 0.5 - near_lim of an integer: its floor may differ from
+// the exact kf's, so the exact kf must decide.
+__device__ __forceinline__ bool kf_near_integer(float kf0, float near_lim) {
+    return fabsf(__builtin_amdgcn_fractf(kf0) - 0.5f) > near_lim;
+}
+
 }  // namespace hough

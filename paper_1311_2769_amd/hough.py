@@ -29,7 +29,7 @@ SYMBOLS = (
     "hough_autotune", "hough_tune_lookup",
     "hough_server_create", "hough_server_destroy", "hough_server_clock", "hough_server_submit",
     "hough_server_replay", "hough_server_poll", "hough_server_stats",
-    "hough_selftest_divide", "hough_selftest_angles", "hough_diag_rates", "hough_status_str", "hough_last_error", "hough_version",
+    "hough_selftest_divide", "hough_selftest_angles", "hough_selftest_near", "hough_diag_rates", "hough_status_str", "hough_last_error", "hough_version",
 )
 
 
@@ -133,6 +133,10 @@ def load(path: str = LIB_PATH):
     lib.hough_selftest_angles.restype = i32
     lib.hough_selftest_angles.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float)]
+    lib.hough_selftest_near.restype = i32
+    lib.hough_selftest_near.argtypes = [i64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, i32,
+                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.hough_status_str.restype = ctypes.c_char_p
     lib.hough_status_str.argtypes = [i32]
     lib.hough_last_error.restype = ctypes.c_char_p
@@ -358,6 +362,16 @@ def selftest_angles(n: int, seed: int = 1):
     _check(lib.hough_selftest_angles(int(n), int(seed), ctypes.byref(ea), ctypes.byref(es)),
            "hough_selftest_angles")
     return ea.value, es.value
+
+
+def selftest_near(n: int, kappa_min: float, kappa_scale: float, n_kappa: int, seed: int = 1):
+    """(mismatches, redone, checked) of the device check of the 3D one-reciprocal quotient."""
+    lib = load()
+    bad, redo, used = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib.hough_selftest_near(int(n), int(seed), float(kappa_min), float(kappa_scale), int(n_kappa),
+                                   ctypes.byref(bad), ctypes.byref(redo), ctypes.byref(used)),
+           "hough_selftest_near")
+    return bad.value, redo.value, used.value
 
 
 def acc_to_numpy(acc, spec: GridSpec):
