@@ -199,7 +199,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     asm volatile("v_mov_b32 %0, %1" : "=v"(trash_v) : "s"(trash));
     const float4 *__restrict__ hrec = a.hits;
     const uint2 *__restrict__ rrow = a.ranges + static_cast<int64_t>(l) * a.range_stride;
-    const int64_t rstep = a.range_step;
+    const int64_t rmask = a.range_step ? -1 : 0;   // per-hit ranges, or the one all-tiles entry
 
     // Kappa bin of one staged hit (x, y, z, w) at row i of this lane: the bin
     // to add to, which is the spare column when the hit casts no vote there.
@@ -364,7 +364,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int64_t h = min(b0 + q * STAGERS + tid, h_end - 1);
-            pr[q] = rrow[h * rstep];
+            pr[q] = rrow[h & rmask];
             ph[q] = hrec[h];
         }
     };
@@ -389,12 +389,12 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
                 bf = atomicAdd(&ts.n_kept[parity][0], __popcll(mf));
             if (lane == 0 && ms)
                 bs = atomicAdd(&ts.n_kept[parity][1], __popcll(ms));
-            bf = __shfl(bf, 0, 64);
-            bs = __shfl(bs, 0, 64);
-            if (keep && fast)
-                ts.hits[bf + rank_below(mf)] = ph[q];
-            else if (keep)
-                ts.hits[SLOW_END - 1 - (bs + rank_below(ms))] = ph[q];
+            // every lane is active here, so the first lane is lane 0
+            bf = __builtin_amdgcn_readfirstlane(bf);
+            bs = __builtin_amdgcn_readfirstlane(bs);
+            const int slot = fast ? bf + rank_below(mf) : SLOW_END - 1 - (bs + rank_below(ms));
+            if (keep)
+                ts.hits[slot] = ph[q];
         }
         lds_barrier();
         const int n_fast = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][0]);   // with the carried hits
