@@ -46,6 +46,13 @@ def _bind(lib):
     lib.hough_oracle_peaks.restype = ctypes.c_int64
     lib.hough_oracle_peaks.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i64p,
                                        ctypes.c_int64, ctypes.c_int64, i64p, i64p]
+    i32, f32 = ctypes.c_int32, ctypes.c_float
+    lib.hough_oracle_vertex_vote.restype = ctypes.c_int64
+    lib.hough_oracle_vertex_vote.argtypes = [ctypes.c_int64, i64p, i64p, ctypes.c_int64,
+                                             i32, f32p, i32, f32p, f32p, i32,
+                                             i32, f32p, f32, f32, i32, f32p, f32, f32, i64p]
+    lib.hough_oracle_vertex_peaks.restype = ctypes.c_int64
+    lib.hough_oracle_vertex_peaks.argtypes = [i32, i32, i64p, ctypes.c_int64, ctypes.c_int64, i64p, i64p]
     return lib
 
 
@@ -115,3 +122,51 @@ def find(x, y, grid, threshold, cap=None, *, library=None):
     acc, n_votes = vote(x, y, grid, library=library)
     v, c, n = peaks(acc, threshold, cap, library=library)
     return acc, n_votes, v, c, n
+
+
+def vertex_vote(cand_votes, cand_cells, track_threshold, grid, vgrid, *, library=None):
+    """Second transform (Section 5): vertex accumulator int64 [n_x, n_y] and the votes cast."""
+    L = library or lib()
+    cv = np.ascontiguousarray(cand_votes, dtype=np.int64)
+    cc = np.ascontiguousarray(cand_cells, dtype=np.int64)
+    if cv.shape != cc.shape or cv.ndim != 1:
+        raise ValueError("candidate votes and cells must be 1-D arrays of equal length")
+    cos_phi, sin_phi = _f32(grid.cos_phi), _f32(grid.sin_phi)
+    d0 = None if grid.d0 is None else _f32(grid.d0)
+    xc, yc = _f32(vgrid.x_centre), _f32(vgrid.y_centre)
+    vacc = np.zeros(vgrid.n_x * vgrid.n_y, dtype=np.int64)
+    n = L.hough_oracle_vertex_vote(cv.shape[0], _ptr(cv, ctypes.c_int64), _ptr(cc, ctypes.c_int64),
+                                   int(track_threshold), grid.n_d0,
+                                   None if d0 is None else _ptr(d0, ctypes.c_float), grid.n_phi,
+                                   _ptr(cos_phi, ctypes.c_float), _ptr(sin_phi, ctypes.c_float), grid.n_kappa,
+                                   vgrid.n_x, _ptr(xc, ctypes.c_float), float(vgrid.x_min), float(vgrid.x_scale),
+                                   vgrid.n_y, _ptr(yc, ctypes.c_float), float(vgrid.y_min), float(vgrid.y_scale),
+                                   _ptr(vacc, ctypes.c_int64))
+    if n < 0:
+        raise ValueError("oracle rejected the vertex-vote arguments")
+    return vacc.reshape(vgrid.n_x, vgrid.n_y), int(n)
+
+
+def vertex_peaks(vacc, threshold, cap=None, *, library=None):
+    """Sorted vertex candidates (votes, cells) -- at most ``cap`` -- and n_found."""
+    L = library or lib()
+    vacc = np.ascontiguousarray(vacc, dtype=np.int64)
+    n_x, n_y = vacc.shape
+    if cap is None:
+        cap = vacc.size
+    votes = np.zeros(max(cap, 1), dtype=np.int64)
+    cells = np.zeros(max(cap, 1), dtype=np.int64)
+    n = L.hough_oracle_vertex_peaks(n_x, n_y, _ptr(vacc, ctypes.c_int64), int(threshold), int(cap),
+                                    _ptr(votes, ctypes.c_int64), _ptr(cells, ctypes.c_int64))
+    if n < 0:
+        raise ValueError("oracle rejected the vertex peak arguments")
+    m = min(n, cap)
+    return votes[:m].copy(), cells[:m].copy(), int(n)
+
+
+def find_vertices(cand_votes, cand_cells, track_threshold, grid, vgrid, vertex_threshold, cap=None, *,
+                  library=None):
+    """Second transform then peaks: (vacc, n_votes, votes, cells, n_found)."""
+    vacc, n = vertex_vote(cand_votes, cand_cells, track_threshold, grid, vgrid, library=library)
+    v, c, nf = vertex_peaks(vacc, vertex_threshold, cap, library=library)
+    return vacc, n, v, c, nf

@@ -38,8 +38,13 @@
  * kappa neighbours outside the grid are ignored.  Candidates are sorted by
  * votes descending, then cell index ascending, cell = (l*n_phi + j)*n_kappa + k.
  *
+ * Displaced vertices (Section 5): hough_oracle_vertex_vote and
+ * hough_oracle_vertex_peaks below take the candidates to a binned (x, y)
+ * vertex grid; their reading is stated above them.
+ *
  * Parity pins live in tests/test_oracle_pins.py.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -169,6 +174,141 @@ int64_t hough_oracle_peaks(int32_t n_d0, int32_t n_phi, int32_t n_kappa, const i
     }
     qsort(list, (size_t)n_found, sizeof(oracle_cand), cand_order);
     int64_t n_out = n_found < cap ? n_found : cap;
+    for (int64_t i = 0; i < n_out; ++i) {
+        out_votes[i] = list[i].votes;
+        out_cell[i] = list[i].cell;
+    }
+    free(list);
+    return n_found;
+}
+
+/*
+ * Displaced-vertex second transform (Section 5: a second Hough transform of
+ * the first one's result finds the vertices; a vertex V is the sinusoid
+ * d0 = V_y cos(phi0) - V_x sin(phi0) in the (phi0, d0) plane).  Reading:
+ * every first-transform candidate with votes >= track_threshold is the
+ * straight line through P0 = (-d0 sin phi0, d0 cos phi0) along (cos phi0,
+ * sin phi0), i.e. the vertices V with V_y c - V_x s = d0, using the bin
+ * centres of its cell.  It votes into a binned (x, y) vertex grid once per
+ * column when |c| >= |s| (the line's y at each column centre) and once per
+ * row otherwise (its x at each row centre), every operation one binary32
+ * operation in the order written:
+ *     column ix:  y = (d0 + x_centre[ix] * s) / c,  fy = (y - y_min) * y_scale,
+ *                 vote (ix, (int)fy) when 0 <= fy < n_y;
+ *     row iy:     x = (y_centre[iy] * c - d0) / s,  fx = (x - x_min) * x_scale,
+ *                 vote ((int)fx, iy) when 0 <= fx < n_x.
+ * vacc is int64 [n_x][n_y], overwritten; vertex cell = ix * n_y + iy.
+ * Returns the number of votes, or -1 on invalid arguments.
+ */
+int64_t hough_oracle_vertex_vote(int64_t n_cands, const int64_t *cand_votes, const int64_t *cand_cell,
+                                 int64_t track_threshold,
+                                 int32_t n_d0, const float *d0, int32_t n_phi, const float *cos_phi,
+                                 const float *sin_phi, int32_t n_kappa,
+                                 int32_t n_x, const float *x_centre, float x_min, float x_scale,
+                                 int32_t n_y, const float *y_centre, float y_min, float y_scale,
+                                 int64_t *vacc)
+{
+    if (n_cands < 0 || n_d0 < 1 || n_phi < 1 || n_kappa < 1 || n_x < 1 || n_y < 1 || !vacc)
+        return -1;
+    if (d0 == NULL && n_d0 != 1)
+        return -1;
+    memset(vacc, 0, (size_t)n_x * (size_t)n_y * sizeof(int64_t));
+    const int64_t track_cells = (int64_t)n_d0 * n_phi * n_kappa;
+    const float n_x_f = (float)n_x;
+    const float n_y_f = (float)n_y;
+    int64_t votes = 0;
+    for (int64_t i = 0; i < n_cands; ++i) {
+        if (cand_votes[i] < track_threshold)
+            continue;
+        const int64_t cell = cand_cell[i];
+        if (cell < 0 || cell >= track_cells)
+            return -1;
+        const int32_t l = (int32_t)(cell / ((int64_t)n_phi * n_kappa));
+        const int32_t j = (int32_t)((cell / n_kappa) % n_phi);
+        const float dt = d0 ? d0[l] : 0.0f;     /* the track's d0 */
+        const float c = cos_phi[j];
+        const float s = sin_phi[j];
+        if (fabsf(c) >= fabsf(s)) {
+            for (int32_t ix = 0; ix < n_x; ++ix) {
+                float t = x_centre[ix] * s;
+                float num = dt + t;
+                float yv = num / c;
+                float fy = (yv - y_min) * y_scale;
+                if (fy >= 0.0f && fy < n_y_f) {
+                    vacc[(int64_t)ix * n_y + (int32_t)fy] += 1;
+                    votes += 1;
+                }
+            }
+        } else {
+            for (int32_t iy = 0; iy < n_y; ++iy) {
+                float t = y_centre[iy] * c;
+                float num = t - dt;
+                float xv = num / s;
+                float fx = (xv - x_min) * x_scale;
+                if (fx >= 0.0f && fx < n_x_f) {
+                    vacc[(int64_t)(int32_t)fx * n_y + iy] += 1;
+                    votes += 1;
+                }
+            }
+        }
+    }
+    return votes;
+}
+
+/* Vertex candidates: the peak rule above on the (x, y) grid, neither axis
+ * periodic (neighbours outside are ignored), offsets ordered (dx, dy); sorted
+ * by votes descending then cell ascending.  Writes the first min(n_found, cap);
+ * returns n_found, or -1 on invalid arguments / allocation failure. */
+int64_t hough_oracle_vertex_peaks(int32_t n_x, int32_t n_y, const int64_t *vacc, int64_t threshold,
+                                  int64_t cap, int64_t *out_votes, int64_t *out_cell)
+{
+    if (n_x < 1 || n_y < 1 || !vacc || cap < 0)
+        return -1;
+    int64_t n_found = 0;
+    int64_t room = 256;
+    oracle_cand *list = (oracle_cand *)malloc((size_t)room * sizeof(oracle_cand));
+    if (!list)
+        return -1;
+    for (int32_t ix = 0; ix < n_x; ++ix) {
+        for (int32_t iy = 0; iy < n_y; ++iy) {
+            const int64_t val = vacc[(int64_t)ix * n_y + iy];
+            if (val < threshold)
+                continue;
+            int keep = 1;
+            for (int dx = -1; dx <= 1 && keep; ++dx) {
+                for (int dy = -1; dy <= 1; ++dy) {
+                    if (dx == 0 && dy == 0)
+                        continue;
+                    const int32_t xx = ix + dx;
+                    const int32_t yy = iy + dy;
+                    if (xx < 0 || xx >= n_x || yy < 0 || yy >= n_y)
+                        continue;
+                    const int64_t w = vacc[(int64_t)xx * n_y + yy];
+                    const int negative = dx != 0 ? dx < 0 : dy < 0;
+                    if (negative ? !(val > w) : !(val >= w)) {
+                        keep = 0;
+                        break;
+                    }
+                }
+            }
+            if (!keep)
+                continue;
+            if (n_found == room) {
+                room *= 2;
+                oracle_cand *grown = (oracle_cand *)realloc(list, (size_t)room * sizeof(oracle_cand));
+                if (!grown) {
+                    free(list);
+                    return -1;
+                }
+                list = grown;
+            }
+            list[n_found].votes = val;
+            list[n_found].cell = (int64_t)ix * n_y + iy;
+            n_found += 1;
+        }
+    }
+    qsort(list, (size_t)n_found, sizeof(oracle_cand), cand_order);
+    const int64_t n_out = n_found < cap ? n_found : cap;
     for (int64_t i = 0; i < n_out; ++i) {
         out_votes[i] = list[i].votes;
         out_cell[i] = list[i].cell;

@@ -109,3 +109,46 @@ def make_grid(n_phi: int, n_kappa: int, *, n_d0: int = 1, d0_range=None,
 GRID_2D_SMALL = make_grid(256, 128)
 GRID_2D = make_grid(1024, 512)
 GRID_3D = make_grid(512, 256, n_d0=64, d0_range=(-30.0, 30.0), acc_type=ACC_U16)
+
+
+@dataclasses.dataclass(frozen=True)
+class VertexGrid:
+    """Binned (x, y) vertex positions of the second transform (Section 5).
+
+    Bin ``i`` of an axis has centre ``lo + (i + 1/2) * (hi - lo) / n``; a
+    position p falls in bin ``(int)((p - min) * scale)`` when that is in
+    ``[0, n)``.  Centres, ``min`` and ``scale`` are fp32 inputs of both sides.
+    """
+    n_x: int
+    n_y: int
+    x_centre: np.ndarray    # fp32 [n_x]
+    y_centre: np.ndarray    # fp32 [n_y]
+    x_min: np.float32
+    x_scale: np.float32
+    y_min: np.float32
+    y_scale: np.float32
+
+    @property
+    def cells(self) -> int:
+        return self.n_x * self.n_y
+
+
+def make_vertex_grid(n_x: int, n_y: int, x_range=(-32.0, 32.0), y_range=(-32.0, 32.0)) -> VertexGrid:
+    if n_x < 1 or n_y < 1:
+        raise ValueError("a vertex grid needs at least one bin per axis")
+
+    def axis(n, rng):
+        lo, hi = float(rng[0]), float(rng[1])
+        if not hi > lo:
+            raise ValueError("empty vertex range")
+        centre = (lo + (np.arange(n, dtype=np.float64) + 0.5) * ((hi - lo) / n)).astype(np.float32)
+        return centre, np.float32(lo), np.float32(n / (hi - lo))
+
+    xc, xm, xs = axis(n_x, x_range)
+    yc, ym, ys = axis(n_y, y_range)
+    return VertexGrid(n_x=n_x, n_y=n_y, x_centre=xc, y_centre=yc, x_min=xm, x_scale=xs, y_min=ym, y_scale=ys)
+
+
+# 128 x 128 bins of 0.5 cm over [-32, 32)^2 cm: the displaced vertices of the
+# displaced-vertex workload lie within 30 cm of the beam line.
+VERTEX_GRID = make_vertex_grid(128, 128)

@@ -38,6 +38,22 @@ MUTANTS = {
                          "                if (jj < 0 || jj >= n_phi)\n                    continue;\n"),
     "sort_votes_ascending": ("return a->votes > b->votes ? -1 : 1;", "return a->votes < b->votes ? -1 : 1;"),
     "sort_cells_descending": ("return a->cell < b->cell ? -1 : 1;", "return a->cell > b->cell ? -1 : 1;"),
+    "vertex_column_num_sign": ("float num = dt + t;", "float num = dt - t;"),
+    "vertex_row_num_sign": ("float num = t - dt;", "float num = t + dt;"),
+    "vertex_d0_ignored": ("const float dt = d0 ? d0[l] : 0.0f;", "const float dt = 0.0f;"),
+    "vertex_mode_inverted": ("if (fabsf(c) >= fabsf(s)) {", "if (fabsf(c) < fabsf(s)) {"),
+    "vertex_column_uses_cos": ("float t = x_centre[ix] * s;", "float t = x_centre[ix] * c;"),
+    "vertex_row_divides_by_cos": ("float xv = num / s;", "float xv = num / c;"),
+    "vertex_y_offset_sign": ("float fy = (yv - y_min) * y_scale;", "float fy = (yv + y_min) * y_scale;"),
+    "vertex_y_lower_edge_exclusive": ("if (fy >= 0.0f && fy < n_y_f)", "if (fy > 0.0f && fy < n_y_f)"),
+    "vertex_x_lower_edge_exclusive": ("if (fx >= 0.0f && fx < n_x_f)", "if (fx > 0.0f && fx < n_x_f)"),
+    "vertex_phi_row_decoding": ("const int32_t j = (int32_t)((cell / n_kappa) % n_phi);",
+                                "const int32_t j = (int32_t)(cell % n_phi);"),
+    "vertex_track_threshold_strict": ("if (cand_votes[i] < track_threshold)", "if (cand_votes[i] <= track_threshold)"),
+    "vertex_tie_rule_y_axis": ("const int negative = dx != 0 ? dx < 0 : dy < 0;",
+                               "const int negative = dx != 0 ? dx < 0 : dy > 0;"),
+    "vertex_peaks_x_periodic": ("const int32_t xx = ix + dx;", "const int32_t xx = (ix + dx + n_x) % n_x;"),
+    "vertex_peak_threshold_strict": ("if (val < threshold)", "if (val <= threshold)"),
 }
 
 RUNNER = r"""

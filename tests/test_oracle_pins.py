@@ -380,3 +380,160 @@ def test_config1_tracks_found():
         if np.any((np.abs(dj) <= 1.6) & (np.abs(k - kt) <= 6)):
             found += 1
     assert found >= 20
+
+
+# --------------------------------------------------------------------------------------
+# Second transform: candidates to displaced vertices (Section 5)
+# --------------------------------------------------------------------------------------
+
+def vertex_vote(cv, cc, t, grid, vgrid):
+    return oracle.vertex_vote(cv, cc, t, grid, vgrid, library=LIBRARY[0])
+
+
+def vertex_peaks(vacc, threshold, cap=None):
+    return oracle.vertex_peaks(vacc, threshold, cap, library=LIBRARY[0])
+
+
+SMALL_VGRID = synth.make_vertex_grid(24, 20, (-6.0, 6.0), (-5.0, 5.0))
+
+
+def _line_grid(angles_deg, d0_values, n_kappa=3):
+    """A track grid whose phi0 rows are the given angles and whose d0 bins are the given values."""
+    a = np.radians(np.asarray(angles_deg, np.float64))
+    return _grid_from_tables(len(a), n_kappa, -0.03, 50.0, np.cos(a), np.sin(a), d0=d0_values)
+
+
+def test_vertex_lines_through_a_cell_centre_meet_there():
+    """Lines of several slopes (both voting modes) through one vertex put all
+    their votes for it into that vertex's cell, and nowhere else as many."""
+    vg = SMALL_VGRID
+    a, b = 7, 13
+    vx, vy = float(vg.x_centre[a]), float(vg.y_centre[b])
+    angles = [5.0, 33.0, 61.0, 97.0, 128.0, 151.0, 178.0, 250.0]
+    cs = np.cos(np.radians(angles)).astype(np.float32).astype(np.float64)
+    sn = np.sin(np.radians(angles)).astype(np.float32).astype(np.float64)
+    # line i: d0 bin i, phi0 row i (d0 = V_y c - V_x s, the sinusoid of V)
+    d0 = (vy * cs - vx * sn).astype(np.float32)
+    grid = _line_grid(angles, d0)
+    n = len(angles)
+    cells = np.array([(i * grid.n_phi + i) * grid.n_kappa + (i % grid.n_kappa) for i in range(n)], np.int64)
+    vacc, nv = vertex_vote(np.full(n, 9), cells, 9, grid, vg)
+    assert vacc[a, b] == n
+    others = vacc.copy()
+    others[a, b] = 0
+    assert others.max() < n
+    v, c, nf = vertex_peaks(vacc, n)
+    assert nf == 1 and c.tolist() == [a * vg.n_y + b] and v.tolist() == [n]
+
+
+def test_vertex_votes_once_per_column_or_row():
+    """A shallow line votes once in every column, a steep one once in every row,
+    when all its crossings of the dominant axis lie inside the grid."""
+    vg = SMALL_VGRID
+    for ang, steep in ((20.0, False), (160.0, False), (60.0, True), (115.0, True)):
+        grid = _line_grid([ang], [0.3])
+        vacc, nv = vertex_vote([5], [0], 1, grid, vg)
+        if steep:
+            assert nv == vg.n_y
+            assert (vacc.sum(axis=0) == 1).all()
+        else:
+            assert nv == vg.n_x
+            assert (vacc.sum(axis=1) == 1).all()
+
+
+def test_vertex_axis_lines_closed_form():
+    """phi0 = 0: the line y = d0 fills one row of cells; phi0 = 90 deg: x = -d0 fills one column."""
+    vg = SMALL_VGRID
+    g = _grid_from_tables(2, 1, -0.03, 50.0, [1.0, 0.0], [0.0, 1.0], d0=[1.2, 2.3])
+    vacc, nv = vertex_vote([3], [0 * 2 + 0], 1, g, vg)            # d0 = 1.2, phi0 = 0
+    iy = int((1.2 - vg.y_min) * vg.y_scale)
+    expect = np.zeros((vg.n_x, vg.n_y), np.int64)
+    expect[:, iy] = 1
+    np.testing.assert_array_equal(vacc, expect)
+    vacc, nv = vertex_vote([3], [1 * 2 + 1], 1, g, vg)            # d0 = 2.3, phi0 = 90 deg
+    ix = int((-2.3 - vg.x_min) * vg.x_scale)
+    expect = np.zeros((vg.n_x, vg.n_y), np.int64)
+    expect[ix, :] = 1
+    np.testing.assert_array_equal(vacc, expect)
+    # the lower edges are inside, the upper edges outside
+    g = _grid_from_tables(2, 1, -0.03, 50.0, [1.0, 0.0], [0.0, 1.0], d0=[-5.0, 5.0])
+    vacc, nv = vertex_vote([3], [0], 1, g, vg)                    # y = -5 = y_min: row 0
+    assert nv == vg.n_x and (vacc[:, 0] == 1).all()
+    vacc, nv = vertex_vote([3], [1 * 2 + 0], 1, g, vg)            # y = 5 = y_max: no row
+    assert nv == 0
+    g = _grid_from_tables(2, 1, -0.03, 50.0, [0.0, 0.0], [1.0, -1.0], d0=[6.0, 6.0])
+    vacc, nv = vertex_vote([3], [0], 1, g, vg)                    # x = -6 = x_min: column 0
+    assert nv == vg.n_y and (vacc[0, :] == 1).all()
+    vacc, nv = vertex_vote([3], [1 * 2 + 1], 1, g, vg)            # x = 6 = x_max: no column
+    assert nv == 0
+
+
+def test_vertex_transpose_symmetry():
+    """Swapping the x and y axes maps the line (c, s, d0) to (s, c, -d0) and the
+    accumulator to its transpose, bit for bit (the two voting modes trade places)."""
+    vg = synth.make_vertex_grid(16, 16, (-4.0, 4.0), (-4.0, 4.0))
+    rng = np.random.default_rng(5)
+    ang = rng.uniform(0.0, 360.0, size=40)
+    ang = ang[np.abs(np.abs(np.cos(np.radians(ang))) - np.abs(np.sin(np.radians(ang)))) > 1e-3]
+    c = np.cos(np.radians(ang)).astype(np.float32)
+    s = np.sin(np.radians(ang)).astype(np.float32)
+    d = rng.uniform(-3.0, 3.0, size=ang.size).astype(np.float32)
+    n = ang.size
+    cells = np.array([(i * n + i) for i in range(n)], np.int64)
+    g1 = _grid_from_tables(n, 1, -0.03, 50.0, c, s, d0=d)
+    g2 = _grid_from_tables(n, 1, -0.03, 50.0, s, c, d0=-d)
+    v1, n1 = vertex_vote(np.ones(n), cells, 1, g1, vg)
+    v2, n2 = vertex_vote(np.ones(n), cells, 1, g2, vg)
+    assert n1 == n2 > 0
+    np.testing.assert_array_equal(v1, v2.T)
+
+
+def test_vertex_track_threshold():
+    """Candidates below the track threshold cast nothing; at it they vote."""
+    vg = SMALL_VGRID
+    grid = _line_grid([30.0], [0.5])
+    assert vertex_vote([6], [0], 7, grid, vg)[1] == 0
+    assert vertex_vote([7], [0], 7, grid, vg)[1] == vg.n_x
+
+
+def _vertex_peaks_brute(vacc, t):
+    n_x, n_y = vacc.shape
+    out = []
+    for ix in range(n_x):
+        for iy in range(n_y):
+            v = vacc[ix, iy]
+            if v < t:
+                continue
+            ok = True
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    if (dx, dy) == (0, 0) or not (0 <= ix + dx < n_x and 0 <= iy + dy < n_y):
+                        continue
+                    w = vacc[ix + dx, iy + dy]
+                    earlier = dx < 0 or (dx == 0 and dy < 0)
+                    ok &= (v > w) if earlier else (v >= w)
+            if ok:
+                out.append((-int(v), ix * n_y + iy))
+    out.sort()
+    return [-a for a, _ in out], [b for _, b in out]
+
+
+@pytest.mark.parametrize("shape,hi", [((5, 7), 3), ((9, 4), 6), ((1, 6), 2), ((12, 12), 9)])
+def test_vertex_peaks_brute_force(shape, hi):
+    rng = np.random.default_rng(shape[0] * 31 + shape[1])
+    for _ in range(15):
+        vacc = rng.integers(0, hi + 1, size=shape).astype(np.int64)
+        for t in (1, hi // 2 + 1):
+            v, c, n = vertex_peaks(vacc, t)
+            bv, bc = _vertex_peaks_brute(vacc, t)
+            assert n == len(bc) and v.tolist() == bv and c.tolist() == bc
+
+
+def test_vertex_peak_edges_are_not_periodic():
+    vacc = np.zeros((6, 5), np.int64)
+    vacc[0, 2] = 4
+    vacc[5, 2] = 5          # would hide (0, 2) if x wrapped
+    vacc[3, 0] = 3
+    vacc[3, 4] = 6          # would hide (3, 0) if y wrapped
+    v, c, n = vertex_peaks(vacc, 1)
+    assert sorted(c.tolist()) == sorted([0 * 5 + 2, 5 * 5 + 2, 3 * 5 + 0, 3 * 5 + 4])
