@@ -123,7 +123,54 @@ hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t 
 hough_status hough_peaks(hough_ctx *ctx, const void *acc, int32_t threshold,
                          hough_cand *out, int32_t cap, int32_t *n_found, void *stream);
 
-/* Vote and find peaks for a batch of independent events in one pass
+/* ------------------------------------------------------------------------
+ * Displaced vertices: the second Hough transform (Section 5).
+ *
+ * A vertex V is the sinusoid d0 = V_y cos(phi0) - V_x sin(phi0) of the
+ * (phi0, d0) plane.  Every first-transform candidate with votes >=
+ * track_threshold is read as the straight line of vertices V with
+ * V_y c - V_x s = d0 (c, s, d0 the bin centres of its cell in the context's
+ * grid) and votes into a binned (x, y) vertex grid, one binary32 operation at
+ * a time with no contraction:
+ *   |c| >= |s|: for every column ix
+ *       y = (d0 + x_centre[ix] * s) / c;  fy = (y - y_min) * y_scale;
+ *       if (fy >= 0 && fy < n_y) vacc[ix][(int)fy] += 1
+ *   otherwise:  for every row iy
+ *       x = (y_centre[iy] * c - d0) / s;  fx = (x - x_min) * x_scale;
+ *       if (fx >= 0 && fx < n_x) vacc[(int)fx][iy] += 1
+ * Vertex candidates are cells with vacc >= vertex_threshold that pass the
+ * asymmetric 3x3 local-maximum rule (earlier offsets in (dx, dy) order must
+ * be exceeded, later ones reached; neither axis is periodic), sorted by votes
+ * descending then cell = ix * n_y + iy ascending.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_x, n_y;            /* bins per axis: n_x*n_y <= 16384, ceil(n_x/2)*ceil(n_y/2) <= 4096 */
+    float x_min, x_scale;        /* fx = (x - x_min) * x_scale */
+    float y_min, y_scale;        /* fy = (y - y_min) * y_scale */
+    const float *x_centre;       /* [dev][n_x] fp32 column centres */
+    const float *y_centre;       /* [dev][n_y] fp32 row centres */
+} hough_vertex_grid;
+
+/* Second transform for n_events events whose first-transform candidates are
+ * in cands (e.g. the output of hough_event_batch on this context):
+ *   cands:      [dev] hough_cand lists; event e's list is cands[cand_off[e] ..
+ *               cand_off[e] + min(n_found[e], cand_off[e+1] - cand_off[e])).
+ *   cand_off:   [dev][n_events+1] int64 list offsets (nondecreasing).
+ *   n_found:    [dev][n_events] int32 candidates found per event.
+ *   vout:       [dev] vertex candidates; event e gets the first
+ *               vout_off[e+1] - vout_off[e] of its sorted list at vout_off[e].
+ *   vout_off:   [dev][n_events+1] int64 (nondecreasing).
+ *   n_vertices: [dev][n_events] int32, the full number of vertex candidates.
+ *   vacc:       [dev][n_events][n_x*n_y] int32 accumulators, or NULL.
+ * Candidate cells outside the context's grid are skipped.  Allocates
+ * nothing; asynchronous on stream.  EINVAL: null required pointers,
+ * n_events < 1, a vertex grid beyond the limits above. */
+hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int32_t n_events,
+                            const hough_cand *cands, const int64_t *cand_off, const int32_t *n_found,
+                            int32_t track_threshold, int32_t vertex_threshold, hough_cand *vout,
+                            const int64_t *vout_off, int32_t *n_vertices, int32_t *vacc, void *stream);
+
+/* Vote and find peaks for a batch of independent events in one pass/* Vote and find peaks for a batch of independent events in one pass
  * (Section 4: hits, and so events, are independent).  Equivalent, bit for bit,
  * to hough_vote followed by hough_peaks on each event.
  *   hit_off:  host [n_events+1] CSR offsets into x, y (hit_off[0] == 0).

@@ -609,6 +609,27 @@ hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t 
     return HOUGH_OK;
 }
 
+hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int32_t n_events,
+                            const hough_cand *cands, const int64_t *cand_off, const int32_t *n_found,
+                            int32_t track_threshold, int32_t vertex_threshold, hough_cand *vout,
+                            const int64_t *vout_off, int32_t *n_vertices, int32_t *vacc, void *stream) {
+    if (!ctx || !vgrid || n_events < 1 || !cand_off || !n_found || !vout_off || !n_vertices || !vout)
+        return HOUGH_EINVAL;
+    if (!cands)
+        return HOUGH_EINVAL;
+    const hough_vertex_grid &vg = *vgrid;
+    if (vg.n_x < 1 || vg.n_y < 1 || !vg.x_centre || !vg.y_centre)
+        return HOUGH_EINVAL;
+    if (static_cast<int64_t>(vg.n_x) * vg.n_y > kVtxMaxCells || vertex_sort_size(vg.n_x, vg.n_y) > kVtxMaxPeaks) {
+        set_last_error("hough_vertices: vertex grid larger than 16384 cells or 4096 survivors");
+        return HOUGH_EINVAL;
+    }
+    HIP_TRY(launch_vertices(ctx->g, vg, n_events, reinterpret_cast<const Cand *>(cands), cand_off, n_found,
+                            track_threshold, vertex_threshold, reinterpret_cast<Cand *>(vout), vout_off, n_vertices,
+                            vacc, static_cast<hipStream_t>(stream)));
+    return HOUGH_OK;
+}
+
 hough_status hough_peaks(hough_ctx *ctx, const void *acc, int32_t threshold, hough_cand *out, int32_t cap,
                          int32_t *n_found, void *stream) {
     if (!ctx || !acc || !n_found || cap < 0 || (cap > 0 && !out))

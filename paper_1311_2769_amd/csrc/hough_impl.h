@@ -178,6 +178,16 @@ hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_
                         int32_t threshold, const SortWork &w, hipStream_t stream);
 hipError_t launch_sort(const SortWork &w, int32_t n_events, hipStream_t stream);
 
+// Second transform (vertex.hip).  Grids need n_x * n_y <= kVtxMaxCells and a
+// survivor bound ceil(n_x/2) * ceil(n_y/2) <= kVtxMaxPeaks (LDS-resident).
+constexpr int32_t kVtxMaxCells = 16384;
+constexpr int32_t kVtxMaxPeaks = 4096;
+int32_t vertex_sort_size(int32_t n_x, int32_t n_y);
+hipError_t launch_vertices(const GridArgs &g, const hough_vertex_grid &vg, int32_t n_events, const Cand *cands,
+                           const int64_t *cand_off, const int32_t *n_found, int32_t track_threshold,
+                           int32_t vertex_threshold, Cand *vout, const int64_t *vout_off, int32_t *n_vertices,
+                           int32_t *vacc, hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // Launch-shape cache (tune.hip).
 // ---------------------------------------------------------------------------

@@ -24,7 +24,7 @@ ACC_I32, ACC_U16 = 0, 1
 
 SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
-    "hough_vote_batch",
+    "hough_vote_batch", "hough_vertices",
     "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
     "hough_autotune", "hough_tune_lookup",
     "hough_server_create", "hough_server_destroy", "hough_server_clock", "hough_server_submit",
@@ -47,6 +47,12 @@ class _Grid(ctypes.Structure):
                 ("kappa_min", ctypes.c_float), ("kappa_scale", ctypes.c_float),
                 ("cos_phi", ctypes.c_void_p), ("sin_phi", ctypes.c_void_p), ("d0", ctypes.c_void_p),
                 ("acc_type", ctypes.c_int32)]
+
+
+class _VertexGrid(ctypes.Structure):
+    _fields_ = [("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32), ("x_min", ctypes.c_float),
+                ("x_scale", ctypes.c_float), ("y_min", ctypes.c_float), ("y_scale", ctypes.c_float),
+                ("x_centre", ctypes.c_void_p), ("y_centre", ctypes.c_void_p)]
 
 
 class _Opts(ctypes.Structure):
@@ -127,6 +133,8 @@ def load(path: str = LIB_PATH):
     lib.hough_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.hough_diag_rates.restype = i32
     lib.hough_diag_rates.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.hough_vertices.restype = i32
+    lib.hough_vertices.argtypes = [vp, ctypes.POINTER(_VertexGrid), i32, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp]
     lib.hough_selftest_divide.restype = i32
     lib.hough_selftest_divide.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64)]
@@ -193,6 +201,27 @@ class GridSpec:
     def max_candidates(self):
         """Upper bound on candidates of one event: no two candidates are neighbours."""
         return ((self.n_d0 + 1) // 2 if self.n_d0 > 1 else 1) * (self.n_phi // 2) * ((self.n_kappa + 1) // 2)
+
+
+class VertexGridSpec:
+    """A binned (x, y) vertex grid (Section 5) with its fp32 centre tables on a device."""
+
+    def __init__(self, vgrid, device="cuda"):
+        self.n_x, self.n_y = int(vgrid.n_x), int(vgrid.n_y)
+        self.device = torch.device(device)
+        self.x_centre = torch.from_numpy(np.asarray(vgrid.x_centre, np.float32).copy()).to(self.device)
+        self.y_centre = torch.from_numpy(np.asarray(vgrid.y_centre, np.float32).copy()).to(self.device)
+        self.struct = _VertexGrid(self.n_x, self.n_y, float(vgrid.x_min), float(vgrid.x_scale),
+                                  float(vgrid.y_min), float(vgrid.y_scale), self.x_centre.data_ptr(),
+                                  self.y_centre.data_ptr())
+
+    @property
+    def cells(self):
+        return self.n_x * self.n_y
+
+    def max_candidates(self):
+        """No two vertex candidates are neighbours."""
+        return ((self.n_x + 1) // 2) * ((self.n_y + 1) // 2)
 
 
 class HoughContext:
@@ -266,6 +295,31 @@ class HoughContext:
         _check(self.lib.hough_peaks(self.handle, _ptr(acc), int(threshold), _ptr(out) if cap else None,
                                     int(cap), _ptr(n_found), _stream_handle(stream)), "hough_peaks")
         return out, n_found
+
+    def vertices(self, vgrid, cands, cand_off, n_found, track_threshold, vertex_threshold, vout=None,
+                 vout_off=None, n_vertices=None, vacc=None, want_acc=False, stream=None):
+        """Second transform of this context's candidates (hough_vertices).  cand_off and
+        vout_off are host or device int64 offsets; returns (vout, vout_off, n_vertices, vacc)."""
+        if not isinstance(vgrid, VertexGridSpec):
+            vgrid = VertexGridSpec(vgrid, self.device)
+        off = torch.as_tensor(np.asarray(cand_off, np.int64) if not torch.is_tensor(cand_off) else cand_off,
+                              dtype=torch.int64).to(self.device)
+        n_events = off.numel() - 1
+        if vout_off is None:
+            vout_off = np.arange(n_events + 1, dtype=np.int64) * vgrid.max_candidates()
+        voff = torch.as_tensor(np.asarray(vout_off, np.int64) if not torch.is_tensor(vout_off) else vout_off,
+                               dtype=torch.int64).to(self.device)
+        if vout is None:
+            vout = torch.empty((max(int(voff[-1].item()), 1), 2), dtype=torch.int32, device=self.device)
+        if n_vertices is None:
+            n_vertices = torch.empty(n_events, dtype=torch.int32, device=self.device)
+        if vacc is None and want_acc:
+            vacc = torch.empty((n_events, vgrid.n_x, vgrid.n_y), dtype=torch.int32, device=self.device)
+        _check(self.lib.hough_vertices(self.handle, ctypes.byref(vgrid.struct), n_events, _ptr(cands), _ptr(off),
+                                       _ptr(n_found), int(track_threshold), int(vertex_threshold), _ptr(vout),
+                                       _ptr(voff), _ptr(n_vertices), _ptr(vacc), _stream_handle(stream)),
+               "hough_vertices")
+        return vout, voff, n_vertices, vacc
 
     def event_batch(self, hit_off, x, y, threshold, cand_off=None, cands=None, n_found=None,
                     n_votes=None, acc=None, want_votes=True, stream=None):
