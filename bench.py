@@ -33,6 +33,8 @@ PEAK_FP32_OPS = 256 * 64 * 2.4e9          # 39.3e12 single fp32 operations / s
 PEAK_LDS_ATOMIC = 256 * 64 * 2.4e9        # 39.3e12 dword atomics / s if every bank retires one per clock
 FLOPS_PER_EVAL_2D = 7                     # u: 2 mul + 1 sub; 2u: 1 mul; divide: 1; kf: 1 sub + 1 mul
 FLOPS_PER_HIT_2D = 3                      # r^2: 2 mul + 1 add
+VERTEX_TRACK_THRESHOLD = 300              # track candidates that vote in the second transform
+VERTEX_THRESHOLD = 4                      # vertex candidates: lines meeting in a cell
 
 # HBM bytes of the dominant kernel from rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE in KiB per dispatch, each scaled by what the counter reads for a
@@ -217,11 +219,42 @@ def displaced_3d(hough, torch, dev, synth, log_fn, n_events=8, reps=10):
         vote.append(ctx.get_timing()[0])
     ctx.set_timing(False)
     evals = int(b.n_hits) * wc.grid.n_d0 * wc.grid.n_phi
+
+    # second transform (Section 5) on the batch's candidates: track candidates
+    # with >= 300 votes as lines into 128 x 128 vertex bins of 0.5 cm
+    vg = hough.VertexGridSpec(synth.VERTEX_GRID, dev)
+    voff = torch.from_numpy(np.arange(n_events + 1, dtype=np.int64) * vg.max_candidates()).to(dev)
+    coff = torch.from_numpy(cand_off).to(dev)
+    vout = torch.empty((n_events * vg.max_candidates(), 2), dtype=torch.int32, device=dev)
+    n_vtx = torch.empty(n_events, dtype=torch.int32, device=dev)
+
+    def vstep():
+        ctx.vertices(vg, cands, coff, n_found, VERTEX_TRACK_THRESHOLD, VERTEX_THRESHOLD, vout=vout, vout_off=voff,
+                     n_vertices=n_vtx)
+
+    for _ in range(3):
+        vstep()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        vstep()
+    ev1.record()
+    torch.cuda.synchronize()
+    v_ms = ev0.elapsed_time(ev1) / reps
+    cv = cands[:, 0].cpu().numpy()
+    nf = n_found.cpu().numpy()
+    lines = sum(int((cv[cand_off[e]:cand_off[e] + min(int(nf[e]), cap)] >= VERTEX_TRACK_THRESHOLD).sum())
+                for e in range(n_events))
+    vertices = {"track_threshold": VERTEX_TRACK_THRESHOLD, "vertex_threshold": VERTEX_THRESHOLD,
+                "grid": [vg.n_x, vg.n_y], "lines_per_event": lines // n_events,
+                "ms_per_launch": v_ms, "ms_per_event": v_ms / n_events,
+                "vertex_candidates_per_event": int(n_vtx.sum().item()) // n_events}
     return {"workload": "displaced_3d_35k_64x512x256_u16", "events": n_events, "hits": int(b.n_hits),
             "ms_per_event": 1e3 * dt / n_events, "events_per_s": n_events / dt,
             "vote_ms_per_event": float(np.mean(vote[1:])) / n_events,
             "evaluations_per_s": evals / dt, "votes_per_event": int(n_votes.sum().item()) // n_events,
-            "candidates_per_event": int(n_found.sum().item()) // n_events}
+            "candidates_per_event": int(n_found.sum().item()) // n_events, "vertices": vertices}
 
 
 def served_stream(args, hough, synth, batch, log_fn):

@@ -144,7 +144,8 @@ hough_status hough_peaks(hough_ctx *ctx, const void *acc, int32_t threshold,
  * descending then cell = ix * n_y + iy ascending.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int32_t n_x, n_y;            /* bins per axis: n_x*n_y <= 16384, ceil(n_x/2)*ceil(n_y/2) <= 4096 */
+    int32_t n_x, n_y;            /* bins per axis: n_x*n_y <= 16384, ceil(n_x/2)*ceil(n_y/2) <= 4096,
+                                    and n_x*(n_y+1) cells of LDS with the sort keys within 160 KB */
     float x_min, x_scale;        /* fx = (x - x_min) * x_scale */
     float y_min, y_scale;        /* fy = (y - y_min) * y_scale */
     const float *x_centre;       /* [dev][n_x] fp32 column centres */
@@ -157,18 +158,23 @@ typedef struct {
  *               cand_off[e] + min(n_found[e], cand_off[e+1] - cand_off[e])).
  *   cand_off:   [dev][n_events+1] int64 list offsets (nondecreasing).
  *   n_found:    [dev][n_events] int32 candidates found per event.
+ *   sorted_lists: nonzero when every list is sorted by votes descending (as
+ *               hough_event_batch and hough_peaks write them): the voting
+ *               candidates are then a prefix and the scan stops at the first
+ *               one below track_threshold.  Zero scans whole lists.
  *   vout:       [dev] vertex candidates; event e gets the first
  *               vout_off[e+1] - vout_off[e] of its sorted list at vout_off[e].
  *   vout_off:   [dev][n_events+1] int64 (nondecreasing).
  *   n_vertices: [dev][n_events] int32, the full number of vertex candidates.
- *   vacc:       [dev][n_events][n_x*n_y] int32 accumulators, or NULL.
+ *   vacc:       [dev][n_events][n_x*n_y] int32 accumulators (overwritten), or NULL.
  * Candidate cells outside the context's grid are skipped.  Allocates
  * nothing; asynchronous on stream.  EINVAL: null required pointers,
  * n_events < 1, a vertex grid beyond the limits above. */
 hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int32_t n_events,
                             const hough_cand *cands, const int64_t *cand_off, const int32_t *n_found,
-                            int32_t track_threshold, int32_t vertex_threshold, hough_cand *vout,
-                            const int64_t *vout_off, int32_t *n_vertices, int32_t *vacc, void *stream);
+                            int32_t sorted_lists, int32_t track_threshold, int32_t vertex_threshold,
+                            hough_cand *vout, const int64_t *vout_off, int32_t *n_vertices, int32_t *vacc,
+                            void *stream);
 
 /* Vote and find peaks for a batch of independent events in one pass/* Vote and find peaks for a batch of independent events in one pass
  * (Section 4: hits, and so events, are independent).  Equivalent, bit for bit,

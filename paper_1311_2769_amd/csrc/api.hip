@@ -611,8 +611,9 @@ hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t 
 
 hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int32_t n_events,
                             const hough_cand *cands, const int64_t *cand_off, const int32_t *n_found,
-                            int32_t track_threshold, int32_t vertex_threshold, hough_cand *vout,
-                            const int64_t *vout_off, int32_t *n_vertices, int32_t *vacc, void *stream) {
+                            int32_t sorted_lists, int32_t track_threshold, int32_t vertex_threshold,
+                            hough_cand *vout, const int64_t *vout_off, int32_t *n_vertices, int32_t *vacc,
+                            void *stream) {
     if (!ctx || !vgrid || n_events < 1 || !cand_off || !n_found || !vout_off || !n_vertices || !vout)
         return HOUGH_EINVAL;
     if (!cands)
@@ -620,13 +621,13 @@ hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int3
     const hough_vertex_grid &vg = *vgrid;
     if (vg.n_x < 1 || vg.n_y < 1 || !vg.x_centre || !vg.y_centre)
         return HOUGH_EINVAL;
-    if (static_cast<int64_t>(vg.n_x) * vg.n_y > kVtxMaxCells || vertex_sort_size(vg.n_x, vg.n_y) > kVtxMaxPeaks) {
-        set_last_error("hough_vertices: vertex grid larger than 16384 cells or 4096 survivors");
+    if (!vertex_grid_supported(vg.n_x, vg.n_y)) {
+        set_last_error("hough_vertices: vertex grid beyond 16384 cells, 4096 survivors or the LDS of a workgroup");
         return HOUGH_EINVAL;
     }
     HIP_TRY(launch_vertices(ctx->g, vg, n_events, reinterpret_cast<const Cand *>(cands), cand_off, n_found,
-                            track_threshold, vertex_threshold, reinterpret_cast<Cand *>(vout), vout_off, n_vertices,
-                            vacc, static_cast<hipStream_t>(stream)));
+                            track_threshold, vertex_threshold, sorted_lists, reinterpret_cast<Cand *>(vout), vout_off,
+                            n_vertices, vacc, static_cast<hipStream_t>(stream)));
     return HOUGH_OK;
 }
 

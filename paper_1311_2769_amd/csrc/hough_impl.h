@@ -183,10 +183,11 @@ hipError_t launch_sort(const SortWork &w, int32_t n_events, hipStream_t stream);
 constexpr int32_t kVtxMaxCells = 16384;
 constexpr int32_t kVtxMaxPeaks = 4096;
 int32_t vertex_sort_size(int32_t n_x, int32_t n_y);
+bool vertex_grid_supported(int32_t n_x, int32_t n_y);   // the limits above and the workgroup's LDS
 hipError_t launch_vertices(const GridArgs &g, const hough_vertex_grid &vg, int32_t n_events, const Cand *cands,
                            const int64_t *cand_off, const int32_t *n_found, int32_t track_threshold,
-                           int32_t vertex_threshold, Cand *vout, const int64_t *vout_off, int32_t *n_vertices,
-                           int32_t *vacc, hipStream_t stream);
+                           int32_t vertex_threshold, int32_t sorted, Cand *vout, const int64_t *vout_off,
+                           int32_t *n_vertices, int32_t *vacc, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Launch-shape cache (tune.hip).

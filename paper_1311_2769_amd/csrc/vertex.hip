@@ -16,21 +16,29 @@
 // cell (ix * n_y + iy) ascending.
 //
 // One workgroup per event holds the event's whole vertex accumulator in LDS
-// (at most kVtxMaxCells cells): wavefronts take candidates, lanes take the
-// columns or rows of a line, votes are LDS atomics; the peak test then runs
-// over LDS, survivors are packed as 64-bit keys (0x7fffffff - votes, cell),
-// bitonic-sorted in LDS and written to the caller's list.
+// (at most kVtxMaxCells cells).  It reads the candidates in coalesced rounds
+// and lists the ones that vote; wavefronts then take lines and lanes the
+// columns or rows of a line, each vote an LDS atomic.  A list sorted by
+// votes (as the first transform writes it) ends its scan at the first
+// candidate below the track threshold.  The peak test runs over LDS;
+// survivors are packed as 64-bit keys (0x7fffffff - votes, cell),
+// bitonic-sorted in LDS and written out.  (Spreading one event over many
+// workgroups with atomics into memory measured 4x slower.)
 #pragma clang fp contract(off)
 
 #include <climits>
 
 #include "hough_impl.h"
+#include "peak_tile.h"
 
 namespace hough {
 namespace {
 
 constexpr int kVtxThreads = 1024;
 constexpr int kVtxWaves = kVtxThreads / 64;
+constexpr int kVtxPer = 4;                          // candidates per thread per round
+constexpr int kVtxScan = kVtxPer * kVtxThreads;     // candidates per round
+constexpr int kVtxRegCentres = 4;                   // centres per lane kept in registers (axes <= 256 bins)
 
 struct VertexArgs {
     GridArgs g;                   // the track grid of the candidates
@@ -39,6 +47,7 @@ struct VertexArgs {
     const int32_t *n_found;       // [dev][n_events] candidates found (may exceed the slice)
     int32_t track_threshold;
     int32_t vertex_threshold;
+    int32_t sorted;               // lists sorted by votes descending: stop at the first below threshold
     int32_t n_x, n_y;
     float x_min, x_scale, y_min, y_scale;
     const float *x_centre;        // [dev][n_x]
@@ -53,6 +62,8 @@ struct VertexArgs {
 __global__ __launch_bounds__(kVtxThreads) void vertex_kernel(VertexArgs a) {
     extern __shared__ uint64_t vtx_lds[];
     __shared__ int32_t n_peaks;
+    __shared__ int32_t n_lines;
+    __shared__ float3 lines[kVtxScan];    // (d0, cos phi0, sin phi0) of the round's voting candidates
     const int e = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -60,16 +71,24 @@ __global__ __launch_bounds__(kVtxThreads) void vertex_kernel(VertexArgs a) {
     const int n_x = a.n_x;
     const int n_y = a.n_y;
     const int cells = n_x * n_y;
+    // LDS columns are n_y + 1 dwords apart: the 64 lanes of a shallow line add
+    // into 64 consecutive columns, which would otherwise share one bank
+    const int ys = n_y + 1;
     uint64_t *keys = vtx_lds;                                              // [sort_size]
-    int32_t *acc = reinterpret_cast<int32_t *>(vtx_lds + a.sort_size);     // [cells]
+    int32_t *acc = reinterpret_cast<int32_t *>(vtx_lds + a.sort_size);     // [n_x][ys]
 
-    for (int i = tid; i < cells; i += kVtxThreads)
+    for (int i = tid; i < n_x * ys; i += kVtxThreads)
         acc[i] = 0;
-    if (tid == 0)
+    if (tid == 0) {
         n_peaks = 0;
-    __syncthreads();
+        n_lines = 0;
+    }
 
-    // votes: a wavefront per candidate, its lanes across the columns or rows
+    // Votes, in rounds of kVtxScan candidates: the workgroup reads a round
+    // (coalesced; the next round is loaded while this one votes), lists the
+    // lines that vote, then a wavefront per line casts it with its lanes
+    // across the columns or rows.  Integer counts do not depend on the order
+    // of the votes.
     const GridArgs &g = a.g;
     const int64_t begin = a.cand_off[e];
     const int64_t room = a.cand_off[e + 1] - begin;
@@ -79,51 +98,113 @@ __global__ __launch_bounds__(kVtxThreads) void vertex_kernel(VertexArgs a) {
     const int plane = g.n_phi * g.n_kappa;
     const float nxf = static_cast<float>(n_x);
     const float nyf = static_cast<float>(n_y);
-    for (int64_t i = wave; i < n; i += kVtxWaves) {
-        const Cand cd = a.cands[begin + i];
-        if (cd.votes < a.track_threshold || cd.cell < 0 || cd.cell >= track_cells)
-            continue;   // (cells outside the grid are never produced by the first transform)
-        const int l = cd.cell / plane;
-        const int j = (cd.cell / g.n_kappa) % g.n_phi;
-        const float dt = g.d0 ? g.d0[l] : 0.0f;
-        const float c = g.cos_phi[j];
-        const float s = g.sin_phi[j];
-        if (fabsf(c) >= fabsf(s)) {
-            for (int ix = lane; ix < n_x; ix += 64) {
-                const float t = a.x_centre[ix] * s;
+    // the column and row centres of this lane (the same for every line)
+    float xcr[kVtxRegCentres], ycr[kVtxRegCentres];
+#pragma unroll
+    for (int k = 0; k < kVtxRegCentres; ++k) {
+        xcr[k] = lane + 64 * k < n_x ? a.x_centre[lane + 64 * k] : 0.0f;
+        ycr[k] = lane + 64 * k < n_y ? a.y_centre[lane + 64 * k] : 0.0f;
+    }
+    Cand pf[kVtxPer];
+    auto fetch = [&](int64_t r0) {
+#pragma unroll
+        for (int q = 0; q < kVtxPer; ++q) {
+            const int64_t i = r0 + q * kVtxThreads + tid;
+            pf[q] = i < n ? a.cands[begin + i] : Cand{INT_MIN, -1};
+        }
+    };
+    fetch(0);
+    __syncthreads();
+    for (int64_t r0 = 0; r0 < n; r0 += kVtxScan) {
+        bool below = false;
+#pragma unroll
+        for (int q = 0; q < kVtxPer; ++q) {
+            const Cand cd = pf[q];
+            const bool live = r0 + q * kVtxThreads + tid < n;
+            below = below || (live && cd.votes < a.track_threshold);
+            // (cells outside the grid are never produced by the first transform);
+            // one slot reservation per wavefront, and the line's constants are
+            // loaded here, by every lister at once
+            const bool vote = cd.votes >= a.track_threshold && cd.cell >= 0 && cd.cell < track_cells;
+            const uint64_t mask = __ballot(vote);
+            int base = 0;
+            if (lane == 0 && mask)
+                base = atomicAdd(&n_lines, __popcll(mask));
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (vote) {
+                const int l = cd.cell / plane;
+                const int j = (cd.cell / g.n_kappa) % g.n_phi;
+                lines[base + rank_below(mask)] = make_float3(g.d0 ? g.d0[l] : 0.0f, g.cos_phi[j], g.sin_phi[j]);
+            }
+        }
+        // a sorted list has no voting candidate after its first one below threshold
+        const bool last = __syncthreads_or(a.sorted && below) != 0;
+        if (!last && r0 + kVtxScan < n)
+            fetch(r0 + kVtxScan);
+        const int m = n_lines;
+        for (int li = wave; li < m; li += kVtxWaves) {
+            const float3 ln = lines[li];
+            const float dt = ln.x;
+            const float c = ln.y;
+            const float s = ln.z;
+            auto col = [&](int ix, float xc) {
+                const float t = xc * s;
                 const float num = dt + t;
                 const float yv = num / c;
                 const float fy = (yv - a.y_min) * a.y_scale;
                 if (fy >= 0.0f && fy < nyf)
-                    atomicAdd(&acc[ix * n_y + static_cast<int>(fy)], 1);
-            }
-        } else {
-            for (int iy = lane; iy < n_y; iy += 64) {
-                const float t = a.y_centre[iy] * c;
+                    atomicAdd(&acc[ix * ys + static_cast<int>(fy)], 1);
+            };
+            auto row = [&](int iy, float yc) {
+                const float t = yc * c;
                 const float num = t - dt;
                 const float xv = num / s;
                 const float fx = (xv - a.x_min) * a.x_scale;
                 if (fx >= 0.0f && fx < nxf)
-                    atomicAdd(&acc[static_cast<int>(fx) * n_y + iy], 1);
+                    atomicAdd(&acc[static_cast<int>(fx) * ys + iy], 1);
+            };
+            if (fabsf(c) >= fabsf(s)) {
+#pragma unroll
+                for (int k = 0; k < kVtxRegCentres; ++k) {
+                    if (lane + 64 * k < n_x)
+                        col(lane + 64 * k, xcr[k]);
+                }
+                for (int ix = lane + 64 * kVtxRegCentres; ix < n_x; ix += 64)
+                    col(ix, a.x_centre[ix]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kVtxRegCentres; ++k) {
+                    if (lane + 64 * k < n_y)
+                        row(lane + 64 * k, ycr[k]);
+                }
+                for (int iy = lane + 64 * kVtxRegCentres; iy < n_y; iy += 64)
+                    row(iy, a.y_centre[iy]);
             }
         }
+        __syncthreads();
+        if (tid == 0)
+            n_lines = 0;
+        __syncthreads();
+        if (last)
+            break;
     }
-    __syncthreads();
 
     if (a.vacc) {
         int32_t *dst = a.vacc + static_cast<int64_t>(e) * cells;
-        for (int i = tid; i < cells; i += kVtxThreads)
-            dst[i] = acc[i];
+        for (int i = tid; i < cells; i += kVtxThreads) {
+            const int ix = i / n_y;
+            dst[i] = acc[i + ix];
+        }
     }
 
     // peaks: neighbours outside the grid are ignored; earlier offsets (dx, dy)
     // must be exceeded, later ones reached
     for (int cell = tid; cell < cells; cell += kVtxThreads) {
-        const int32_t v = acc[cell];
-        if (v < a.vertex_threshold)
-            continue;
         const int ix = cell / n_y;
         const int iy = cell - ix * n_y;
+        const int32_t v = acc[ix * ys + iy];
+        if (v < a.vertex_threshold)
+            continue;
         bool keep = true;
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
@@ -135,7 +216,7 @@ __global__ __launch_bounds__(kVtxThreads) void vertex_kernel(VertexArgs a) {
                 const int yy = iy + dy;
                 if (xx < 0 || xx >= n_x || yy < 0 || yy >= n_y)
                     continue;
-                const int32_t w = acc[xx * n_y + yy];
+                const int32_t w = acc[xx * ys + yy];
                 const bool earlier = dx < 0 || (dx == 0 && dy < 0);
                 keep = keep && (earlier ? v > w : v >= w);
             }
@@ -198,10 +279,18 @@ int32_t vertex_sort_size(int32_t n_x, int32_t n_y) {
     return p;
 }
 
+bool vertex_grid_supported(int32_t n_x, int32_t n_y) {
+    if (n_x < 1 || n_y < 1 || static_cast<int64_t>(n_x) * n_y > kVtxMaxCells || vertex_sort_size(n_x, n_y) > kVtxMaxPeaks)
+        return false;
+    const size_t lds = static_cast<size_t>(vertex_sort_size(n_x, n_y)) * sizeof(uint64_t) +
+                       static_cast<size_t>(n_x) * (n_y + 1) * sizeof(int32_t) + kVtxScan * sizeof(float3) + 64;
+    return lds <= 160u * 1024u;
+}
+
 hipError_t launch_vertices(const GridArgs &g, const hough_vertex_grid &vg, int32_t n_events, const Cand *cands,
                            const int64_t *cand_off, const int32_t *n_found, int32_t track_threshold,
-                           int32_t vertex_threshold, Cand *vout, const int64_t *vout_off, int32_t *n_vertices,
-                           int32_t *vacc, hipStream_t stream) {
+                           int32_t vertex_threshold, int32_t sorted, Cand *vout, const int64_t *vout_off,
+                           int32_t *n_vertices, int32_t *vacc, hipStream_t stream) {
     VertexArgs a{};
     a.g = g;
     a.cands = cands;
@@ -209,6 +298,7 @@ hipError_t launch_vertices(const GridArgs &g, const hough_vertex_grid &vg, int32
     a.n_found = n_found;
     a.track_threshold = track_threshold;
     a.vertex_threshold = vertex_threshold;
+    a.sorted = sorted ? 1 : 0;
     a.n_x = vg.n_x;
     a.n_y = vg.n_y;
     a.x_min = vg.x_min;
@@ -223,7 +313,7 @@ hipError_t launch_vertices(const GridArgs &g, const hough_vertex_grid &vg, int32
     a.n_vertices = n_vertices;
     a.vacc = vacc;
     const size_t lds = static_cast<size_t>(a.sort_size) * sizeof(uint64_t) +
-                       static_cast<size_t>(vg.n_x) * vg.n_y * sizeof(int32_t);
+                       static_cast<size_t>(vg.n_x) * (vg.n_y + 1) * sizeof(int32_t);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(vertex_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess)

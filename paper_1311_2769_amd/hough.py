@@ -134,7 +134,8 @@ def load(path: str = LIB_PATH):
     lib.hough_diag_rates.restype = i32
     lib.hough_diag_rates.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.hough_vertices.restype = i32
-    lib.hough_vertices.argtypes = [vp, ctypes.POINTER(_VertexGrid), i32, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp]
+    lib.hough_vertices.argtypes = [vp, ctypes.POINTER(_VertexGrid), i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp,
+                                   vp]
     lib.hough_selftest_divide.restype = i32
     lib.hough_selftest_divide.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64)]
@@ -297,9 +298,10 @@ class HoughContext:
         return out, n_found
 
     def vertices(self, vgrid, cands, cand_off, n_found, track_threshold, vertex_threshold, vout=None,
-                 vout_off=None, n_vertices=None, vacc=None, want_acc=False, stream=None):
+                 vout_off=None, n_vertices=None, vacc=None, want_acc=False, sorted_lists=True, stream=None):
         """Second transform of this context's candidates (hough_vertices).  cand_off and
-        vout_off are host or device int64 offsets; returns (vout, vout_off, n_vertices, vacc)."""
+        vout_off are host or device int64 offsets; sorted_lists: the lists are sorted by
+        votes descending, as this context writes them.  Returns (vout, vout_off, n_vertices, vacc)."""
         if not isinstance(vgrid, VertexGridSpec):
             vgrid = VertexGridSpec(vgrid, self.device)
         off = torch.as_tensor(np.asarray(cand_off, np.int64) if not torch.is_tensor(cand_off) else cand_off,
@@ -316,8 +318,9 @@ class HoughContext:
         if vacc is None and want_acc:
             vacc = torch.empty((n_events, vgrid.n_x, vgrid.n_y), dtype=torch.int32, device=self.device)
         _check(self.lib.hough_vertices(self.handle, ctypes.byref(vgrid.struct), n_events, _ptr(cands), _ptr(off),
-                                       _ptr(n_found), int(track_threshold), int(vertex_threshold), _ptr(vout),
-                                       _ptr(voff), _ptr(n_vertices), _ptr(vacc), _stream_handle(stream)),
+                                       _ptr(n_found), 1 if sorted_lists else 0, int(track_threshold),
+                                       int(vertex_threshold), _ptr(vout), _ptr(voff), _ptr(n_vertices), _ptr(vacc),
+                                       _stream_handle(stream)),
                "hough_vertices")
         return vout, voff, n_vertices, vacc
 

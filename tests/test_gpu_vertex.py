@@ -32,7 +32,7 @@ def _random_candidates(grid, n, rng, vmax=40):
     return votes, cells
 
 
-def _run(ctx, vgrid, lists, track_t, vertex_t, caps=None, room=None):
+def _run(ctx, vgrid, lists, track_t, vertex_t, caps=None, room=None, sorted_lists=False):
     """hough_vertices on several events' candidate lists; returns per-event
     (vacc, n_vertices, votes, cells)."""
     dev = _dev()
@@ -53,7 +53,7 @@ def _run(ctx, vgrid, lists, track_t, vertex_t, caps=None, room=None):
     vout_off[1:] = np.cumsum(caps)
     vout, _, nv, vacc = ctx.vertices(spec, torch.from_numpy(cands).to(dev), cand_off,
                                      torch.from_numpy(n_found).to(dev), track_t, vertex_t,
-                                     vout_off=vout_off, want_acc=True)
+                                     vout_off=vout_off, want_acc=True, sorted_lists=sorted_lists)
     torch.cuda.synchronize()
     vout, nv, vacc = vout.cpu().numpy(), nv.cpu().numpy(), vacc.cpu().numpy()
     out = []
@@ -86,6 +86,25 @@ def test_vertices_match_oracle_on_synthetic_candidates(grid_name, vshape):
         res = _run(ctx, vgrid, lists, track_t, vertex_t)
         for (v, c), got in zip(lists, res):
             _assert_vertex_parity(got, grid, vgrid, v, c, track_t, vertex_t)
+
+
+def test_sorted_lists_stop_at_the_threshold_and_agree():
+    """Lists sorted by votes (as the first transform writes them) may end their scan
+    at the first candidate below the track threshold; the result is the full scan's."""
+    grid = synth.GRID_3D
+    vgrid = synth.VERTEX_GRID
+    ctx = hough.HoughContext(grid, device=_dev())
+    rng = np.random.default_rng(11)
+    lists = []
+    for n in (0, 5, 8191, 8192, 8193, 30000):
+        v, c = _random_candidates(grid, n, rng, vmax=400)
+        order = np.lexsort((c, -v))
+        lists.append((v[order], c[order]))
+    for track_t in (1, 150, 399, 401):
+        print(f"[vertex] sorted lists, track threshold {track_t}", flush=True)
+        res = _run(ctx, vgrid, lists, track_t, 2, sorted_lists=True)
+        for (v, c), got in zip(lists, res):
+            _assert_vertex_parity(got, grid, vgrid, v, c, track_t, 2)
 
 
 def test_vertices_of_a_displaced_event_end_to_end():
@@ -150,6 +169,6 @@ def test_vertex_grid_limits_raise():
     ctx = hough.HoughContext(synth.GRID_2D_SMALL, device=dev)
     cands = torch.zeros((1, 2), dtype=torch.int32, device=dev)
     nf = torch.zeros(1, dtype=torch.int32, device=dev)
-    for shape in ((129, 128), (1, 9000)):
+    for shape in ((129, 128), (1, 9000), (8192, 2)):
         with pytest.raises(hough.HoughError):
             ctx.vertices(synth.make_vertex_grid(*shape), cands, [0, 1], nf, 1, 1)
