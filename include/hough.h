@@ -70,6 +70,16 @@ typedef enum {
     HOUGH_ACC_U16 = 1    /* uint16 cells; requires n_hits <= 65535 per event and even n_kappa */
 } hough_acc_type;
 
+typedef enum {
+    HOUGH_CURVED = 0,    /* circles (d0, phi0, kappa): the vote formula above */
+    HOUGH_STRAIGHT = 1   /* straight lines (phi0, d0), the kappa = 0 family: n_d0 == 1, d0 == NULL, and
+                            the last axis holds d0 -- kappa_min is the d0 lower edge (cm) and
+                            kappa_scale the bins per cm.  A hit votes, for every phi0 bin,
+                                u = y*c - x*s;  fd = (u - kappa_min) * kappa_scale;
+                                if (fd >= 0 && fd < n_kappa) acc[j][(int)fd] += 1
+                            (binary32, in this order): the d0 of the line through the hit. */
+} hough_family;
+
 /* The binned parameter space.  Bin tables are shared inputs computed once by
  * the caller (fp32), so no transcendental is evaluated on the device. */
 typedef struct {
@@ -82,6 +92,7 @@ typedef struct {
     const float *sin_phi;    /* [dev][n_phi] sin of the phi0 bin centres */
     const float *d0;         /* [dev][n_d0] d0 bin centres (cm), or NULL for 2D */
     int32_t acc_type;        /* hough_acc_type */
+    int32_t family;          /* hough_family (0: curved tracks) */
 } hough_grid;
 
 typedef struct {

@@ -47,6 +47,8 @@ def _bind(lib):
     lib.hough_oracle_peaks.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i64p,
                                        ctypes.c_int64, ctypes.c_int64, i64p, i64p]
     i32, f32 = ctypes.c_int32, ctypes.c_float
+    lib.hough_oracle_vote_straight.restype = ctypes.c_int64
+    lib.hough_oracle_vote_straight.argtypes = [ctypes.c_int64, f32p, f32p, i32, f32p, f32p, i32, f32, f32, i64p]
     lib.hough_oracle_vertex_vote.restype = ctypes.c_int64
     lib.hough_oracle_vertex_vote.argtypes = [ctypes.c_int64, i64p, i64p, ctypes.c_int64,
                                              i32, f32p, i32, f32p, f32p, i32,
@@ -170,3 +172,27 @@ def find_vertices(cand_votes, cand_cells, track_threshold, grid, vgrid, vertex_t
     vacc, n = vertex_vote(cand_votes, cand_cells, track_threshold, grid, vgrid, library=library)
     v, c, nf = vertex_peaks(vacc, vertex_threshold, cap, library=library)
     return vacc, n, v, c, nf
+
+
+def vote_straight(x, y, grid, *, library=None):
+    """Straight-track accumulator (int64, shape (1, n_phi, n_d0)) and the votes cast.
+    ``grid`` is a straight grid: its kappa fields describe the d0 axis."""
+    L = library or lib()
+    x, y = _f32(x), _f32(y)
+    if x.shape != y.shape or x.ndim != 1:
+        raise ValueError("x and y must be 1-D arrays of equal length")
+    cos_phi, sin_phi = _f32(grid.cos_phi), _f32(grid.sin_phi)
+    acc = np.zeros(grid.n_phi * grid.n_kappa, dtype=np.int64)
+    n = L.hough_oracle_vote_straight(x.shape[0], _ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), grid.n_phi,
+                                     _ptr(cos_phi, ctypes.c_float), _ptr(sin_phi, ctypes.c_float), grid.n_kappa,
+                                     float(grid.kappa_min), float(grid.kappa_scale), _ptr(acc, ctypes.c_int64))
+    if n < 0:
+        raise ValueError("oracle rejected the straight grid")
+    return acc.reshape(1, grid.n_phi, grid.n_kappa), int(n)
+
+
+def find_straight(x, y, grid, threshold, cap=None, *, library=None):
+    """Straight vote then peaks: (acc, n_votes, votes, cells, n_found)."""
+    acc, n_votes = vote_straight(x, y, grid, library=library)
+    v, c, n = peaks(acc, threshold, cap, library=library)
+    return acc, n_votes, v, c, n

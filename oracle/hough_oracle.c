@@ -38,6 +38,9 @@
  * kappa neighbours outside the grid are ignored.  Candidates are sorted by
  * votes descending, then cell index ascending, cell = (l*n_phi + j)*n_kappa + k.
  *
+ * Straight tracks: hough_oracle_vote_straight below (the two-parameter
+ * family); its peaks are the peak rule above on a (1, n_phi, n_d0) array.
+ *
  * Displaced vertices (Section 5): hough_oracle_vertex_vote and
  * hough_oracle_vertex_peaks below take the candidates to a binned (x, y)
  * vertex grid; their reading is stated above them.
@@ -85,6 +88,37 @@ int64_t hough_oracle_vote(int64_t n_hits, const float *x, const float *y,
                     acc[((int64_t)l * n_phi + j) * n_kappa + k] += 1;
                     votes += 1;
                 }
+            }
+        }
+    }
+    return votes;
+}
+
+/* Straight tracks (Section 3: a straight line needs two parameters, the
+ * kappa = 0 family): the hypothesis (phi0, d0) is the line through
+ * P0 = (-d0 sin phi0, d0 cos phi0) along (cos phi0, sin phi0).  A hit lies on
+ * it when u = y cos(phi0) - x sin(phi0) equals d0, so for every phi0 bin it
+ * votes d0 bin (int)fd, fd = (u - d0_min) * d0_scale, when 0 <= fd < n_d0
+ * (binary32 operations in this order).  acc is int64 [n_phi][n_d0],
+ * overwritten; cell = j * n_d0 + k.  Returns the number of votes. */
+int64_t hough_oracle_vote_straight(int64_t n_hits, const float *x, const float *y,
+                                   int32_t n_phi, const float *cos_phi, const float *sin_phi,
+                                   int32_t n_d0, float d0_min, float d0_scale, int64_t *acc)
+{
+    if (n_hits < 0 || n_phi < 1 || n_d0 < 1 || !acc)
+        return -1;
+    memset(acc, 0, (size_t)n_phi * (size_t)n_d0 * sizeof(int64_t));
+    const float n_d0_f = (float)n_d0;
+    int64_t votes = 0;
+    for (int64_t i = 0; i < n_hits; ++i) {
+        const float xh = x[i];
+        const float yh = y[i];
+        for (int32_t j = 0; j < n_phi; ++j) {
+            float along = yh * cos_phi[j] - xh * sin_phi[j];
+            float fd = (along - d0_min) * d0_scale;
+            if (fd >= 0.0f && fd < n_d0_f) {
+                acc[(int64_t)j * n_d0 + (int32_t)fd] += 1;
+                votes += 1;
             }
         }
     }

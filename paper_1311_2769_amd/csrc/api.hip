@@ -376,6 +376,10 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         return HOUGH_EINVAL;
     if (grid->n_d0 > 1 && !grid->d0)
         return HOUGH_EINVAL;
+    if (grid->family != HOUGH_CURVED && grid->family != HOUGH_STRAIGHT)
+        return HOUGH_EINVAL;
+    if (grid->family == HOUGH_STRAIGHT && (grid->n_d0 != 1 || grid->d0 != nullptr))
+        return HOUGH_EINVAL;
     if (grid->acc_type != HOUGH_ACC_I32 && grid->acc_type != HOUGH_ACC_U16)
         return HOUGH_EINVAL;
     const bool u16 = grid->acc_type == HOUGH_ACC_U16;
@@ -419,6 +423,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     g.kappa_scale = grid->kappa_scale;
     g.bin_bits = grid->kappa_scale >= 1.0f ? 1 : 0;
     g.near_lim = -1.0f;
+    g.straight = grid->family == HOUGH_STRAIGHT ? 1 : 0;
     g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
     g.cells = cells;
     g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;

@@ -65,6 +65,7 @@ struct GridArgs {
     int32_t row_dwords;   // dwords per (d0, phi0) row in global memory
     int32_t bin_bits;     // kappa_scale >= 1 and kappa_min != +0: the vote's unsigned range test is exact
     float near_lim;       // 3D: 0.5 - E of the one-reciprocal quotient (vote_near_limit), or -1: exact quotients only
+    int32_t straight;     // straight-line family: kappa := u (hit records (x, y, 1, 1)), the last axis is d0
     int64_t cells;        // cells per event
     int64_t acc_dwords;   // dwords per event accumulator
 };

@@ -697,6 +697,8 @@ struct PrepArgs {
     uint32_t stride_magic;      // ceil(2^32 / tile_stride), 0 when tile_stride == 1
     int32_t div_fast;
     float kabs;                 // K' rounded up to fp32 (may be +inf)
+    int32_t straight;           // straight-line family: records (x, y, 1, 1), arcs from the d0 range
+    float dlo, dhi;             // straight: the d0 range, rounded outwards
 };
 
 // 3D quotient range (every phi0 row of one hit and d0 slice): with a phi0
@@ -777,7 +779,12 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     const int l_begin = blockIdx.y * kPrepSlices;
     if (l_begin == 0) {
         float4 rec = make_float4(xf, yf, r2, 0.0f);
-        if (p.div_fast && p.d0 == nullptr) {
+        if (p.straight) {
+            // the 2D fast path then computes kappa = quot_apply(u, 1, 1) = u
+            // exactly (q0 = u, both remainders 0; a -0 may come out +0, which
+            // lands in the same bin)
+            rec = make_float4(xf, yf, 1.0f, 1.0f);
+        } else if (p.div_fast && p.d0 == nullptr) {
             const float half = 0.5f * r2;
             if (quot_den_ok(half))
                 rec = make_float4(xf, yf, half, quot_recip(half));
@@ -795,6 +802,34 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     const float sc = static_cast<float>(p.n_phi) * 0.159154943f;
     const float pi = 3.14159274f;
     const int l_end = min(l_begin + kPrepSlices, p.d0 ? p.n_d0 : 1);
+    // the sine interval -> two arcs -> two tile ranges
+    auto arcs = [&](float slo, float shi) {
+        if (!(isfinite(slo) && isfinite(shi)))
+            return make_uint2(kAllTiles, 0u);   // full circle
+        if (slo > 1.0f || shi < -1.0f)
+            return make_uint2(0u, 0u);
+        if (slo <= -1.0f && shi >= 1.0f)
+            return make_uint2(kAllTiles, 0u);
+        const float alo = arc_asin(fmaxf(slo, -1.0f));
+        const float ahi = arc_asin(fminf(shi, 1.0f));
+        const float pm = ph - pi;
+        return make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi, sc), p),
+                          tile_range(pack_arc(pm + alo, pm + ahi, p.n_phi, sc), p));
+    };
+    if (p.straight) {
+        // Straight lines: a vote needs u_c in [dlo, dhi] up to the rounding of
+        // fd = (u_c - dlo) * scale (relative 2^-22 of the range), and u_c is
+        // within r 2^-20 of r sin(phi_h - phi0); so the sine lies in
+        // [dlo/r, dhi/r] widened by 1e-5 plus 2^-18 (2|dlo| + 2|dhi|)/r, which
+        // covers both and the fp32 rounding of the ends.
+        uint2 out = make_uint2(kAllTiles, 0u);
+        if (r_ok) {
+            const float m = 1e-5f + 0x1.0p-18f * (2.0f * fabsf(p.dlo) + 2.0f * fabsf(p.dhi)) * inv_r;
+            out = arcs(p.dlo * inv_r - m, p.dhi * inv_r + m);
+        }
+        p.ranges[i] = out;
+        return;
+    }
     for (int l = l_begin; l < l_end; ++l) {
         uint2 out = make_uint2(kAllTiles, 0u);
         const float d = p.d0 ? p.d0[l] : 0.0f;
@@ -808,19 +843,7 @@ __global__ void hit_prep_kernel(PrepArgs p) {
             const float s2 = (b + a) * half_inv_r * arc_rcp(1.0f + K * d);
             const float w = arc_rcp(1.0f - kd);
             const float m = 1e-5f + 0x1.0p-18f * (a + 2.0f * ad) * inv_r * w * w;
-            const float slo = fminf(s1, s2) - m;
-            const float shi = fmaxf(s1, s2) + m;
-            if (!(isfinite(slo) && isfinite(shi))) {
-                // full circle
-            } else if (slo > 1.0f || shi < -1.0f) {
-                out = make_uint2(0u, 0u);
-            } else if (!(slo <= -1.0f && shi >= 1.0f)) {
-                const float alo = arc_asin(fmaxf(slo, -1.0f));
-                const float ahi = arc_asin(fminf(shi, 1.0f));
-                const float pm = ph - pi;
-                out = make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi, sc), p),
-                                 tile_range(pack_arc(pm + alo, pm + ahi, p.n_phi, sc), p));
-            }
+            out = arcs(fminf(s1, s2) - m, fmaxf(s1, s2) + m);
         }
         if (p.d0 && p.div_fast && fast_div_3d(r, d, ad))
             out.y |= kFastDiv;
@@ -1001,6 +1024,18 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     if (static_cast<double>(Kf) < K)
         Kf = nextafterf(Kf, INFINITY);
     p.kabs = std::isnan(K) ? INFINITY : Kf;
+    p.straight = g.straight;
+    if (g.straight) {
+        const double lo = g.kappa_min;
+        const double hi = lo + static_cast<double>(g.n_kappa) / g.kappa_scale;
+        float flo = static_cast<float>(lo), fhi = static_cast<float>(hi);
+        if (static_cast<double>(flo) > lo)
+            flo = nextafterf(flo, -INFINITY);
+        if (static_cast<double>(fhi) < hi)
+            fhi = nextafterf(fhi, INFINITY);
+        p.dlo = std::isfinite(flo) ? flo : -INFINITY;
+        p.dhi = std::isfinite(fhi) ? fhi : INFINITY;
+    }
     p.stride_magic = tg.stride > 1
         ? static_cast<uint32_t>(((1ull << 32) + static_cast<uint64_t>(tg.stride) - 1) / static_cast<uint64_t>(tg.stride))
         : 0u;

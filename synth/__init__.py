@@ -7,8 +7,8 @@ paper's Section 3, Figure 1 setup) and writes the binned parameter grids (the
 shared cos/sin tables of the phi0 bin centres) that both sides take as inputs.
 """
 
-from .grids import (Grid, make_grid, GRID_2D_SMALL, GRID_2D, GRID_3D, VertexGrid, make_vertex_grid,
-                    VERTEX_GRID)
+from .grids import (Grid, make_grid, make_straight_grid, GRID_2D_SMALL, GRID_2D, GRID_3D, GRID_STRAIGHT,
+                    VertexGrid, make_vertex_grid, VERTEX_GRID)
 from .events import (
     Event, Batch, gen_config_event, gen_batch, gen_tracks_event,
     track_hits, LAYERS_CM, BASE_SEED, pack_events, poisson_arrivals,
@@ -16,7 +16,8 @@ from .events import (
 from .configs import CONFIGS, WorkloadConfig
 
 __all__ = [
-    "Grid", "make_grid", "GRID_2D_SMALL", "GRID_2D", "GRID_3D", "VertexGrid", "make_vertex_grid", "VERTEX_GRID",
+    "Grid", "make_grid", "make_straight_grid", "GRID_2D_SMALL", "GRID_2D", "GRID_3D", "GRID_STRAIGHT",
+    "VertexGrid", "make_vertex_grid", "VERTEX_GRID",
     "Event", "Batch", "gen_config_event", "gen_batch", "gen_tracks_event",
     "track_hits", "LAYERS_CM", "BASE_SEED", "pack_events", "poisson_arrivals", "CONFIGS", "WorkloadConfig",
 ]

@@ -274,6 +274,35 @@ def gen_displaced_event(rng, n_prompt=3000, n_vertices=20, tracks_per_vertex=10,
                      noise_to=total_hits)
 
 
+def straight_hits(d0, phi0, radii=LAYERS_CM):
+    """Noise-free hits of straight lines (the kappa = 0 family) given by d0 and
+    phi0 at closest approach: the forward crossing P0 + t (cos phi0, sin phi0),
+    t = sqrt(r^2 - d0^2), of every layer with r > |d0|.  (x, y, ok) fp64."""
+    d0 = np.asarray(d0, np.float64)[:, None]
+    phi0 = np.asarray(phi0, np.float64)[:, None]
+    r = np.asarray(radii, np.float64)[None, :]
+    ok = r > np.abs(d0)
+    t = np.sqrt(np.where(ok, r * r - d0 * d0, 0.0))
+    x = -d0 * np.sin(phi0) + t * np.cos(phi0)
+    y = d0 * np.cos(phi0) + t * np.sin(phi0)
+    ok = np.broadcast_to(ok, x.shape)
+    return x, y, ok
+
+
+def gen_straight_event(rng, n_tracks=2000, d0_max=25.0, noise_frac=0.2, smear=True):
+    """Straight displaced tracks (d0 uniform in [-d0_max, d0_max], phi0 uniform)
+    with r-phi smearing and a fraction of noise hits."""
+    d0 = rng.uniform(-d0_max, d0_max, size=n_tracks)
+    phi0 = rng.uniform(0.0, TWO_PI, size=n_tracks)
+    hx, hy, ok = straight_hits(d0, phi0)
+    if smear:
+        hx, hy = _smear(hx, hy, rng, SMEAR_RPHI_CM)
+    lab = np.broadcast_to(np.arange(n_tracks, dtype=np.int32)[:, None], ok.shape)
+    hx, hy, lab = hx[ok], hy[ok], lab[ok]
+    n_noise = int(round(noise_frac * hx.shape[0]))
+    return _assemble([hx], [hy], [lab], rng, (d0, phi0, np.zeros(n_tracks)), "straight", n_noise=n_noise)
+
+
 def _pt_uniform_1_20(rng, n):
     return rng.uniform(1.0, 20.0, size=n)
 
@@ -286,6 +315,7 @@ def gen_config_event(cfg: int, event_index: int = 0, *, seed: int = BASE_SEED):
     3: 3,000 prompt + 20 vertices x 10 displaced tracks, noise to 35,000 hits.
     4: prompt, track count lognormal in [200, 8000], 30 % noise.
     5: a stream event: 80 % workload-4 style, 20 % workload-3 style.
+    6: 2,000 straight tracks, |d0| <= 25 cm, 20 % noise (the kappa = 0 family).
     """
     ss = np.random.SeedSequence(seed + cfg, spawn_key=(event_index,))
     rng = np.random.default_rng(ss)
@@ -301,6 +331,8 @@ def gen_config_event(cfg: int, event_index: int = 0, *, seed: int = BASE_SEED):
         if rng.uniform() < 0.2:
             return gen_displaced_event(rng)
         return gen_prompt_event(rng, sample_track_count(rng), sample_pt_lognormal, 0.3)
+    if cfg == 6:
+        return gen_straight_event(rng)
     raise ValueError(f"unknown workload {cfg}")
 
 

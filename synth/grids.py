@@ -33,6 +33,7 @@ class Grid:
     sin_phi: np.ndarray          # fp32 [n_phi]
     d0: np.ndarray | None        # fp32 [n_d0] bin centres, None for the 2D grid
     acc_type: str                # "i32" or "u16"
+    family: str = "curved"       # "straight": (phi0, d0) lines; the kappa fields then describe d0
 
     @property
     def is_3d(self) -> bool:
@@ -104,11 +105,25 @@ def make_grid(n_phi: int, n_kappa: int, *, n_d0: int = 1, d0_range=None,
                 acc_type=acc_type)
 
 
+def make_straight_grid(n_phi: int, n_d0: int, d0_range=(-32.0, 32.0), acc_type: str = ACC_I32) -> Grid:
+    """Grid of the straight-line (phi0, d0) family: phi0 bin centres as for
+    curved tracks, and ``n_d0`` d0 bins over ``d0_range`` held in the kappa
+    fields (``kappa_min`` = lower d0 edge, ``kappa_scale`` = bins per cm)."""
+    lo, hi = float(d0_range[0]), float(d0_range[1])
+    if n_phi < 1 or n_d0 < 1 or not hi > lo:
+        raise ValueError("bad straight grid")
+    curved = make_grid(n_phi, n_d0, acc_type=acc_type)
+    return dataclasses.replace(curved, kappa_min=np.float32(lo), kappa_scale=np.float32(n_d0 / (hi - lo)),
+                               family="straight")
+
+
 # The three grids of the workloads: 256 x 128 int32; 1024 x 512 int32;
 # 64 d0 in [-30, 30) cm x 512 phi0 x 256 kappa uint16.
 GRID_2D_SMALL = make_grid(256, 128)
 GRID_2D = make_grid(1024, 512)
 GRID_3D = make_grid(512, 256, n_d0=64, d0_range=(-30.0, 30.0), acc_type=ACC_U16)
+# Straight lines: 1024 phi0 x 512 d0 bins of 0.125 cm over [-32, 32) cm, int32.
+GRID_STRAIGHT = make_straight_grid(1024, 512)
 
 
 @dataclasses.dataclass(frozen=True)

@@ -54,6 +54,12 @@ MUTANTS = {
                                "const int negative = dx != 0 ? dx < 0 : dy > 0;"),
     "vertex_peaks_x_periodic": ("const int32_t xx = ix + dx;", "const int32_t xx = (ix + dx + n_x) % n_x;"),
     "vertex_peak_threshold_strict": ("if (val < threshold)", "if (val <= threshold)"),
+    "straight_u_sign": ("float along = yh * cos_phi[j] - xh * sin_phi[j];",
+                        "float along = yh * cos_phi[j] + xh * sin_phi[j];"),
+    "straight_u_transposed": ("float along = yh * cos_phi[j] - xh * sin_phi[j];",
+                              "float along = xh * cos_phi[j] - yh * sin_phi[j];"),
+    "straight_offset_sign": ("float fd = (along - d0_min) * d0_scale;", "float fd = (along + d0_min) * d0_scale;"),
+    "straight_lower_edge_exclusive": ("if (fd >= 0.0f && fd < n_d0_f)", "if (fd > 0.0f && fd < n_d0_f)"),
 }
 
 RUNNER = r"""

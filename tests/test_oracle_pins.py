@@ -5,6 +5,7 @@ track model (Section 3), a closed form, a library routine or a hand-derived
 fixture -- never against a retyped copy of its own formula.
 """
 
+import dataclasses
 import json
 import math
 import os
@@ -537,3 +538,65 @@ def test_vertex_peak_edges_are_not_periodic():
     vacc[3, 4] = 6          # would hide (3, 0) if y wrapped
     v, c, n = vertex_peaks(vacc, 1)
     assert sorted(c.tolist()) == sorted([0 * 5 + 2, 5 * 5 + 2, 3 * 5 + 0, 3 * 5 + 4])
+
+
+# --------------------------------------------------------------------------------------
+# Straight lines: the kappa = 0 family (phi0, d0)
+# --------------------------------------------------------------------------------------
+
+def vote_straight(x, y, grid):
+    return oracle.vote_straight(x, y, grid, library=LIBRARY[0])
+
+
+def test_straight_hits_on_a_line_vote_its_cell():
+    """Noise-free hits of a line at a (phi0, d0) bin centre all vote that cell, and
+    its mirror (d0 -> -d0, phi0 -> phi0 + pi) gets as many."""
+    grid = synth.make_straight_grid(64, 48, (-12.0, 12.0))
+    for j, k in ((5, 30), (40, 10), (17, 24)):
+        phi0 = float(grid.phi_centre(j))
+        d0 = -12.0 + (k + 0.5) * 0.5
+        hx, hy, ok = synth.events.straight_hits([d0], [phi0])
+        x, y = hx[ok].astype(np.float32), hy[ok].astype(np.float32)
+        acc, n = vote_straight(x, y, grid)
+        assert acc[0, j, k] == x.size > 5
+        jm, km = (j + 32) % 64, 47 - k
+        assert acc[0, jm, km] == x.size
+        v, c, nf = peaks(acc, x.size)
+        assert sorted(c.tolist()) == sorted([j * 48 + k, jm * 48 + km])
+
+
+def test_straight_closed_form_single_hits():
+    """A hit votes, in row j, the d0 bin of r sin(phi_h - phi0_j)."""
+    grid = synth.make_straight_grid(96, 40, (-20.0, 20.0))
+    rng = np.random.default_rng(9)
+    phis = grid.phi_centre(np.arange(grid.n_phi))
+    for _ in range(40):
+        r = rng.uniform(1.0, 30.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        x, y = np.float32(r * math.cos(ph)), np.float32(r * math.sin(ph))
+        acc, n = vote_straight([x], [y], grid)
+        rr, pp = math.hypot(float(x), float(y)), math.atan2(float(y), float(x))
+        for j in range(grid.n_phi):
+            fd = (rr * math.sin(pp - phis[j]) + 20.0) * 1.0
+            row = acc[0, j]
+            if abs(fd - round(fd)) < 1e-3:
+                continue                                  # too close to a bin edge to call
+            if 0.0 <= fd < grid.n_kappa:
+                assert row[int(fd)] == 1 and row.sum() == 1
+            else:
+                assert row.sum() == 0
+
+
+def test_straight_one_vote_per_row_and_edges():
+    grid = synth.make_straight_grid(32, 64, (-120.0, 120.0))
+    ev = synth.gen_config_event(1)
+    acc, n = vote_straight(ev.x, ev.y, grid)
+    assert n == ev.n_hits * grid.n_phi
+    assert (acc.sum(axis=2) == ev.n_hits).all()
+    # phi0 = 0: u = y exactly; the lower d0 edge is inside, the upper outside
+    g = _grid_from_tables(3, 8, -4.0, 1.0, [1.0, 0.0, -1.0], [0.0, 1.0, 0.0])   # d0 in [-4, 4)
+    g = dataclasses.replace(g, family="straight")
+    acc, n = vote_straight([0.0, 0.0], [-4.0, 0.0], g)
+    assert acc[0, 0, 0] == 1 and acc[0, 0, 4] == 1
+    acc, n = vote_straight([0.0], [4.0], g)             # u = 4 = upper edge at phi0 = 0
+    assert acc[0, 0].sum() == 0 and acc[0, 2, 0] == 1   # and -4 at phi0 = pi
