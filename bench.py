@@ -55,6 +55,7 @@ def parse_args():
     ap.add_argument("--latency-events", type=int, default=64)
     ap.add_argument("--skip-per-event", action="store_true", help="skip the per-event-launch comparison")
     ap.add_argument("--skip-3d", action="store_true", help="skip the displaced-vertex (3D) batch leg")
+    ap.add_argument("--skip-straight", action="store_true", help="skip the straight-line batch leg")
     ap.add_argument("--serve-rates", default="1000,5000,20000",
                     help="offered rates (events/s) of the served stream; empty to skip")
     ap.add_argument("--serve-events", type=int, default=20000, help="measured arrivals per rate")
@@ -257,6 +258,46 @@ def displaced_3d(hough, torch, dev, synth, log_fn, n_events=8, reps=10):
             "candidates_per_event": int(n_found.sum().item()) // n_events, "vertices": vertices}
 
 
+def straight_2d(hough, torch, dev, synth, log_fn, n_events=256, reps=10):
+    """The straight-line family (2,000 lines and 20 % noise per event, 1024 phi0
+    x 512 d0 int32, threshold 7) as one graph-replayed batch of n_events."""
+    wc = synth.CONFIGS[6]
+    log_fn(f"straight-line batch of {n_events}")
+    b = synth.pack_events([synth.gen_config_event(6, i) for i in range(n_events)])
+    x = torch.from_numpy(b.x).to(dev)
+    y = torch.from_numpy(b.y).to(dev)
+    ctx = hough.HoughContext(wc.grid, device=dev, max_events=n_events, max_hits=b.n_hits)
+    cap = ctx.spec.max_candidates()
+    cand_off = np.arange(n_events + 1, dtype=np.int64) * cap
+    cands = torch.empty((n_events * cap, 2), dtype=torch.int32, device=dev)
+    n_found = torch.empty(n_events, dtype=torch.int32, device=dev)
+    n_votes = torch.empty(n_events, dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.event_batch(b.hit_off, x, y, wc.threshold, cand_off=cand_off, cands=cands, n_found=n_found,
+                        n_votes=n_votes)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.set_timing(True)
+    vote = []
+    for _ in range(4):
+        step()
+        vote.append(ctx.get_timing()[0])
+    ctx.set_timing(False)
+    evals = int(b.n_hits) * wc.grid.n_phi
+    return {"workload": "straight_batch256_2000lines_1024x512", "events": n_events, "hits": int(b.n_hits),
+            "ms_per_step": 1e3 * dt, "events_per_s": n_events / dt, "vote_ms": float(np.mean(vote[1:])),
+            "evaluations_per_s": evals / dt, "votes_per_step": int(n_votes.sum().item()),
+            "candidates_per_step": int(n_found.sum().item())}
+
+
 def served_stream(args, hough, synth, batch, log_fn):
     """Open-loop served stream: Poisson arrivals of 80 % batch-workload 2D and
     20 % displaced 3D events at each offered rate, through the library's
@@ -426,6 +467,8 @@ def main():
     line_extra = {}
     if not args.skip_3d:
         line_extra["displaced_3d"] = displaced_3d(hough, torch, dev, synth, log)
+    if not args.skip_straight:
+        line_extra["straight_2d"] = straight_2d(hough, torch, dev, synth, log)
     served = served_stream(args, hough, synth, batch, log)
     if served is not None:
         line_extra["served"] = served
