@@ -360,12 +360,15 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     constexpr int STAGERS = kHitBlock / PER;    // threads that stage
     float4 ph[PER];
     uint2 pr[PER];
-    auto fetch = [&](int64_t b0) {
+    // (always inlined, through a local: otherwise the 2D kernels kept the
+    // prefetched records in a stack slot and waited for each load at once)
+    auto fetch = [&](int64_t b0) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int64_t h = min(b0 + q * STAGERS + tid, h_end - 1);
             pr[q] = rrow[h & rmask];
-            ph[q] = hrec[h];
+            const float4 v = hrec[h];
+            ph[q] = v;
         }
     };
     if (h_begin < h_end)
