@@ -139,20 +139,27 @@ int32_t batch_tiles_per_event(const hough_ctx *c, const VoteShape &s, bool fused
     return c->g.n_d0 * vote_tiles_per_slice(c->g, s, fused);
 }
 
-VoteInputs vote_inputs(const hough_ctx *c) {
+// Tile masks instead of ranges when culling is on and a slice has few enough tiles.
+bool use_masks(const hough_ctx *c, const VoteShape &s, bool fused) {
+    return c->cull_ok && vote_tile_geom(c->g, s, fused).tiles <= kMaskTiles;
+}
+
+VoteInputs vote_inputs(const hough_ctx *c, const VoteShape &s, bool fused) {
     VoteInputs in{};
     in.hits = c->hits;
     in.ranges = c->cull_ok ? c->ranges : c->all_tiles;
     in.range_stride = c->cull_ok ? c->max_hits : 0;
     in.range_step = c->cull_ok ? 1 : 0;
+    in.mask_mode = use_masks(c, s, fused) ? 1 : 0;
     return in;
 }
 
-// Hit records (and tile ranges) for a vote launch of shape s.
+// Hit records (and tile ranges or masks) for a vote launch of shape s.
 hipError_t hit_prep(const hough_ctx *c, const VoteShape &s, bool fused, const float *x, const float *y,
                     int64_t n_hits, const int64_t *n_hits_dev, hipStream_t stream) {
     return launch_hit_prep(c->g, vote_tile_geom(c->g, s, fused), x, y, n_hits, n_hits_dev, c->hits,
-                           c->cull_ok ? c->ranges : nullptr, c->max_hits, c->cull_ok, stream);
+                           c->cull_ok ? c->ranges : nullptr, c->max_hits, c->cull_ok, use_masks(c, s, fused),
+                           stream);
 }
 
 SortWork sort_work(const hough_ctx *c, bool fused_layout) {
@@ -331,7 +338,7 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
         ce = hipEventRecord(ctx->ev_vote0, cs);
     uint32_t *a = (fused || acc_dw) ? acc_dw : ctx->acc_ws;
     if (ce == hipSuccess)
-        ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx), dd.desc,
+        ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, vs, fused), dd.desc,
                                &dd.hdr->n_items, dd.items, ctx->max_items, ctx->work_counter,
                                ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs);
     if (ce == hipSuccess && timed)
@@ -609,7 +616,7 @@ hough_status hough_vote(hough_ctx *ctx, const float *x, const float *y, int32_t 
     if (nv)
         HIP_TRY(launch_prep(nullptr, 1, nv, s));
     HIP_TRY(hit_prep(ctx, vs, false, x, y, n_hits, nullptr, s));
-    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, vs, vote_inputs(ctx), n_hits,
+    HIP_TRY(launch_vote_single(ctx->g, ctx->u16, vs, vote_inputs(ctx, vs, false), n_hits,
                                static_cast<uint32_t *>(acc), nv, s));
     return HOUGH_OK;
 }
@@ -674,7 +681,7 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
     auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
     HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, s));
     HIP_TRY(hit_prep(ctx, vs, false, x, y, hit_off[n_events], nullptr, s));
-    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx), dd.desc, &dd.hdr->n_items,
+    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, vs, false), dd.desc, &dd.hdr->n_items,
                               dd.items, ctx->max_items, ctx->work_counter, ctx->persistent_groups,
                               static_cast<uint32_t *>(acc), nv, nullptr, 0, s));
     return HOUGH_OK;

@@ -105,6 +105,7 @@ struct VoteInputs {
     const uint2 *ranges;       // [n_d0][range_stride] tile ranges per hit, or one all-tiles entry
     int64_t range_stride;      // 0 with the all-tiles entry
     int32_t range_step;        // 1 with ranges, 0 with the all-tiles entry
+    int32_t mask_mode;         // per-hit entries are 64-bit tile masks (culling on, at most kMaskTiles tiles)
 };
 
 // A tile range packs first | count << 16 (tile indices of one d0 slice,
@@ -112,6 +113,10 @@ struct VoteInputs {
 // Bit 31 of a hit's second range is kFastDiv: every phi0 row of that (hit,
 // d0 slice) has its 3D quotient operands in the range of vote_math.h.
 constexpr uint32_t kAllTiles = 0x7fffu << 16;
+// With at most kMaskTiles tiles per slice a hit's entry is instead the 64-bit
+// mask of the tiles it can vote in (bit t: tile t; low dword first), and bit
+// 63 -- bit 31 of the high dword, where kFastDiv sits -- keeps that flag.
+constexpr int32_t kMaskTiles = 63;
 constexpr uint32_t kFastDiv = 1u << 31;
 
 // Tile geometry of a vote launch: tile t of a slice owns phi0 rows
@@ -156,7 +161,7 @@ hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
 // (which then only sizes the grid).
 hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x, const float *y, int64_t n_hits,
                            const int64_t *n_hits_dev, float4 *hits, uint2 *ranges, int64_t range_stride,
-                           bool div_fast, hipStream_t stream);
+                           bool div_fast, bool masks, hipStream_t stream);
 
 // One event: hits [0, n_hits).
 hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,

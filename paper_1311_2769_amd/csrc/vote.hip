@@ -80,6 +80,7 @@ struct VoteArgs {
     const uint2 *ranges;        // [n_d0][range_stride] tile ranges per hit; or one all-tiles entry (step 0)
     int64_t range_stride;
     int32_t range_step;         // 1 with ranges, 0 without
+    int32_t mask_mode;          // entries are 64-bit tile masks
     int32_t n_hits;             // single event
     int32_t split;              // single event: hit chunks per tile
     int32_t tiles_per_slice;
@@ -200,6 +201,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const float4 *__restrict__ hrec = a.hits;
     const uint2 *__restrict__ rrow = a.ranges + static_cast<int64_t>(l) * a.range_stride;
     const int64_t rmask = a.range_step ? -1 : 0;   // per-hit ranges, or the one all-tiles entry
+    const bool mask_mode = a.mask_mode != 0;
 
     // Kappa bin of one staged hit (x, y, z, w) at row i of this lane: the bin
     // to add to, which is the spare column when the hit casts no vote there.
@@ -383,7 +385,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const bool mine = tid < STAGERS;
-            const bool keep = mine && b0 + q * STAGERS + tid < h_end && (in_range(pr[q].x) || in_range(pr[q].y));
+            const bool hit_tile = mask_mode ? ((t < 32 ? pr[q].x >> t : pr[q].y >> (t - 32)) & 1u) != 0u
+                                            : (in_range(pr[q].x) || in_range(pr[q].y));
+            const bool keep = mine && b0 + q * STAGERS + tid < h_end && hit_tile;
             const bool fast = D3 ? (pr[q].y & kFastDiv) != 0u : ph[q].w != 0.0f;
             const uint64_t mf = __ballot(keep && fast);
             const uint64_t ms = __ballot(keep && !fast);
@@ -702,7 +706,29 @@ struct PrepArgs {
     float kabs;                 // K' rounded up to fp32 (may be +inf)
     int32_t straight;           // straight-line family: records (x, y, 1, 1), arcs from the d0 range
     float dlo, dhi;             // straight: the d0 range, rounded outwards
+    int32_t mask_mode;          // write 64-bit tile masks instead of ranges (tiles <= kMaskTiles)
 };
+
+// The tiles of a cyclic range as bits of a mask (T <= kMaskTiles).
+__device__ __forceinline__ uint64_t range_bits(uint32_t r, int T) {
+    const int cnt = static_cast<int>((r >> 16) & 0x7fffu);
+    const int first = static_cast<int>(r & 0xffffu);
+    if (cnt == 0)
+        return 0ull;
+    if (cnt >= T)
+        return (1ull << T) - 1ull;
+    if (first + cnt <= T)
+        return ((1ull << cnt) - 1ull) << first;
+    return (((1ull << (T - first)) - 1ull) << first) | ((1ull << (first + cnt - T)) - 1ull);
+}
+
+// A hit's entry: the two ranges (and the kFastDiv flag), or their tile mask.
+__device__ __forceinline__ uint2 hit_entry(uint2 ranges, const PrepArgs &p) {
+    if (!p.mask_mode)
+        return ranges;
+    const uint64_t m = range_bits(ranges.x, p.tiles) | range_bits(ranges.y & ~kFastDiv, p.tiles);
+    return make_uint2(static_cast<uint32_t>(m), static_cast<uint32_t>(m >> 32) | (ranges.y & kFastDiv));
+}
 
 // 3D quotient range (every phi0 row of one hit and d0 slice): with a phi0
 // table of bin centres, r in [2^-8, 2^10], d = 0 or |d| in [2^-20, 2^10] and
@@ -830,7 +856,7 @@ __global__ void hit_prep_kernel(PrepArgs p) {
             const float m = 1e-5f + 0x1.0p-18f * (2.0f * fabsf(p.dlo) + 2.0f * fabsf(p.dhi)) * inv_r;
             out = arcs(p.dlo * inv_r - m, p.dhi * inv_r + m);
         }
-        p.ranges[i] = out;
+        p.ranges[i] = hit_entry(out, p);
         return;
     }
     for (int l = l_begin; l < l_end; ++l) {
@@ -850,7 +876,7 @@ __global__ void hit_prep_kernel(PrepArgs p) {
         }
         if (p.d0 && p.div_fast && fast_div_3d(r, d, ad))
             out.y |= kFastDiv;
-        p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = out;
+        p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = hit_entry(out, p);
     }
 }
 
@@ -935,6 +961,7 @@ void fill_inputs(VoteArgs &a, const VoteInputs &in) {
     a.ranges = in.ranges;
     a.range_stride = in.range_stride;
     a.range_step = in.range_step;
+    a.mask_mode = in.mask_mode;
 }
 
 void set_geometry(VoteArgs &a, const GridArgs &g, const VoteShape &s, bool fused) {
@@ -1002,7 +1029,7 @@ int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s) {
 
 hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x, const float *y, int64_t n_hits,
                            const int64_t *n_hits_dev, float4 *hits, uint2 *ranges, int64_t range_stride,
-                           bool div_fast, hipStream_t stream) {
+                           bool div_fast, bool masks, hipStream_t stream) {
     if (n_hits <= 0)
         return hipSuccess;
     PrepArgs p{};
@@ -1020,6 +1047,7 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     p.tile_stride = tg.stride;
     p.halo = tg.halo;
     p.div_fast = div_fast ? 1 : 0;
+    p.mask_mode = masks && ranges && tg.tiles <= kMaskTiles ? 1 : 0;
     const double kmin = g.kappa_min;
     const double kmax = static_cast<double>(g.kappa_min) + static_cast<double>(g.n_kappa) / g.kappa_scale;
     const double K = fmax(fabs(kmin), fabs(kmax)) * (1.0 + 1e-3);
