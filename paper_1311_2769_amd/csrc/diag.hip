@@ -32,7 +32,10 @@ __global__ __launch_bounds__(kProbeThreads) void lds_add_probe(int iters, unsign
     unsigned long long s = 0;
     for (int i = threadIdx.x; i < kLdsWords; i += kProbeThreads)
         s += buf[i];
-    atomicAdd(out, s);
+    for (int o = 32; o > 0; o >>= 1)
+        s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0)
+        atomicAdd(out, s);
 }
 
 __global__ __launch_bounds__(kProbeThreads) void valu_probe(int iters, float m, float c, float *out) {

@@ -221,9 +221,16 @@ __global__ __launch_bounds__(kVtxThreads) void vertex_kernel(VertexArgs a) {
                 keep = keep && (earlier ? v > w : v >= w);
             }
         }
+        // one slot reservation per wavefront, by its lowest surviving lane
+        const uint64_t pm = __ballot(keep);
         if (keep) {
+            const int leader = __ffsll(static_cast<unsigned long long>(pm)) - 1;
+            int base = 0;
+            if (lane == leader)
+                base = atomicAdd(&n_peaks, __popcll(pm));
+            base = __shfl(base, leader);
             // survivors are at most sort_size (host-checked independence bound)
-            const int slot = atomicAdd(&n_peaks, 1);
+            const int slot = base + __popcll(pm & ((1ull << lane) - 1ull));
             if (slot < a.sort_size)
                 keys[slot] = (static_cast<uint64_t>(0x7fffffffu - static_cast<uint32_t>(v)) << 32) |
                              static_cast<uint32_t>(cell);
