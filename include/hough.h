@@ -352,17 +352,20 @@ hough_status hough_selftest_divide(int64_t n, uint64_t seed, uint64_t *mismatche
  * Allocates and frees an 8-byte device buffer; synchronous. */
 hough_status hough_selftest_angles(int64_t n, uint64_t seed, float *max_err_atan2, float *max_err_asin);
 
-/* Diagnostic: on the current device, check the 3D vote's quotient by one
- * reciprocal for a grid's kappa_min, kappa_scale and n_kappa.  Over n
- * pseudo-random operand pairs of the 3D fast-path range, with quotients placed
+/* Diagnostic: on the current device, check the vote's approximate bins (one
+ * FMA per evaluation, exact redo inside a band above each integer) for a
+ * grid's kappa_min, kappa_scale and n_kappa.  form 0: the 3D quotient
+ * 2 (u - d) / den by one reciprocal; form 1: the 2D quotient u / (r2/2) from
+ * the hit's scaled reciprocal (straight-line records included).  Over n
+ * pseudo-random operand pairs of the fast-path range, with quotients placed
  * across the kappa band (half of them within a few bound-widths of a bin
- * edge), every kf0 that is not flagged near an integer must give the exact
- * kf's bin or miss.  Writes the mismatches (must be 0), the flagged pairs
- * (which the vote redoes exactly) and the pairs checked.  EINVAL when the grid
- * does not use the one-reciprocal quotient.  Allocates and frees a 24-byte
- * device buffer; synchronous. */
+ * edge), every approximate bin outside the band must be the exact kf's bin or
+ * miss.  Writes the mismatches (must be 0), the flagged pairs (which the vote
+ * redoes exactly) and the pairs checked.  EINVAL for another form or when the
+ * grid does not take approximate bins.  Allocates and frees a 24-byte device
+ * buffer; synchronous. */
 hough_status hough_selftest_near(int64_t n, uint64_t seed, float kappa_min, float kappa_scale, int32_t n_kappa,
-                                 uint64_t *mismatches, uint64_t *redone, uint64_t *checked);
+                                 int32_t form, uint64_t *mismatches, uint64_t *redone, uint64_t *checked);
 
 /* Diagnostics (measurement only; no part of the method).  Saturating probes
  * on the current device: the rate of conflict-free, no-return 32-bit LDS

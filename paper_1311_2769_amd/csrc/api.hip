@@ -429,13 +429,20 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     g.kappa_min = (grid->kappa_min == 0.0f) ? -0.0f : grid->kappa_min;
     g.kappa_scale = grid->kappa_scale;
     g.bin_bits = grid->kappa_scale >= 1.0f ? 1 : 0;
-    g.near_lim = -1.0f;
+    g.near_band = -1.0f;
+    g.kf_off = 0.0f;
+    g.kscale2 = 2.0f * grid->kappa_scale;
     g.straight = grid->family == HOUGH_STRAIGHT ? 1 : 0;
     g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
     g.cells = cells;
     g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;
-    if (grid->d0)
-        g.near_lim = vote_near_limit(g);
+    {
+        float band = 0.0f, off = 0.0f;
+        if (vote_near_band(g, &band, &off)) {
+            g.near_band = band;
+            g.kf_off = off;
+        }
+    }
     c->fused_batch = !u16 && grid->d0 == nullptr;
 
     // Default launch shapes (the autotuner may replace them).

@@ -64,7 +64,9 @@ struct GridArgs {
     float kappa_min, kappa_scale;
     int32_t row_dwords;   // dwords per (d0, phi0) row in global memory
     int32_t bin_bits;     // kappa_scale >= 1 and kappa_min != +0: the vote's unsigned range test is exact
-    float near_lim;       // 3D: 0.5 - E of the one-reciprocal quotient (vote_near_limit), or -1: exact quotients only
+    float near_band;      // 2E rounded up (vote_near_band): fast hits take the approximate bins; or -1: exact only
+    float kf_off;         // RN(E - kappa_min kappa_scale), the approximate bins' offset
+    float kscale2;        // 2 kappa_scale, the 3D approximate bins' slope
     int32_t straight;     // straight-line family: kappa := u (hit records (x, y, 1, 1)), the last axis is d0
     int64_t cells;        // cells per event
     int64_t acc_dwords;   // dwords per event accumulator
@@ -140,9 +142,11 @@ struct VoteShape {
 // ---------------------------------------------------------------------------
 bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa);
 size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa);
-// 0.5 - E, where E bounds |kf0 - kf| on |kf| <= n_kappa + 2 for the 3D
-// one-reciprocal quotient (twice the derived error), or -1 when E > 1/64.
-float vote_near_limit(const GridArgs &g);
+// Constants of the approximate bins (vote_math.h): E is twice the derived
+// bound of |kf1 - (kf + E)| on |kf| <= n_kappa + 2; *band = 2E rounded up and
+// *off = RN(E - kappa_min kappa_scale).  False (and the exact quotient only)
+// when the grid is outside the range the bound covers.
+bool vote_near_band(const GridArgs &g, float *band, float *off);
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
 TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused);
 int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);
@@ -154,8 +158,11 @@ hipError_t launch_prep_batch(EventState *state, int32_t max_events, const int32_
                              unsigned long long *n_votes, int32_t *work_counter, hipStream_t stream);
 hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
 // Per-hit preparation of a vote launch with tile geometry tg.  hits[h] =
-// (x, y, r2/2, refined 1/(r2/2)) for 2D hits whose quotient may use the
-// hoisted division (div_fast and r2/2 in range), else (x, y, r2, 0).  With
+// (x, y, r2/2, w) for 2D hits whose quotient may use the hoisted division
+// (div_fast and r2/2 in range), where w is the refined 1/(r2/2), times
+// kappa_scale when the grid takes approximate bins (near_band > 0); else
+// (x, y, r2, 0).  Straight-line hits are (x, y, 1, 1), or (x, y, 1,
+// kappa_scale) with approximate bins.  With
 // ranges: ranges[l*range_stride + h] holds the two tile ranges of slice l
 // outside which hit h cannot vote.  n_hits_dev, when given, overrides n_hits
 // (which then only sizes the grid).

@@ -5,8 +5,8 @@
 //  - The angle functions of the culling arcs (arc_math.h): their largest
 //    absolute error against fp64 over n pseudo-random arguments from their
 //    whole domain in hit_prep_kernel.
-//  - The 3D one-reciprocal quotient (vote_math.h): wherever kf0 is not near
-//    an integer, its bin (or its miss) must be the exact kf's.
+//  - The approximate bins (vote_math.h), 3D and 2D: wherever kf1 is outside
+//    the band above an integer, its bin (or its miss) must be the exact kf's.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -108,19 +108,22 @@ __device__ __forceinline__ int canonical_bin(float kf, int nk) {
     return (kf >= 0.0f && kf < static_cast<float>(nk)) ? static_cast<int>(kf) : -1;
 }
 
-// Operands of the 3D fast path: den in [2^-27, 2^23] and a numerator chosen
-// so that kf lands across the kappa band, half of the draws within a few E of
-// an integer, a tenth of them outside the band.
-__global__ void near_check_kernel(int64_t n, uint64_t seed, float kmin, float kscale, int nk, float near_lim,
-                                  unsigned long long *bad, unsigned long long *redone,
+// Operands of the fast paths, with the exact kf placed across the kappa band
+// (half of the draws within a few E of an integer, a tenth outside the
+// band).  form 0: 3D, den in [2^-27, 2^23]; form 1: 2D, h = r2/2 in
+// [2^-30, 2^30], an eighth of them h = 1 (the straight-line records).
+__global__ void near_check_kernel(int64_t n, uint64_t seed, int form, float kmin, float kscale, int nk,
+                                  float band, float off, unsigned long long *bad, unsigned long long *redone,
                                   unsigned long long *used) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const float E = 0.5f - near_lim;
+    const float E = 0.5f * band;
     unsigned long long nbad = 0, nredo = 0, nused = 0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t h1 = mix64(seed + 2 * static_cast<uint64_t>(i));
         const uint64_t h2 = mix64(seed + 2 * static_cast<uint64_t>(i) + 1);
-        const float den = fabsf(draw(h1, -27, 22));
+        float den = form == 0 ? fabsf(draw(h1, -27, 22)) : fabsf(draw(h1, -30, 29));
+        if (form == 1 && ((h1 >> 60) & 7u) == 0u)
+            den = 1.0f;
         const float u01 = static_cast<float>(h2 >> 40) * 0x1.0p-24f;
         const uint32_t kind = static_cast<uint32_t>(h2) & 15u;
         float kf_t;
@@ -128,21 +131,30 @@ __global__ void near_check_kernel(int64_t n, uint64_t seed, float kmin, float ks
             kf_t = (kind ? static_cast<float>(nk) + 2.0f : -102.0f) + 100.0f * u01;   // outside the band
         } else if (kind < 9) {
             const float m = floorf(u01 * static_cast<float>(nk + 3)) - 1.0f;            // an integer of the band
-            const float off = (static_cast<float>((h2 >> 8) & 0xffffu) * 0x1.0p-16f - 0.5f) * 8.0f * E;
-            kf_t = m + off;
+            const float dev = (static_cast<float>((h2 >> 8) & 0xffffu) * 0x1.0p-16f - 0.5f) * 8.0f * E;
+            kf_t = m + dev;
         } else {
             kf_t = -2.0f + u01 * static_cast<float>(nk + 4);
         }
-        const float q_t = 0.5f * (kf_t / kscale + kmin);
+        const float q_t = form == 0 ? 0.5f * (kf_t / kscale + kmin) : kf_t / kscale + kmin;
         const float num = q_t * den;
         if (!hough::quot_den_ok(den) || !hough::quot_num_ok(num))
             continue;
         ++nused;
-        const float kf0 = hough::kf_one_rcp(num, den, kmin, kscale);
-        const float kf = hough::kf_exact(num, den, kmin, kscale);
-        if (hough::kf_near_integer(kf0, near_lim))
+        float kf1, kf;
+        if (form == 0) {
+            kf1 = hough::kf_offset_3d(num, den, 2.0f * kscale, off);
+            kf = hough::kf_exact_3d(num, den, kmin, kscale);
+        } else {
+            kf1 = hough::kf_offset_2d(num, hough::quot_recip(den) * kscale, off);
+            kf = hough::kf_exact_2d(num, den, kmin, kscale);
+        }
+        // the vote's bin: the clamped value truncated, n_kappa for a miss
+        const float v = hough::kf_clamp(kf1, __float_as_uint(static_cast<float>(nk) + 0.5f));
+        const int b1 = static_cast<int>(v);
+        if (hough::kf_in_band(v, band))
             ++nredo;
-        else if (canonical_bin(kf0, nk) != canonical_bin(kf, nk))
+        else if ((b1 < nk ? b1 : -1) != canonical_bin(kf, nk))
             ++nbad;
     }
     if (nbad)
@@ -203,17 +215,17 @@ extern "C" hough_status hough_selftest_angles(int64_t n, uint64_t seed, float *m
 }
 
 extern "C" hough_status hough_selftest_near(int64_t n, uint64_t seed, float kappa_min, float kappa_scale,
-                                            int32_t n_kappa, uint64_t *mismatches, uint64_t *redone,
+                                            int32_t n_kappa, int32_t form, uint64_t *mismatches, uint64_t *redone,
                                             uint64_t *checked) {
-    if (n < 0 || n_kappa < 1 || !mismatches || !redone || !checked)
+    if (n < 0 || n_kappa < 1 || (form != 0 && form != 1) || !mismatches || !redone || !checked)
         return HOUGH_EINVAL;
     hough::GridArgs g{};
     g.kappa_min = kappa_min;
     g.kappa_scale = kappa_scale;
     g.n_kappa = n_kappa;
-    const float near_lim = hough::vote_near_limit(g);
-    if (near_lim <= 0.0f)
-        return HOUGH_EINVAL;     // the grid never uses the one-reciprocal quotient
+    float band = 0.0f, off = 0.0f;
+    if (!hough::vote_near_band(g, &band, &off))
+        return HOUGH_EINVAL;     // the grid never takes approximate bins
     unsigned long long *d = nullptr;
     if (hipMalloc(reinterpret_cast<void **>(&d), 3 * sizeof(unsigned long long)) != hipSuccess)
         return HOUGH_ENOMEM;
@@ -222,8 +234,8 @@ extern "C" hough_status hough_selftest_near(int64_t n, uint64_t seed, float kapp
     if (hipMemset(d, 0, sizeof h) != hipSuccess)
         st = HOUGH_EDEVICE;
     if (st == HOUGH_OK) {
-        hipLaunchKernelGGL(near_check_kernel, dim3(4096), dim3(256), 0, 0, n, seed, kappa_min, kappa_scale, n_kappa,
-                           near_lim, d, d + 1, d + 2);
+        hipLaunchKernelGGL(near_check_kernel, dim3(4096), dim3(256), 0, 0, n, seed, static_cast<int>(form), kappa_min,
+                           kappa_scale, n_kappa, band, off, d, d + 1, d + 2);
         if (hipGetLastError() != hipSuccess || hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
             st = HOUGH_EDEVICE;
     }

@@ -209,16 +209,17 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // and the operator divides.
     //
     // The range test 0 <= kf < n_kappa.  With bits (GridArgs::bin_bits) it is
-    // one unsigned minimum: kf >= +0 and kf < n_kappa exactly when the bit
-    // pattern of kf is below that of (float)n_kappa (non-negative floats order
-    // like their patterns; negative numbers and NaNs have larger patterns), so
-    // min(bits(kf), bits(n_kappa)) is kf itself when it votes and n_kappa --
-    // the spare column -- when it does not.  This needs kf never to be -0,
+    // one unsigned minimum: non-negative floats order like their bit patterns,
+    // and negative numbers and NaNs have larger patterns, so
+    // v = min(bits(kf), bits(n_kappa + 1/2)) is kf itself on [+0, n_kappa +
+    // 1/2) and n_kappa + 1/2 elsewhere; truncated, it is kf's bin when kf votes
+    // and n_kappa -- the spare column -- when it does not.  This needs kf never to be -0,
     // which the oracle would accept: kf = (kappa - kappa_min) * kappa_scale is
     // -0 only for kappa = -0 with kappa_min = +0 (the context stores -0
     // instead, which changes no vote) or when a nonzero difference (at least
     // 2^-149) times kappa_scale rounds to zero, impossible for kappa_scale >= 1.
-    const uint32_t lim_bits = __float_as_uint(nkf);
+    // (The approximate bins clamp the same way, kf_clamp.)
+    const uint32_t lim_bits = __float_as_uint(nkf + 0.5f);
     auto bin_of = [&](float kf, int i, bool valid, auto bits) -> int {
         if constexpr (decltype(bits)::value) {
             const uint32_t b = valid ? __float_as_uint(kf) : 0xffffffffu;
@@ -253,34 +254,38 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         const float kf = (kappa - kmin) * kscale;
         return bin_of(kf, i, valid, bits);
     };
-    // 3D quotient by one reciprocal (fast hits, GridArgs::near_lim > 0).
-    // q0 = (u - d) * rcp(den) is within 2^-22 |q| of the correctly rounded
-    // quotient q (rcp is within 1 ulp); on |kf| <= n_kappa + 2 that puts the
-    // kf0 built from q0 within E of the exact kf, a grid constant the host
-    // derives (vote_near_limit) with a factor 2 to spare.  When kf0 is at
-    // least E from every integer, floor(kf0) = floor(kf), and the range test
-    // (its limits 0 and n_kappa are integers) decides alike; beyond the band
-    // kf0 and kf are both out of range.  Lanes whose kf0 is nearer an integer
-    // than E redo the quotient exactly, so every bin is the exact one.
-    const float near_lim = g.near_lim;
+    // Approximate bins with exact redos (fast hits, GridArgs::near_band > 0;
+    // the bound is in vote_math.h): kf1 from one FMA, and the lanes whose kf1
+    // falls in the band above an integer take the exact kf.  num: the
+    // quotient's numerator (u in 2D), kept for the redo.
+    const float near_band = g.near_band;
+    const float kf_off = g.kf_off;
+    const float kscale2 = g.kscale2;
     auto bin_approx = [&](const float4 &h, int i, bool valid, auto bits, float &num, float &den, bool &near) -> int {
         const float u = h.y * c[i] - h.x * s[i];
-        num = u - d;
-        den = (h.z - d2 * u) + dd;
-        const float kf0 = kf_one_rcp(num, den, kmin, kscale);
-        near = kf_near_integer(kf0, near_lim);
-        return bin_of(kf0, i, valid, bits);
+        float kf1;
+        if constexpr (D3) {
+            num = u - d;
+            den = (h.z - d2 * u) + dd;
+            kf1 = kf_offset_3d(num, den, kscale2, kf_off);
+        } else {
+            num = u;
+            kf1 = kf_offset_2d(u, h.w, kf_off);
+        }
+        const float v = kf_clamp(valid ? kf1 : __builtin_nanf(""), lim_bits);
+        near = kf_in_band(v, near_band);
+        return static_cast<int>(v);
     };
     auto bin_exact = [&](float num, float den, int i, bool valid, auto bits) -> int {
-        return bin_of(kf_exact(num, den, kmin, kscale), i, valid, bits);
+        return bin_of(D3 ? kf_exact_3d(num, den, kmin, kscale) : kf_exact_2d(num, den, kmin, kscale), i, valid, bits);
     };
     auto vote = [&](int kk, int i) { lds_add(&lds[kk * stride + rowoff[i]], 1u); };
     // Evaluate and vote two hits of this lane group (valid: the hit exists).
-    // fast: 0 the division operator, 1 the hoisted exact quotient, 2 (3D) the
-    // one-reciprocal quotient with exact redos.
+    // fast: 0 the division operator, 1 the hoisted exact quotient, 2 the
+    // approximate bins with exact redos.
     auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast, auto bits) {
         int ka[RPT], kb[RPT];
-        if constexpr (D3 && decltype(fast)::value == 2) {
+        if constexpr (decltype(fast)::value == 2) {
             float na[RPT], da[RPT], nb[RPT], db[RPT];
             bool fa[RPT], fb[RPT];
             bool any_a = false, any_b = false;
@@ -293,6 +298,14 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             }
             // one wave-uniform branch for both hits, so their chains interleave
             if (__ballot(any_a || any_b)) {
+                if constexpr (!D3) {
+                    // the 2D denominator r2/2 is the hit's own
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) {
+                        da[i] = ha.z;
+                        db[i] = hb.z;
+                    }
+                }
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     if (fa[i])
@@ -415,8 +428,8 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             carry_v = ts.hits[whole + tid];      // nothing writes the staged hits until the next barrier
         if (!last)
             fetch(b0 + kHitBlock);
-        if (D3 && near_lim > 0.0f)
-            sweep(0, whole, std::integral_constant<int, D3 ? 2 : 1>{});
+        if (near_band > 0.0f)
+            sweep(0, whole, std::integral_constant<int, 2>{});
         else
             sweep(0, whole, std::true_type{});
         sweep(SLOW_END - n_slow, SLOW_END, std::false_type{});
@@ -703,6 +716,7 @@ struct PrepArgs {
     int32_t tiles, tile_stride, halo;
     uint32_t stride_magic;      // ceil(2^32 / tile_stride), 0 when tile_stride == 1
     int32_t div_fast;
+    float w_scale;              // kappa_scale with approximate bins, else 1 (hit record w)
     float kabs;                 // K' rounded up to fp32 (may be +inf)
     int32_t straight;           // straight-line family: records (x, y, 1, 1), arcs from the d0 range
     float dlo, dhi;             // straight: the d0 range, rounded outwards
@@ -811,12 +825,13 @@ __global__ void hit_prep_kernel(PrepArgs p) {
         if (p.straight) {
             // the 2D fast path then computes kappa = quot_apply(u, 1, 1) = u
             // exactly (q0 = u, both remainders 0; a -0 may come out +0, which
-            // lands in the same bin)
-            rec = make_float4(xf, yf, 1.0f, 1.0f);
+            // lands in the same bin), and the approximate bins fma(u, w, off)
+            // with w = kappa_scale
+            rec = make_float4(xf, yf, 1.0f, p.w_scale);
         } else if (p.div_fast && p.d0 == nullptr) {
             const float half = 0.5f * r2;
             if (quot_den_ok(half))
-                rec = make_float4(xf, yf, half, quot_recip(half));
+                rec = make_float4(xf, yf, half, quot_recip(half) * p.w_scale);
         }
         p.hits[i] = rec;
     }
@@ -995,26 +1010,36 @@ bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa) {
     return vote_lds_bytes(s, n_kappa) + sizeof(TileScratch<1024>) <= 160u * 1024u;
 }
 
-float vote_near_limit(const GridArgs &g) {
-    // Bound chain (one IEEE rounding per operation; ulp(x) = 2^(floor(log2 x) - 23)):
-    //   |kf| <= K = n_kappa + 2 gives |t| <= T = max(K, 2) / kappa_scale (1 + 2^-20)
-    //   for t = RN(2q - kappa_min), and |q| <= Q = (T + |kappa_min|) / 2 (1 + 2^-20);
-    //   |q0 - q| <= 2^-22 Q, so |t0 - t| <= 2^-21 Q + ulp(2T) and
-    //   |kf0 - kf| <= kappa_scale |t0 - t| (1 + 2^-20) + ulp(2K).
+bool vote_near_band(const GridArgs &g, float *band, float *off) {
+    // Bound chain on |kf| <= K = n_kappa + 2, with u = 2^-24 (one rounding per
+    // operation), M = |kappa_min| kappa_scale, kf_r the bin in real arithmetic
+    // of the same fp32 operands and P its slope term, |P| <= K + M:
+    //   exact kf:  |kf - kf_r| <= u |P| (the quotient) + 2u |kf_r| (two roundings after it);
+    //   kf1:       |kf1 - (kf_r + E)| <= 3u |P| (the reciprocal's 1 ulp, the product's
+    //              rounding) + u (E + M) (off) + u |kf1| (the FMA), |kf1| <= K + 1;
+    // second-order terms fit in the factor 1 + 2^-20.  E is twice the sum.
+    // Beyond the band (|kf_r| > K) the same relative bounds keep kf and kf1 out
+    // of [0, n_kappa) while K + M <= 2^20.  kappa_scale in [2^-60, 2^60] keeps
+    // the 2D hit constant w = RN(y kappa_scale) normal and finite.
     const double ks = g.kappa_scale;
     const double km = std::fabs(static_cast<double>(g.kappa_min));
-    if (!(ks > 0.0) || !std::isfinite(ks) || !std::isfinite(km))
-        return -1.0f;
-    auto ulp = [](double x) { return std::ldexp(1.0, std::ilogb(x) - 23); };
+    if (!(ks >= 0x1.0p-60 && ks <= 0x1.0p60) || !std::isfinite(km))
+        return false;
     const double K = static_cast<double>(g.n_kappa) + 2.0;
-    const double T = std::max(K, 2.0) / ks * (1.0 + 0x1.0p-20);
-    const double Q = (T + km) / 2.0 * (1.0 + 0x1.0p-20);
-    const double et = 0x1.0p-21 * Q + ulp(2.0 * T);
-    const double ekf = ks * et * (1.0 + 0x1.0p-20) + ulp(2.0 * K);
+    const double M = km * ks;
+    if (!(K + M <= 0x1.0p20))
+        return false;
+    const double u = 0x1.0p-24;
+    const double ekf = (4.0 * u * (K + M) + 2.0 * u * K + u * (1.0 + M) + u * (K + 1.0)) * (1.0 + 0x1.0p-20);
     const double E = 2.0 * ekf;
     if (!(E <= 1.0 / 64.0))
-        return -1.0f;
-    return static_cast<float>(0.5 - E);
+        return false;
+    float b = static_cast<float>(2.0 * E);
+    if (static_cast<double>(b) < 2.0 * E)
+        b = std::nextafter(b, INFINITY);
+    *band = b;
+    *off = static_cast<float>(E - static_cast<double>(g.kappa_min) * ks);
+    return true;
 }
 
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused) {
@@ -1047,6 +1072,7 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     p.tile_stride = tg.stride;
     p.halo = tg.halo;
     p.div_fast = div_fast ? 1 : 0;
+    p.w_scale = g.near_band > 0.0f ? g.kappa_scale : 1.0f;
     p.mask_mode = masks && ranges && tg.tiles <= kMaskTiles ? 1 : 0;
     const double kmin = g.kappa_min;
     const double kmax = static_cast<double>(g.kappa_min) + static_cast<double>(g.n_kappa) / g.kappa_scale;

@@ -60,27 +60,57 @@ __device__ __forceinline__ float quot_apply(float a, float b, float y) {
     return __builtin_fmaf(r1, y, q1);
 }
 
-// The 3D vote's fractional kappa bin from a quotient by one reciprocal:
-// kf0 = (2 (num * rcp(den)) - kappa_min) * kappa_scale, with the same two
-// roundings after the quotient as the exact kf.  num * rcp(den) is within
-// 2^-22 |q| of the correctly rounded quotient q (rcp is within 1 ulp) when
-// both operands are in the range above.
-__device__ __forceinline__ float kf_one_rcp(float num, float den, float kmin, float kscale) {
+// Approximate bins with exact redos.  The exact fractional bin is
+//   2D: kf = RN(RN(q - kappa_min) kappa_scale),     q = RN(u / h),
+//   3D: kf = RN(RN(2 q - kappa_min) kappa_scale),   q = RN(num / den),
+// and a vote lands in floor(kf) when 0 <= kf < n_kappa.  Both are replaced
+// by kf1, an estimate of kf + E from a single FMA whose slope term P
+// (q kappa_scale, or 2 q kappa_scale) is within 3 2^-24 |P| of its real value:
+//   2D: kf1 = RN(u w + off),              w = RN(y kappa_scale), y the refined
+//                                         reciprocal of h (a hit constant);
+//   3D: kf1 = RN(RN(num rcp(den)) s2 + off), s2 = 2 kappa_scale (exact);
+// with off = RN(E - kappa_min kappa_scale).  vote_near_band derives E from
+// the grid so that |kf1 - (kf + E)| < E wherever |kf| <= n_kappa + 2.  Then
+// kf1 in [k + 2E, k + 1) puts kf in (k, k + 1): floor(kf1) = floor(kf), and
+// the range test (integer limits) decides alike; further out both miss.
+// kf1 is first clamped (kf_clamp) to v in [0, n_kappa + 1/2]: a kf1 that is
+// negative or at least n_kappa + 1/2 becomes n_kappa + 1/2, and kf misses
+// then too (kf < kf1, or kf > kf1 - 2E > n_kappa with 2E <= 1/32).  A lane
+// whose v has a fractional part below the band 2E (rounded up) redoes the
+// exact kf, so every bin is the exact one; far-off lanes, whose kf1 has few
+// or no fraction bits, are never flagged.
+__device__ __forceinline__ float kf_offset_2d(float u, float w, float off) {
+    return __builtin_fmaf(u, w, off);
+}
+
+__device__ __forceinline__ float kf_offset_3d(float num, float den, float s2, float off) {
     const float q0 = num * __builtin_amdgcn_rcpf(den);
-    return __builtin_fmaf(2.0f, q0, -kmin) * kscale;
+    return __builtin_fmaf(q0, s2, off);
+}
+
+// min(kf1, n_kappa + 1/2) in bit order, given lim = bits(n_kappa + 1/2): kf1
+// itself on [0, n_kappa + 1/2), else n_kappa + 1/2 (negative numbers and NaNs
+// have larger bit patterns; kf1 = RN(a + off) is never -0, as off is not -0).
+// Truncated to an integer it is the bin, n_kappa (the spare column) for a miss.
+__device__ __forceinline__ float kf_clamp(float kf1, uint32_t lim) {
+    return __uint_as_float(min(__float_as_uint(kf1), lim));
+}
+
+// v = kf_clamp(kf1) is within the band above an integer: the exact kf must decide.
+__device__ __forceinline__ bool kf_in_band(float kf1, float band) {
+    return __builtin_amdgcn_fractf(kf1) < band;
 }
 
 // The exact kf from the correctly rounded quotient (the division operator's
-// own steps, valid in the same range).
-__device__ __forceinline__ float kf_exact(float num, float den, float kmin, float kscale) {
-    const float q = quot_apply(num, den, quot_recip(den));
-    return __builtin_fmaf(2.0f, q, -kmin) * kscale;
+// own steps, valid in the range above).
+__device__ __forceinline__ float kf_exact_2d(float u, float h, float kmin, float kscale) {
+    const float q = quot_apply(u, h, quot_recip(h));
+    return (q - kmin) * kscale;
 }
 
-// kf0 lies within 0.5 - near_lim of an integer: its floor may differ from
-// the exact kf's, so the exact kf must decide.
-__device__ __forceinline__ bool kf_near_integer(float kf0, float near_lim) {
-    return fabsf(__builtin_amdgcn_fractf(kf0) - 0.5f) > near_lim;
+__device__ __forceinline__ float kf_exact_3d(float num, float den, float kmin, float kscale) {
+    const float q = quot_apply(num, den, quot_recip(den));
+    return __builtin_fmaf(2.0f, q, -kmin) * kscale;
 }
 
 }  // namespace hough

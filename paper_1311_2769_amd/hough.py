@@ -143,7 +143,7 @@ def load(path: str = LIB_PATH):
     lib.hough_selftest_angles.argtypes = [i64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float)]
     lib.hough_selftest_near.restype = i32
-    lib.hough_selftest_near.argtypes = [i64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, i32,
+    lib.hough_selftest_near.argtypes = [i64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, i32, i32,
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                         ctypes.POINTER(ctypes.c_uint64)]
     lib.hough_status_str.restype = ctypes.c_char_p
@@ -424,11 +424,12 @@ def selftest_angles(n: int, seed: int = 1):
     return ea.value, es.value
 
 
-def selftest_near(n: int, kappa_min: float, kappa_scale: float, n_kappa: int, seed: int = 1):
-    """(mismatches, redone, checked) of the device check of the 3D one-reciprocal quotient."""
+def selftest_near(n: int, kappa_min: float, kappa_scale: float, n_kappa: int, form: int = 0, seed: int = 1):
+    """(mismatches, redone, checked) of the device check of the approximate bins
+    (form 0: 3D one-reciprocal quotient, 1: 2D scaled hit reciprocal)."""
     lib = load()
     bad, redo, used = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-    _check(lib.hough_selftest_near(int(n), int(seed), float(kappa_min), float(kappa_scale), int(n_kappa),
+    _check(lib.hough_selftest_near(int(n), int(seed), float(kappa_min), float(kappa_scale), int(n_kappa), int(form),
                                    ctypes.byref(bad), ctypes.byref(redo), ctypes.byref(used)),
            "hough_selftest_near")
     return bad.value, redo.value, used.value

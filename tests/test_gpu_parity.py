@@ -530,15 +530,22 @@ def test_culling_angle_functions_stay_within_their_budget():
         assert 0.0 < e_asin <= 1e-6
 
 
+def _grid_args(g):
+    return float(g.kappa_min), float(g.kappa_scale), g.n_kappa
+
+
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("kappa_min,kappa_scale,n_kappa", [
-    (float(synth.GRID_3D.kappa_min), float(synth.GRID_3D.kappa_scale), synth.GRID_3D.n_kappa),
-    (-0.25, 96.0, 48), (-1e-3, 1.0e5, 200), (0.0, 2048.0, 64), (-3.0, 0.75, 5)])
-def test_one_reciprocal_quotient_never_changes_a_bin(kappa_min, kappa_scale, n_kappa):
-    """Device check of the 3D vote's one-reciprocal quotient: outside the flagged
-    band around bin edges it always picks the exact bin."""
+    _grid_args(synth.GRID_3D), _grid_args(synth.GRID_2D), _grid_args(synth.GRID_STRAIGHT),
+    (-0.25, 96.0, 48), (-1e-3, 1.0e5, 200), (0.0, 2048.0, 64), (-3.0, 0.75, 5), (-20.0, 500.0, 4096)])
+def test_approximate_bins_never_change_a_bin(kappa_min, kappa_scale, n_kappa, form):
+    """Device check of the vote's approximate bins (form 0: the 3D one-reciprocal
+    quotient, 1: the 2D scaled hit reciprocal): outside the flagged band above
+    each integer they always pick the exact bin."""
     _dev()
-    bad, redo, used = hough.selftest_near(20_000_000, kappa_min, kappa_scale, n_kappa)
-    print(f"[near] kappa_min {kappa_min} scale {kappa_scale} n {n_kappa}: {used} pairs, {redo} redone", flush=True)
+    bad, redo, used = hough.selftest_near(20_000_000, kappa_min, kappa_scale, n_kappa, form)
+    print(f"[near] form {form} kappa_min {kappa_min} scale {kappa_scale} n {n_kappa}: {used} pairs, {redo} redone",
+          flush=True)
     assert used > 10_000_000
     assert bad == 0, f"{bad} bins differ"
     assert 0 < redo < used // 4
