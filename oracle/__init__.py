@@ -42,13 +42,14 @@ def _bind(lib):
     lib.hough_oracle_vote.restype = ctypes.c_int64
     lib.hough_oracle_vote.argtypes = [ctypes.c_int64, f32p, f32p, ctypes.c_int32, f32p,
                                       ctypes.c_int32, f32p, f32p, ctypes.c_int32,
-                                      ctypes.c_float, ctypes.c_float, i64p]
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, i64p]
     lib.hough_oracle_peaks.restype = ctypes.c_int64
     lib.hough_oracle_peaks.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i64p,
                                        ctypes.c_int64, ctypes.c_int64, i64p, i64p]
     i32, f32 = ctypes.c_int32, ctypes.c_float
     lib.hough_oracle_vote_straight.restype = ctypes.c_int64
-    lib.hough_oracle_vote_straight.argtypes = [ctypes.c_int64, f32p, f32p, i32, f32p, f32p, i32, f32, f32, i64p]
+    lib.hough_oracle_vote_straight.argtypes = [ctypes.c_int64, f32p, f32p, i32, f32p, f32p, i32, f32, f32, i32,
+                                               i64p]
     lib.hough_oracle_vertex_vote.restype = ctypes.c_int64
     lib.hough_oracle_vertex_vote.argtypes = [ctypes.c_int64, i64p, i64p, ctypes.c_int64,
                                              i32, f32p, i32, f32p, f32p, i32,
@@ -94,7 +95,7 @@ def vote(x, y, grid, *, library=None):
                             grid.n_d0, None if d0 is None else _ptr(d0, ctypes.c_float),
                             grid.n_phi, _ptr(cos_phi, ctypes.c_float), _ptr(sin_phi, ctypes.c_float),
                             grid.n_kappa, float(grid.kappa_min), float(grid.kappa_scale),
-                            _ptr(acc, ctypes.c_int64))
+                            int(bool(getattr(grid, "forward", False))), _ptr(acc, ctypes.c_int64))
     if n < 0:
         raise ValueError("oracle rejected the grid")
     return acc.reshape(grid.shape), int(n)
@@ -185,7 +186,8 @@ def vote_straight(x, y, grid, *, library=None):
     acc = np.zeros(grid.n_phi * grid.n_kappa, dtype=np.int64)
     n = L.hough_oracle_vote_straight(x.shape[0], _ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), grid.n_phi,
                                      _ptr(cos_phi, ctypes.c_float), _ptr(sin_phi, ctypes.c_float), grid.n_kappa,
-                                     float(grid.kappa_min), float(grid.kappa_scale), _ptr(acc, ctypes.c_int64))
+                                     float(grid.kappa_min), float(grid.kappa_scale),
+                                     int(bool(getattr(grid, "forward", False))), _ptr(acc, ctypes.c_int64))
     if n < 0:
         raise ValueError("oracle rejected the straight grid")
     return acc.reshape(1, grid.n_phi, grid.n_kappa), int(n)

@@ -41,6 +41,16 @@
  * Straight tracks: hough_oracle_vote_straight below (the two-parameter
  * family); its peaks are the peak rule above on a (1, n_phi, n_d0) array.
  *
+ * Forward-hemisphere option (forward != 0; an addition, not the paper's
+ * method): a hit votes for a phi0 bin only when it lies ahead of P0 along
+ * (cos phi0, sin phi0), i.e. ahead = x cos(phi0) + y sin(phi0) > 0, one
+ * binary32 operation each in that order (P0 itself is orthogonal to the
+ * direction, so the test does not involve d0).  Every hit is compatible with
+ * two directions of travel through it; the cut keeps the one moving away from
+ * the origin and drops the mirror solution (for a prompt track, the peak at
+ * phi0 + pi with the opposite curvature).  A hit exactly abreast (ahead == 0)
+ * does not vote.
+ *
  * Displaced vertices (Section 5): hough_oracle_vertex_vote and
  * hough_oracle_vertex_peaks below take the candidates to a binned (x, y)
  * vertex grid; their reading is stated above them.
@@ -53,13 +63,14 @@
 #include <string.h>
 
 /* Vote every hit into the accumulator (Section 3).  acc is int64 [n_d0][n_phi][n_kappa],
- * overwritten.  d0 == NULL means a 2D grid (n_d0 must be 1, d0 = +0).  Returns the number
- * of votes cast, or -1 on invalid arguments. */
+ * overwritten.  d0 == NULL means a 2D grid (n_d0 must be 1, d0 = +0).  forward != 0 applies
+ * the forward-hemisphere option.  Returns the number of votes cast, or -1 on invalid
+ * arguments. */
 int64_t hough_oracle_vote(int64_t n_hits, const float *x, const float *y,
                           int32_t n_d0, const float *d0,
                           int32_t n_phi, const float *cos_phi, const float *sin_phi,
                           int32_t n_kappa, float kappa_min, float kappa_scale,
-                          int64_t *acc)
+                          int32_t forward, int64_t *acc)
 {
     if (n_hits < 0 || n_d0 < 1 || n_phi < 1 || n_kappa < 1 || !acc)
         return -1;
@@ -78,6 +89,11 @@ int64_t hough_oracle_vote(int64_t n_hits, const float *x, const float *y,
             for (int32_t j = 0; j < n_phi; ++j) {
                 float c = cos_phi[j];
                 float s = sin_phi[j];
+                if (forward) {
+                    float ahead = xi * c + yi * s;
+                    if (!(ahead > 0.0f))
+                        continue;
+                }
                 float u = yi * c - xi * s;
                 float num = 2.0f * (u - d);
                 float den = r2 - 2.0f * d * u + d * d;
@@ -99,11 +115,13 @@ int64_t hough_oracle_vote(int64_t n_hits, const float *x, const float *y,
  * P0 = (-d0 sin phi0, d0 cos phi0) along (cos phi0, sin phi0).  A hit lies on
  * it when u = y cos(phi0) - x sin(phi0) equals d0, so for every phi0 bin it
  * votes d0 bin (int)fd, fd = (u - d0_min) * d0_scale, when 0 <= fd < n_d0
- * (binary32 operations in this order).  acc is int64 [n_phi][n_d0],
- * overwritten; cell = j * n_d0 + k.  Returns the number of votes. */
+ * (binary32 operations in this order).  forward != 0 applies the
+ * forward-hemisphere option.  acc is int64 [n_phi][n_d0], overwritten;
+ * cell = j * n_d0 + k.  Returns the number of votes. */
 int64_t hough_oracle_vote_straight(int64_t n_hits, const float *x, const float *y,
                                    int32_t n_phi, const float *cos_phi, const float *sin_phi,
-                                   int32_t n_d0, float d0_min, float d0_scale, int64_t *acc)
+                                   int32_t n_d0, float d0_min, float d0_scale, int32_t forward,
+                                   int64_t *acc)
 {
     if (n_hits < 0 || n_phi < 1 || n_d0 < 1 || !acc)
         return -1;
@@ -114,6 +132,11 @@ int64_t hough_oracle_vote_straight(int64_t n_hits, const float *x, const float *
         const float xh = x[i];
         const float yh = y[i];
         for (int32_t j = 0; j < n_phi; ++j) {
+            if (forward) {
+                float fwd = xh * cos_phi[j] + yh * sin_phi[j];
+                if (!(fwd > 0.0f))
+                    continue;
+            }
             float along = yh * cos_phi[j] - xh * sin_phi[j];
             float fd = (along - d0_min) * d0_scale;
             if (fd >= 0.0f && fd < n_d0_f) {

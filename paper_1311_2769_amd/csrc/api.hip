@@ -46,9 +46,11 @@ struct GraphKey {
     const void *x, *y, *acc, *cands, *n_found, *n_votes;
     int32_t threshold;
     int64_t hit_bucket;
+    uint32_t key_mask;      // sort-key digits that can differ (sets the sort passes)
     bool operator==(const GraphKey &o) const {
         return x == o.x && y == o.y && acc == o.acc && cands == o.cands && n_found == o.n_found &&
-               n_votes == o.n_votes && threshold == o.threshold && hit_bucket == o.hit_bucket;
+               n_votes == o.n_votes && threshold == o.threshold && hit_bucket == o.hit_bucket &&
+               key_mask == o.key_mask;
     }
 };
 
@@ -303,6 +305,23 @@ DevDesc device_descriptors(const hough_ctx *ctx) {
 // needs at most a few graphs whatever its batches hold.
 constexpr int64_t kHitBucket = 1 << 16;
 
+// Sort-key digits that can differ within the events of a batch.  A key is
+// 0x7fffffff - votes, which is 0x7fffffff XOR votes for 0 <= votes, so two
+// keys differ only within the bits of the larger count.  A cell takes at most
+// one vote per hit (one kappa bin per (d0, phi0) row), so an event of n hits
+// has counts of at most n, and uint16 cells at most 65535.
+uint32_t batch_key_mask(const hough_ctx *ctx, int32_t n_events, const int64_t *hit_off) {
+    int64_t most = 0;
+    for (int32_t e = 0; e < n_events; ++e)
+        most = std::max(most, hit_off[e + 1] - hit_off[e]);
+    if (ctx->u16)
+        most = std::min<int64_t>(most, 0xffff);
+    uint32_t mask = 0;
+    while (mask < 0x7fffffffu && static_cast<int64_t>(mask) < most)
+        mask = (mask << 1) | 1u;
+    return mask;
+}
+
 int64_t hit_bucket(int64_t hits) {
     int64_t b = kHitBucket;
     while (b < hits)
@@ -316,11 +335,12 @@ int64_t hit_bucket(int64_t hits) {
 // `timed`, events bracket the whole sequence and the vote kernel.
 hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const float *y, int32_t threshold,
                          void *acc, hough_cand *cands, int32_t *n_found, uint64_t *n_votes, int64_t bucket,
-                         bool timed) {
+                         uint32_t key_mask, bool timed) {
     DevDesc dd = device_descriptors(ctx);
     const VoteShape &vs = ctx->shape_batch;
     const bool fused = ctx->fused_batch;
     SortWork w = sort_work(ctx, fused);
+    w.key_mask = key_mask;
     w.desc = dd.desc;
     w.out = cands;
     w.n_found = n_found;
@@ -716,7 +736,8 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
         return st;
 
     const int64_t bucket = hit_bucket(hit_off[n_events]);
-    GraphKey key{x, y, acc, cands, n_found, n_votes, threshold, bucket};
+    const uint32_t key_mask = batch_key_mask(ctx, n_events, hit_off);
+    GraphKey key{x, y, acc, cands, n_found, n_votes, threshold, bucket, key_mask};
     hipGraphExec_t exec = nullptr;
     for (auto &ge : ctx->graphs)
         if (ge.key == key)
@@ -725,7 +746,7 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
         // Direct launches with events around the vote (no graph).
         if (changed)
             HIP_TRY(hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, s));
-        HIP_TRY(enqueue_batch(ctx, s, x, y, threshold, acc, cands, n_found, n_votes, bucket, true));
+        HIP_TRY(enqueue_batch(ctx, s, x, y, threshold, acc, cands, n_found, n_votes, bucket, key_mask, true));
         ctx->timed_once = true;
         if (changed) {
             HIP_TRY(hipEventRecord(ctx->desc_done, s));
@@ -738,7 +759,7 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, cs);
         if (ce == hipSuccess)
-            ce = enqueue_batch(ctx, cs, x, y, threshold, acc, cands, n_found, n_votes, bucket, false);
+            ce = enqueue_batch(ctx, cs, x, y, threshold, acc, cands, n_found, n_votes, bucket, key_mask, false);
         hipGraph_t graph = nullptr;
         hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (ce != hipSuccess) {

@@ -96,7 +96,7 @@ struct SortWork {
     hough_cand *out;          // caller's candidate array
     int32_t cap;              // used when desc == nullptr (one event)
     int32_t *n_found;         // caller's [events]
-    uint32_t key_mask;        // 0xffffffff (i32) or 0xffff (u16): digits that can differ
+    uint32_t key_mask;        // sort-key bits that can differ within an event (sets the passes)
     const int32_t *n_events_dev;  // batch: live event count on the device, or nullptr
 };
 

@@ -625,7 +625,10 @@ hipError_t launch_peaks(const GridArgs &g, bool u16, const uint32_t *acc, int32_
 }
 
 hipError_t launch_sort(const SortWork &w, int32_t n_events, hipStream_t stream) {
-    const int max_passes = w.key_mask == 0xffffu ? 2 : kMaxPasses;
+    // one pass per 8-bit digit that can differ (at least one: it places the lists)
+    int max_passes = 1;
+    while (max_passes < kMaxPasses && (w.key_mask >> (8 * max_passes)) != 0u)
+        ++max_passes;
     const unsigned later_chunks = static_cast<unsigned>((w.bound + kSortChunk - 1) / kSortChunk);
     const unsigned first_chunks = static_cast<unsigned>((w.s0.n_blocks0 + w.s0.cb - 1) / w.s0.cb);
     for (int pass = 0; pass < max_passes; ++pass) {

@@ -34,6 +34,7 @@ class Grid:
     d0: np.ndarray | None        # fp32 [n_d0] bin centres, None for the 2D grid
     acc_type: str                # "i32" or "u16"
     family: str = "curved"       # "straight": (phi0, d0) lines; the kappa fields then describe d0
+    forward: bool = False        # forward-hemisphere option: only phi0 with x cos + y sin > 0
 
     @property
     def is_3d(self) -> bool:

@@ -60,6 +60,13 @@ MUTANTS = {
                               "float along = xh * cos_phi[j] - yh * sin_phi[j];"),
     "straight_offset_sign": ("float fd = (along - d0_min) * d0_scale;", "float fd = (along + d0_min) * d0_scale;"),
     "straight_lower_edge_exclusive": ("if (fd >= 0.0f && fd < n_d0_f)", "if (fd > 0.0f && fd < n_d0_f)"),
+    "forward_not_strict": ("if (!(ahead > 0.0f))", "if (!(ahead >= 0.0f))"),
+    "forward_term_sign": ("float ahead = xi * c + yi * s;", "float ahead = xi * c - yi * s;"),
+    "forward_uses_the_offset": ("float ahead = xi * c + yi * s;", "float ahead = yi * c - xi * s;"),
+    "forward_backward": ("if (!(ahead > 0.0f))", "if (!(ahead < 0.0f))"),
+    "straight_forward_backward": ("if (!(fwd > 0.0f))", "if (!(fwd < 0.0f))"),
+    "straight_forward_operands": ("float fwd = xh * cos_phi[j] + yh * sin_phi[j];",
+                                  "float fwd = yh * cos_phi[j] + xh * sin_phi[j];"),
 }
 
 RUNNER = r"""

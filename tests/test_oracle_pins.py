@@ -600,3 +600,111 @@ def test_straight_one_vote_per_row_and_edges():
     assert acc[0, 0, 0] == 1 and acc[0, 0, 4] == 1
     acc, n = vote_straight([0.0], [4.0], g)             # u = 4 = upper edge at phi0 = 0
     assert acc[0, 0].sum() == 0 and acc[0, 2, 0] == 1   # and -4 at phi0 = pi
+
+
+# --------------------------------------------------------------------------------------
+# Forward-hemisphere option: a hit votes only where it lies ahead of P0
+# --------------------------------------------------------------------------------------
+
+def _forward(grid):
+    return dataclasses.replace(grid, forward=True)
+
+
+@pytest.mark.parametrize("which", ["small2d", "big2d", "3d"])
+def test_forward_option_keeps_the_track_and_drops_its_mirror(which):
+    """A noise-free bin-centre track moving away from the origin keeps its #hits votes at its
+    own cell under the forward option; its mirror cell (-d0, phi0 + pi, -kappa), whose direction
+    of travel puts every hit behind P0, gets none, and the candidates sit at the track."""
+    grid = {"small2d": synth.GRID_2D_SMALL, "big2d": synth.GRID_2D, "3d": synth.GRID_3D}[which]
+    fg = _forward(grid)
+    rng = np.random.default_rng(8)
+    done = 0
+    while done < 6:
+        l = int(rng.integers(0, grid.n_d0))
+        j = int(rng.integers(0, grid.n_phi))
+        k = int(rng.integers(int(grid.n_kappa * 0.25), int(grid.n_kappa * 0.75)))
+        d0, phi0, kappa = _bin_centre_track(grid, l, j, k)
+        if grid.is_3d and np.min(np.abs(synth.LAYERS_CM - abs(d0))) < 2.0:
+            continue
+        ev = synth.gen_tracks_event([d0], [phi0], [kappa])
+        if ev.n_hits < 5:
+            continue
+        acc, n = vote(ev.x, ev.y, fg)
+        full, n_full = vote(ev.x, ev.y, grid)
+        mirror = (grid.n_d0 - 1 - l, (j + grid.n_phi // 2) % grid.n_phi, grid.n_kappa - 1 - k)
+        assert acc[l, j, k] == ev.n_hits
+        assert acc[mirror] == 0 and full[mirror] == ev.n_hits
+        assert np.all(acc <= full) and 0 < n < n_full
+        v, c, nf = peaks(acc, ev.n_hits)
+        assert nf >= 1
+        for cell in c.tolist():
+            a, b, cc = cell // (grid.n_phi * grid.n_kappa), (cell // grid.n_kappa) % grid.n_phi, cell % grid.n_kappa
+            assert b == j and cc == k and abs(a - l) <= (1 if grid.is_3d else 0), (which, cell)
+        done += 1
+
+
+def test_forward_option_votes_the_half_circle_ahead():
+    """On a kappa range so wide that every (hit, phi0) pair votes, the full vote casts n_phi
+    votes per hit, and the forward vote exactly the rows within 90 degrees of the hit's own
+    direction (counted with fp64 angles): n_phi / 2 of the bin centres of an even n_phi."""
+    grid = make_grid(64, 32, kappa_half_range_inv_cm=0.05)       # kappa in [-20, 20) cm^-1
+    fg = _forward(grid)
+    rng = np.random.default_rng(21)
+    phis = grid.phi_centre(np.arange(grid.n_phi))
+    checked = 0
+    for _ in range(60):
+        r = rng.uniform(0.5, 110.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        x, y = np.float32(r * math.cos(ph)), np.float32(r * math.sin(ph))
+        ahead = np.cos(math.atan2(float(y), float(x)) - phis)
+        if np.min(np.abs(ahead)) < 1e-5:
+            continue                                     # a row too close to abreast to call
+        a_full, n_full = vote([x], [y], grid)
+        a_fwd, n_fwd = vote([x], [y], fg)
+        assert n_full == grid.n_phi
+        rows = a_fwd[0].sum(axis=1)
+        np.testing.assert_array_equal(rows, (ahead > 0).astype(np.int64))
+        assert n_fwd == grid.n_phi // 2
+        checked += 1
+    assert checked > 50
+
+
+def test_forward_option_is_strict_and_the_same_for_every_d0():
+    """Hand cases with hit (1, 0) and rows (cos, sin) = (0, 1), (1e-30, 1), (-1e-30, 1),
+    (1, 0): x cos + y sin is 0, 1e-30, -1e-30 and 1, so the forward option keeps rows 1 and 3
+    only (0 is not ahead), in every d0 slice; the full vote keeps all four."""
+    c = [0.0, 1e-30, -1e-30, 1.0]
+    s = [1.0, 1.0, 1.0, 0.0]
+    for d0 in (None, [-0.5, 0.0, 0.5]):
+        g = _grid_from_tables(4, 16, -20.0, 0.4, c, s, d0=d0)     # kappa in [-20, 20)
+        a_full, _ = vote([1.0], [0.0], g)
+        a_fwd, _ = vote([1.0], [0.0], _forward(g))
+        for l in range(g.n_d0):
+            assert a_full[l].sum(axis=1).tolist() == [1, 1, 1, 1]
+            assert a_fwd[l].sum(axis=1).tolist() == [0, 1, 0, 1]
+
+
+def test_forward_option_straight_lines():
+    """Straight family: a line's hits keep its cell and lose its mirror (d0 -> -d0,
+    phi0 -> phi0 + pi); on a d0 range wider than every hit radius, each hit votes exactly the
+    rows within 90 degrees of its direction."""
+    grid = _forward(synth.make_straight_grid(64, 48, (-12.0, 12.0)))
+    for j, k in ((5, 30), (40, 10), (17, 24)):
+        phi0 = float(grid.phi_centre(j))
+        d0 = -12.0 + (k + 0.5) * 0.5
+        hx, hy, ok = synth.events.straight_hits([d0], [phi0])
+        x, y = hx[ok].astype(np.float32), hy[ok].astype(np.float32)
+        acc, n = vote_straight(x, y, grid)
+        assert acc[0, j, k] == x.size > 5
+        assert acc[0, (j + 32) % 64, 47 - k] == 0
+        v, c, nf = peaks(acc, x.size)
+        assert c.tolist() == [j * 48 + k]
+    wide = _forward(synth.make_straight_grid(32, 64, (-120.0, 120.0)))
+    phis = wide.phi_centre(np.arange(wide.n_phi))
+    ev = synth.gen_config_event(1)
+    for i in range(0, ev.n_hits, 11):
+        ahead = np.cos(math.atan2(float(ev.y[i]), float(ev.x[i])) - phis)
+        if np.min(np.abs(ahead)) < 1e-5:
+            continue
+        acc, n = vote_straight(ev.x[i:i + 1], ev.y[i:i + 1], wide)
+        np.testing.assert_array_equal(acc[0].sum(axis=1), (ahead > 0).astype(np.int64))
