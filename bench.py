@@ -56,6 +56,7 @@ def parse_args():
     ap.add_argument("--skip-per-event", action="store_true", help="skip the per-event-launch comparison")
     ap.add_argument("--skip-3d", action="store_true", help="skip the displaced-vertex (3D) batch leg")
     ap.add_argument("--skip-straight", action="store_true", help="skip the straight-line batch leg")
+    ap.add_argument("--skip-forward", action="store_true", help="skip the forward-hemisphere batch leg")
     ap.add_argument("--serve-rates", default="1000,5000,20000",
                     help="offered rates (events/s) of the served stream; empty to skip")
     ap.add_argument("--serve-events", type=int, default=20000, help="measured arrivals per rate")
@@ -298,6 +299,45 @@ def straight_2d(hough, torch, dev, synth, log_fn, n_events=256, reps=10):
             "candidates_per_step": int(n_found.sum().item())}
 
 
+def forward_2d(hough, torch, dev, synth, batch, x, y, log_fn, reps=10):
+    """The batch workload (same events, grid and threshold) with the
+    forward-hemisphere option: each hit votes only where it lies ahead of the
+    point of closest approach, so the mirror solutions are gone."""
+    import dataclasses
+    wc = synth.CONFIGS[4]
+    grid = dataclasses.replace(wc.grid, forward=True)
+    n_events = batch.n_events
+    log_fn(f"forward-hemisphere batch of {n_events}")
+    ctx = hough.HoughContext(grid, device=dev, max_events=n_events, max_hits=batch.n_hits)
+    cap = ctx.spec.max_candidates()
+    cand_off = np.arange(n_events + 1, dtype=np.int64) * cap
+    cands = torch.empty((n_events * cap, 2), dtype=torch.int32, device=dev)
+    n_found = torch.empty(n_events, dtype=torch.int32, device=dev)
+    n_votes = torch.empty(n_events, dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.event_batch(batch.hit_off, x, y, wc.threshold, cand_off=cand_off, cands=cands, n_found=n_found,
+                        n_votes=n_votes)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.set_timing(True)
+    vote = []
+    for _ in range(6):
+        step()
+        vote.append(ctx.get_timing()[0])
+    ctx.set_timing(False)
+    return {"workload": "forward_batch256_uneven2d_1024x512", "events": n_events, "hits": int(batch.n_hits),
+            "ms_per_step": 1e3 * dt, "events_per_s": n_events / dt, "vote_ms": float(np.mean(vote[1:])),
+            "votes_per_step": int(n_votes.sum().item()), "candidates_per_step": int(n_found.sum().item())}
+
+
 def served_stream(args, hough, synth, batch, log_fn):
     """Open-loop served stream: Poisson arrivals of 80 % batch-workload 2D and
     20 % displaced 3D events at each offered rate, through the library's
@@ -469,6 +509,8 @@ def main():
         line_extra["displaced_3d"] = displaced_3d(hough, torch, dev, synth, log)
     if not args.skip_straight:
         line_extra["straight_2d"] = straight_2d(hough, torch, dev, synth, log)
+    if not args.skip_forward:
+        line_extra["forward_2d"] = forward_2d(hough, torch, dev, synth, batch, x, y, log)
     served = served_stream(args, hough, synth, batch, log)
     if served is not None:
         line_extra["served"] = served

@@ -93,6 +93,11 @@ typedef struct {
     const float *d0;         /* [dev][n_d0] d0 bin centres (cm), or NULL for 2D */
     int32_t acc_type;        /* hough_acc_type */
     int32_t family;          /* hough_family (0: curved tracks) */
+    int32_t forward;         /* 0: every phi0 bin.  1, the forward-hemisphere option (an addition to the
+                                paper's method): a hit votes for phi0 bin j only when it lies ahead of P0,
+                                    x*cos_phi[j] + y*sin_phi[j] > 0   (binary32, in this order),
+                                which drops each hit's mirror solution (the direction of travel pointing
+                                back at the origin) and about half of the votes; both families */
 } hough_grid;
 
 typedef struct {

@@ -407,6 +407,8 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         return HOUGH_EINVAL;
     if (grid->family == HOUGH_STRAIGHT && (grid->n_d0 != 1 || grid->d0 != nullptr))
         return HOUGH_EINVAL;
+    if (grid->forward != 0 && grid->forward != 1)
+        return HOUGH_EINVAL;
     if (grid->acc_type != HOUGH_ACC_I32 && grid->acc_type != HOUGH_ACC_U16)
         return HOUGH_EINVAL;
     const bool u16 = grid->acc_type == HOUGH_ACC_U16;
@@ -453,6 +455,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     g.kf_off = 0.0f;
     g.kscale2 = 2.0f * grid->kappa_scale;
     g.straight = grid->family == HOUGH_STRAIGHT ? 1 : 0;
+    g.forward = grid->forward;
     g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
     g.cells = cells;
     g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;
@@ -471,8 +474,8 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->shape_single = VoteShape{32, 512, u16 ? 1 : 4};
     c->shape_batch = VoteShape{32, 512, 1};
-    if (!vote_shape_supported(c->shape_single, u16, g.n_kappa) ||
-        !vote_shape_supported(c->shape_batch, u16, g.n_kappa)) {
+    if (!vote_shape_supported(c->shape_single, u16, g.n_kappa, g.forward != 0) ||
+        !vote_shape_supported(c->shape_batch, u16, g.n_kappa, g.forward != 0)) {
         delete c;
         return HOUGH_EINVAL;   // a kappa row too long for a 32-row LDS tile
     }
@@ -492,7 +495,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
             if (!tune_lookup(cache, key, &e))
                 continue;
             const VoteShape s{e.rows, e.threads, which == 1 ? 1 : e.split};
-            if (vote_shape_supported(s, u16, g.n_kappa))
+            if (vote_shape_supported(s, u16, g.n_kappa, g.forward != 0))
                 (which == 0 ? c->shape_single : c->shape_batch) = s;
         }
     }
@@ -575,7 +578,7 @@ hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32
     VoteShape s{rows, threads, split};
     if (which == 1 && split != 1)
         return HOUGH_EINVAL;
-    if (!vote_shape_supported(s, ctx->u16, ctx->g.n_kappa))
+    if (!vote_shape_supported(s, ctx->u16, ctx->g.n_kappa, ctx->g.forward != 0))
         return HOUGH_EINVAL;
     if (which == 1 && std::max(batch_tiles_per_event(ctx, s, true), batch_tiles_per_event(ctx, s, false)) *
                               static_cast<int64_t>(ctx->max_events) > ctx->max_items)

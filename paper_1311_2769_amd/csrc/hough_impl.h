@@ -68,6 +68,7 @@ struct GridArgs {
     float kf_off;         // RN(E - kappa_min kappa_scale), the approximate bins' offset
     float kscale2;        // 2 kappa_scale, the 3D approximate bins' slope
     int32_t straight;     // straight-line family: kappa := u (hit records (x, y, 1, 1)), the last axis is d0
+    int32_t forward;      // forward-hemisphere option: a vote also needs x cos + y sin > 0
     int64_t cells;        // cells per event
     int64_t acc_dwords;   // dwords per event accumulator
 };
@@ -140,7 +141,7 @@ struct VoteShape {
 // ---------------------------------------------------------------------------
 // Launchers (return hipSuccess or the first launch error).
 // ---------------------------------------------------------------------------
-bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa);
+bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa, bool forward);
 size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa);
 // Constants of the approximate bins (vote_math.h): E is twice the derived
 // bound of |kf1 - (kf + E)| on |kf| <= n_kappa + 2; *band = 2E rounded up and

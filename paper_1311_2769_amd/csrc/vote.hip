@@ -127,7 +127,7 @@ __device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v) {
 
 // Vote hits [h_begin, h_end) of event e into tile t of d0 slice l, then either
 // flush it (unfused) or search its interior rows for peaks (fused).
-template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
+template <bool U16, bool D3, int ROWS, int NT, bool FUSED, bool FWD>
 __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begin, int64_t h_end,
                           uint32_t *__restrict__ acc_event, bool atomic_flush, unsigned long long *n_votes,
                           uint32_t *lds, TileScratch<NT> &ts) {
@@ -229,7 +229,18 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             return ok ? static_cast<int>(kf) : trash_v;
         }
     };
-    auto bin = [&](const float4 &h, int i, bool valid, auto fast, auto bits) -> int {
+    // Forward option: the row counts only when the hit lies ahead,
+    // x c + y s > 0 in binary32 (NaN rows past the tile fail it too).
+    auto ahead = [&](const float4 &h, int i, bool valid, auto fwd) -> bool {
+        if constexpr (decltype(fwd)::value) {
+            const float w = h.x * c[i] + h.y * s[i];
+            return valid && w > 0.0f;
+        } else {
+            return valid;
+        }
+    };
+    auto bin = [&](const float4 &h, int i, bool valid, auto fast, auto bits, auto fwd) -> int {
+        valid = ahead(h, i, valid, fwd);
         const float u = h.y * c[i] - h.x * s[i];
         float kappa;
         if constexpr (D3) {
@@ -261,7 +272,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     const float near_band = g.near_band;
     const float kf_off = g.kf_off;
     const float kscale2 = g.kscale2;
-    auto bin_approx = [&](const float4 &h, int i, bool valid, auto bits, float &num, float &den, bool &near) -> int {
+    auto bin_approx = [&](const float4 &h, int i, bool valid, auto bits, auto fwd, float &num, float &den,
+                          bool &near) -> int {
+        valid = ahead(h, i, valid, fwd);
         const float u = h.y * c[i] - h.x * s[i];
         float kf1;
         if constexpr (D3) {
@@ -283,7 +296,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // Evaluate and vote two hits of this lane group (valid: the hit exists).
     // fast: 0 the division operator, 1 the hoisted exact quotient, 2 the
     // approximate bins with exact redos.
-    auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast, auto bits) {
+    auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast, auto bits, auto fwd) {
         int ka[RPT], kb[RPT];
         if constexpr (decltype(fast)::value == 2) {
             float na[RPT], da[RPT], nb[RPT], db[RPT];
@@ -291,8 +304,8 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             bool any_a = false, any_b = false;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                ka[i] = bin_approx(ha, i, va, bits, na[i], da[i], fa[i]);
-                kb[i] = bin_approx(hb, i, vb, bits, nb[i], db[i], fb[i]);
+                ka[i] = bin_approx(ha, i, va, bits, fwd, na[i], da[i], fa[i]);
+                kb[i] = bin_approx(hb, i, vb, bits, fwd, nb[i], db[i], fb[i]);
                 any_a |= fa[i];
                 any_b |= fb[i];
             }
@@ -317,8 +330,8 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         } else {
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                ka[i] = bin(ha, i, va, fast, bits);
-                kb[i] = bin(hb, i, vb, fast, bits);
+                ka[i] = bin(ha, i, va, fast, bits, fwd);
+                kb[i] = bin(hb, i, vb, fast, bits, fwd);
             }
         }
 #pragma unroll
@@ -334,7 +347,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // read never waits for atomics still in flight.  Whole trips need no
     // per-lane checks; a tail of fewer than 4G hits checks.
     const int lg = wave * HPW + hsub;
-    auto sweep_with = [&](int lo, int hi, auto fast, auto bits) {
+    auto sweep_with = [&](int lo, int hi, auto fast, auto bits, auto fwd) {
         if (lo >= hi)
             return;
         const float4 *hp = ts.hits + lg;
@@ -342,24 +355,26 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         float4 a0 = hp[it], b0 = hp[it + G];
         for (; it + 4 * G <= hi; it += 4 * G) {
             const float4 a1 = hp[it + 2 * G], b1 = hp[it + 3 * G];
-            eval2(a0, b0, true, true, fast, bits);
+            eval2(a0, b0, true, true, fast, bits, fwd);
             a0 = hp[it + 4 * G];
             b0 = hp[it + 5 * G];
-            eval2(a1, b1, true, true, fast, bits);
+            eval2(a1, b1, true, true, fast, bits, fwd);
         }
         if (it < hi) {
             const float4 a1 = hp[it + 2 * G], b1 = hp[it + 3 * G];
-            eval2(a0, b0, it + lg < hi, it + G + lg < hi, fast, bits);
+            eval2(a0, b0, it + lg < hi, it + G + lg < hi, fast, bits, fwd);
             if (it + 2 * G < hi)
-                eval2(a1, b1, it + 2 * G + lg < hi, it + 3 * G + lg < hi, fast, bits);
+                eval2(a1, b1, it + 2 * G + lg < hi, it + 3 * G + lg < hi, fast, bits, fwd);
         }
     };
+    // (the forward option is a kernel of its own: its variants inlined here
+    // beside the default ones cost the default kernel about 3 %)
     const bool bin_bits = g.bin_bits != 0;
     auto sweep = [&](int lo, int hi, auto fast) {
         if (bin_bits)
-            sweep_with(lo, hi, fast, std::true_type{});
+            sweep_with(lo, hi, fast, std::true_type{}, std::integral_constant<bool, FWD>{});
         else
-            sweep_with(lo, hi, fast, std::false_type{});
+            sweep_with(lo, hi, fast, std::false_type{}, std::integral_constant<bool, FWD>{});
     };
     // Is this tile in the cyclic tile range r?
     auto in_range = [&](uint32_t r) {
@@ -612,7 +627,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     lds_barrier();   // the LDS tile and scratch are reused by the next item
 }
 
-template <bool U16, bool D3, int ROWS, int NT, bool FUSED>
+template <bool U16, bool D3, int ROWS, int NT, bool FUSED, bool FWD>
 __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ TileScratch<NT> ts;
@@ -626,7 +641,7 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
         const int64_t per = (n + a.split - 1) / a.split;
         const int64_t hb = static_cast<int64_t>(blockIdx.y) * per;
         const int64_t he = min(n, hb + per);
-        vote_tile<U16, D3, ROWS, NT, FUSED>(a, 0, l, t, hb, he, a.acc, a.split > 1, a.n_votes, lds, ts);
+        vote_tile<U16, D3, ROWS, NT, FUSED, FWD>(a, 0, l, t, hb, he, a.acc, a.split > 1, a.n_votes, lds, ts);
         return;
     }
     const int32_t n_items = *a.n_items;
@@ -646,7 +661,7 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
         const int l = wi.tile / T;
         const int t = wi.tile - l * T;
         uint32_t *acc_e = a.acc ? a.acc + static_cast<int64_t>(wi.event) * a.g.acc_dwords : nullptr;
-        vote_tile<U16, D3, ROWS, NT, FUSED>(a, wi.event, l, t, ev.hit_begin, ev.hit_end, acc_e, false,
+        vote_tile<U16, D3, ROWS, NT, FUSED, FWD>(a, wi.event, l, t, ev.hit_begin, ev.hit_end, acc_e, false,
                                             a.n_votes ? a.n_votes + wi.event : nullptr, lds, ts);
         if (!a.work_counter)
             return;
@@ -719,6 +734,7 @@ struct PrepArgs {
     float w_scale;              // kappa_scale with approximate bins, else 1 (hit record w)
     float kabs;                 // K' rounded up to fp32 (may be +inf)
     int32_t straight;           // straight-line family: records (x, y, 1, 1), arcs from the d0 range
+    int32_t forward;            // forward-hemisphere option: the first arc only
     float dlo, dhi;             // straight: the d0 range, rounded outwards
     int32_t mask_mode;          // write 64-bit tile masks instead of ranges (tiles <= kMaskTiles)
 };
@@ -846,19 +862,25 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     const float sc = static_cast<float>(p.n_phi) * 0.159154943f;
     const float pi = 3.14159274f;
     const int l_end = min(l_begin + kPrepSlices, p.d0 ? p.n_d0 : 1);
-    // the sine interval -> two arcs -> two tile ranges
+    // the sine interval -> two arcs -> two tile ranges.  The first arc,
+    // phi_h - phi0 in [asin(lo), asin(hi)] within [-pi/2, pi/2], holds the
+    // rows where the hit lies ahead (cos(phi_h - phi0) >= 0); the second its
+    // mirror.  The forward option keeps the first alone: the vote's own
+    // ahead test decides the rows within the arc widening of +-pi/2, where
+    // fp32 may call a row either way (within 1e-6 rad of the real boundary).
+    const bool fwd = p.forward != 0;
     auto arcs = [&](float slo, float shi) {
         if (!(isfinite(slo) && isfinite(shi)))
             return make_uint2(kAllTiles, 0u);   // full circle
         if (slo > 1.0f || shi < -1.0f)
             return make_uint2(0u, 0u);
-        if (slo <= -1.0f && shi >= 1.0f)
+        if (!fwd && slo <= -1.0f && shi >= 1.0f)
             return make_uint2(kAllTiles, 0u);
         const float alo = arc_asin(fmaxf(slo, -1.0f));
         const float ahi = arc_asin(fminf(shi, 1.0f));
         const float pm = ph - pi;
         return make_uint2(tile_range(pack_arc(ph - ahi, ph - alo, p.n_phi, sc), p),
-                          tile_range(pack_arc(pm + alo, pm + ahi, p.n_phi, sc), p));
+                          fwd ? 0u : tile_range(pack_arc(pm + alo, pm + ahi, p.n_phi, sc), p));
     };
     if (p.straight) {
         // Straight lines: a vote needs u_c in [dlo, dhi] up to the rounding of
@@ -932,34 +954,49 @@ __global__ void zero_kernel(uint32_t *p, int64_t n) {
 
 using VoteFn = void (*)(VoteArgs);
 
-template <bool U16, bool D3, bool FUSED>
+template <bool U16, bool D3, bool FUSED, bool FWD>
 VoteFn pick_shape(int rows, int threads) {
     const int key = rows * 10000 + threads;
-    switch (key) {
-        case 32 * 10000 + 256: return vote_kernel<U16, D3, 32, 256, FUSED>;
-        case 32 * 10000 + 512: return vote_kernel<U16, D3, 32, 512, FUSED>;
-        case 32 * 10000 + 1024: return vote_kernel<U16, D3, 32, 1024, FUSED>;
-        case 64 * 10000 + 256: return vote_kernel<U16, D3, 64, 256, FUSED>;
-        case 64 * 10000 + 512: return vote_kernel<U16, D3, 64, 512, FUSED>;
-        case 64 * 10000 + 1024: return vote_kernel<U16, D3, 64, 1024, FUSED>;
-        case 128 * 10000 + 256: return vote_kernel<U16, D3, 128, 256, FUSED>;
-        case 128 * 10000 + 512: return vote_kernel<U16, D3, 128, 512, FUSED>;
-        case 128 * 10000 + 1024: return vote_kernel<U16, D3, 128, 1024, FUSED>;
-        default: return nullptr;
+    // the forward option comes in the 32-row tiles only (every default shape)
+    if constexpr (FWD) {
+        switch (key) {
+            case 32 * 10000 + 256: return vote_kernel<U16, D3, 32, 256, FUSED, true>;
+            case 32 * 10000 + 512: return vote_kernel<U16, D3, 32, 512, FUSED, true>;
+            case 32 * 10000 + 1024: return vote_kernel<U16, D3, 32, 1024, FUSED, true>;
+            default: return nullptr;
+        }
+    } else {
+        switch (key) {
+            case 32 * 10000 + 256: return vote_kernel<U16, D3, 32, 256, FUSED, false>;
+            case 32 * 10000 + 512: return vote_kernel<U16, D3, 32, 512, FUSED, false>;
+            case 32 * 10000 + 1024: return vote_kernel<U16, D3, 32, 1024, FUSED, false>;
+            case 64 * 10000 + 256: return vote_kernel<U16, D3, 64, 256, FUSED, false>;
+            case 64 * 10000 + 512: return vote_kernel<U16, D3, 64, 512, FUSED, false>;
+            case 64 * 10000 + 1024: return vote_kernel<U16, D3, 64, 1024, FUSED, false>;
+            case 128 * 10000 + 256: return vote_kernel<U16, D3, 128, 256, FUSED, false>;
+            case 128 * 10000 + 512: return vote_kernel<U16, D3, 128, 512, FUSED, false>;
+            case 128 * 10000 + 1024: return vote_kernel<U16, D3, 128, 1024, FUSED, false>;
+            default: return nullptr;
+        }
     }
 }
 
-VoteFn pick_vote(bool u16, bool d3, bool fused, int rows, int threads) {
+template <bool FWD>
+VoteFn pick_kind(bool u16, bool d3, bool fused, int rows, int threads) {
     if (fused)
-        return (!u16 && !d3) ? pick_shape<false, false, true>(rows, threads) : nullptr;
+        return (!u16 && !d3) ? pick_shape<false, false, true, FWD>(rows, threads) : nullptr;
     if (u16)
-        return d3 ? pick_shape<true, true, false>(rows, threads) : pick_shape<true, false, false>(rows, threads);
-    return d3 ? pick_shape<false, true, false>(rows, threads) : pick_shape<false, false, false>(rows, threads);
+        return d3 ? pick_shape<true, true, false, FWD>(rows, threads) : pick_shape<true, false, false, FWD>(rows, threads);
+    return d3 ? pick_shape<false, true, false, FWD>(rows, threads) : pick_shape<false, false, false, FWD>(rows, threads);
+}
+
+VoteFn pick_vote(bool u16, bool d3, bool fused, bool fwd, int rows, int threads) {
+    return fwd ? pick_kind<true>(u16, d3, fused, rows, threads) : pick_kind<false>(u16, d3, fused, rows, threads);
 }
 
 hipError_t launch_vote(const VoteArgs &a, bool u16, bool fused, const VoteShape &s, dim3 grid,
                        hipStream_t stream) {
-    VoteFn fn = pick_vote(u16, a.g.d0 != nullptr, fused, s.rows, s.threads);
+    VoteFn fn = pick_vote(u16, a.g.d0 != nullptr, fused, a.g.forward != 0, s.rows, s.threads);
     if (!fn)
         return hipErrorInvalidValue;
     const size_t lds = vote_lds_bytes(s, a.g.n_kappa);
@@ -1001,8 +1038,8 @@ size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa) {
     return (static_cast<size_t>(n_kappa) + 1) * static_cast<size_t>(s.rows) * sizeof(uint32_t);
 }
 
-bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa) {
-    if (!pick_vote(u16, false, false, s.rows, s.threads))
+bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa, bool forward) {
+    if (!pick_vote(u16, false, false, forward, s.rows, s.threads))
         return false;
     if (s.split < 1 || s.split > 64)
         return false;
@@ -1082,6 +1119,7 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
         Kf = nextafterf(Kf, INFINITY);
     p.kabs = std::isnan(K) ? INFINITY : Kf;
     p.straight = g.straight;
+    p.forward = g.forward;
     if (g.straight) {
         const double lo = g.kappa_min;
         const double hi = lo + static_cast<double>(g.n_kappa) / g.kappa_scale;

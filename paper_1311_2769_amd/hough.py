@@ -46,7 +46,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [("n_d0", ctypes.c_int32), ("n_phi", ctypes.c_int32), ("n_kappa", ctypes.c_int32),
                 ("kappa_min", ctypes.c_float), ("kappa_scale", ctypes.c_float),
                 ("cos_phi", ctypes.c_void_p), ("sin_phi", ctypes.c_void_p), ("d0", ctypes.c_void_p),
-                ("acc_type", ctypes.c_int32), ("family", ctypes.c_int32)]
+                ("acc_type", ctypes.c_int32), ("family", ctypes.c_int32), ("forward", ctypes.c_int32)]
 
 
 class _VertexGrid(ctypes.Structure):
@@ -184,15 +184,16 @@ class GridSpec:
     d0: np.ndarray | None
     acc_u16: bool
     straight: bool = False     # the (phi0, d0) straight-line family; the kappa fields describe d0
+    forward: bool = False      # forward-hemisphere option: only phi0 with x cos + y sin > 0
 
     @classmethod
     def from_grid(cls, g):
         """From any object with the fields of a grid (n_d0, n_phi, ..., acc_type "i32"/"u16",
-        optionally family "curved"/"straight")."""
+        optionally family "curved"/"straight" and forward)."""
         return cls(int(g.n_d0), int(g.n_phi), int(g.n_kappa), float(g.kappa_min), float(g.kappa_scale),
                    np.asarray(g.cos_phi, np.float32), np.asarray(g.sin_phi, np.float32),
                    None if g.d0 is None else np.asarray(g.d0, np.float32), g.acc_type == "u16",
-                   getattr(g, "family", "curved") == "straight")
+                   getattr(g, "family", "curved") == "straight", bool(getattr(g, "forward", False)))
 
     @property
     def cells(self):
@@ -242,7 +243,7 @@ class HoughContext:
         self.d0 = None if s.d0 is None else torch.from_numpy(s.d0.copy()).to(self.device)
         g = _Grid(s.n_d0, s.n_phi, s.n_kappa, s.kappa_min, s.kappa_scale, self.cos_phi.data_ptr(),
                   self.sin_phi.data_ptr(), None if self.d0 is None else self.d0.data_ptr(),
-                  ACC_U16 if s.acc_u16 else ACC_I32, 1 if s.straight else 0)
+                  ACC_U16 if s.acc_u16 else ACC_I32, 1 if s.straight else 0, 1 if s.forward else 0)
         opts = _Opts(int(max_events), int(max_hits), tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -496,7 +497,8 @@ class Server:
             self._tables.append((c, sn, d0))
             structs[i] = _Grid(sp.n_d0, sp.n_phi, sp.n_kappa, sp.kappa_min, sp.kappa_scale, c.data_ptr(),
                                sn.data_ptr(), None if d0 is None else d0.data_ptr(),
-                               ACC_U16 if sp.acc_u16 else ACC_I32, 1 if sp.straight else 0)
+                               ACC_U16 if sp.acc_u16 else ACC_I32, 1 if sp.straight else 0,
+                               1 if sp.forward else 0)
         self._keep = [structs]
         thr = (ctypes.c_int32 * n)(*[int(t) for t in thresholds])
 

@@ -69,6 +69,8 @@ def test_null_context_is_rejected_without_touching_the_device(lib):
     assert lib.hough_ctx_create(ctypes.byref(out), ctypes.byref(g), None) == EINVAL
     g = _Grid(2, 8, 8, -1.0, 4.0, 1, 1, 1, 0, 1)            # straight lines have no d0 axis of their own
     assert lib.hough_ctx_create(ctypes.byref(out), ctypes.byref(g), None) == EINVAL
+    g = _Grid(1, 8, 8, -1.0, 4.0, 1, 1, None, 0, 0, 2)      # forward option is 0 or 1
+    assert lib.hough_ctx_create(ctypes.byref(out), ctypes.byref(g), None) == EINVAL
 
 
 def test_product_package_does_not_import_the_oracle():
