@@ -192,7 +192,28 @@ hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int3
                             hough_cand *vout, const int64_t *vout_off, int32_t *n_vertices, int32_t *vacc,
                             void *stream);
 
-/* Vote and find peaks for a batch of independent events in one pass/* Vote and find peaks for a batch of independent events in one pass
+/* Hit association (Section 3: a track candidate is made by the hits
+ * compatible with it) for one event.  Hit h belongs to candidate c when c has
+ * votes >= min_votes and h votes -- the vote of hough_vote, with the grid's
+ * family and forward option -- into a cell of c's window, the cells within
+ * one bin of c's on every axis (phi0 modulo n_phi; d0 and kappa inside the
+ * grid): the window of the peak rule.
+ *   x, y:      [dev][n_hits] fp32 hits of the event.
+ *   cands:     [dev][cands_cap] the event's candidates (e.g. hough_peaks' list);
+ *              the first min(*n_cands, cands_cap) are used, and their cells must
+ *              be distinct (a repeated cell keeps one of its indices).
+ *   n_cands:   [dev] int32 candidate count (e.g. hough_peaks' n_found).
+ *   pairs:     [dev][cap][2] int32 (candidate index, hit index), each pair once,
+ *              in no particular order; the first min(*n_pairs, cap) are written.
+ *   n_pairs:   [dev] uint64 (8-byte aligned), the full number of pairs.
+ * Uses the context's cell map (cells int32): calls on one context must not
+ * overlap.  Allocates nothing; asynchronous on stream.  EINVAL: null required
+ * pointers, negative sizes, a misaligned n_pairs. */
+hough_status hough_associate(hough_ctx *ctx, const float *x, const float *y, int32_t n_hits,
+                             const hough_cand *cands, const int32_t *n_cands, int32_t cands_cap, int32_t min_votes,
+                             int32_t *pairs, int64_t cap, uint64_t *n_pairs, void *stream);
+
+/* Vote and find peaks for a batch of independent events in one pass
  * (Section 4: hits, and so events, are independent).  Equivalent, bit for bit,
  * to hough_vote followed by hough_peaks on each event.
  *   hit_off:  host [n_events+1] CSR offsets into x, y (hit_off[0] == 0).

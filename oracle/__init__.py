@@ -54,6 +54,10 @@ def _bind(lib):
     lib.hough_oracle_vertex_vote.argtypes = [ctypes.c_int64, i64p, i64p, ctypes.c_int64,
                                              i32, f32p, i32, f32p, f32p, i32,
                                              i32, f32p, f32, f32, i32, f32p, f32, f32, i64p]
+    lib.hough_oracle_associate.restype = ctypes.c_int64
+    lib.hough_oracle_associate.argtypes = [ctypes.c_int64, f32p, f32p, i32, f32p, i32, f32p, f32p, i32, f32, f32,
+                                           i32, i32, ctypes.c_int64, i64p, i64p, ctypes.c_int64, ctypes.c_int64,
+                                           i64p, i64p]
     lib.hough_oracle_vertex_peaks.restype = ctypes.c_int64
     lib.hough_oracle_vertex_peaks.argtypes = [i32, i32, i64p, ctypes.c_int64, ctypes.c_int64, i64p, i64p]
     return lib
@@ -198,3 +202,29 @@ def find_straight(x, y, grid, threshold, cap=None, *, library=None):
     acc, n_votes = vote_straight(x, y, grid, library=library)
     v, c, n = peaks(acc, threshold, cap, library=library)
     return acc, n_votes, v, c, n
+
+
+def associate(x, y, grid, cand_votes, cand_cells, min_votes, *, library=None):
+    """Hit association (reading in hough_oracle.c): int64 arrays (candidate index,
+    hit index) of every pair, in candidate order then hit order."""
+    L = library or lib()
+    x, y = _f32(x), _f32(y)
+    if x.shape != y.shape or x.ndim != 1:
+        raise ValueError("x and y must be 1-D arrays of equal length")
+    cv = np.ascontiguousarray(cand_votes, dtype=np.int64)
+    cc = np.ascontiguousarray(cand_cells, dtype=np.int64)
+    cos_phi, sin_phi = _f32(grid.cos_phi), _f32(grid.sin_phi)
+    d0 = None if grid.d0 is None else _f32(grid.d0)
+    family = 1 if getattr(grid, "family", "curved") == "straight" else 0
+    args = (x.shape[0], _ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), grid.n_d0,
+            None if d0 is None else _ptr(d0, ctypes.c_float), grid.n_phi, _ptr(cos_phi, ctypes.c_float),
+            _ptr(sin_phi, ctypes.c_float), grid.n_kappa, float(grid.kappa_min), float(grid.kappa_scale), family,
+            int(bool(getattr(grid, "forward", False))), cv.shape[0], _ptr(cv, ctypes.c_int64),
+            _ptr(cc, ctypes.c_int64), int(min_votes))
+    n = L.hough_oracle_associate(*args, 0, None, None)
+    if n < 0:
+        raise ValueError("oracle rejected the association arguments")
+    out_c = np.zeros(max(n, 1), dtype=np.int64)
+    out_h = np.zeros(max(n, 1), dtype=np.int64)
+    L.hough_oracle_associate(*args, n, _ptr(out_c, ctypes.c_int64), _ptr(out_h, ctypes.c_int64))
+    return out_c[:n].copy(), out_h[:n].copy()

@@ -51,6 +51,9 @@
  * phi0 + pi with the opposite curvature).  A hit exactly abreast (ahead == 0)
  * does not vote.
  *
+ * Hit association (Section 3 reads each track candidate as the hits that
+ * made it): hough_oracle_associate below; its reading is stated above it.
+ *
  * Displaced vertices (Section 5): hough_oracle_vertex_vote and
  * hough_oracle_vertex_peaks below take the candidates to a binned (x, y)
  * vertex grid; their reading is stated above them.
@@ -372,4 +375,95 @@ int64_t hough_oracle_vertex_peaks(int32_t n_x, int32_t n_y, const int64_t *vacc,
     }
     free(list);
     return n_found;
+}
+
+/*
+ * Hit association (Section 3: a track candidate is a local maximum of the
+ * votes, made by the hits compatible with it).  Reading: hit h belongs to
+ * candidate C = (lc, jc, kc) when h casts a vote into some cell of C's
+ * neighbourhood, the cells (lc + dl, jc + dj, kc + dk) with dl, dj, dk in
+ * {-1, 0, 1} -- dj modulo n_phi, dl and dk inside the grid, dl = 0 for a 2D
+ * or straight grid -- i.e. the same 3x3(x3) window as the peak rule.  The
+ * vote is the one of hough_oracle_vote (curved, family 0) or
+ * hough_oracle_vote_straight (family 1), with the forward option when
+ * forward != 0, recomputed here per (hit, slice, row).  Only candidates with
+ * votes >= min_votes take part.  Writes the pairs (candidate index, hit
+ * index) in candidate order, hits ascending within a candidate: the first
+ * min(n_pairs, cap).  Returns n_pairs, or -1 on invalid arguments.
+ */
+static int assoc_bin(float hx, float hy, float hr2, int32_t family, int32_t forward, float dl0,
+                     float cj, float sj, float kmin, float kscale, int32_t nk, int32_t *bin)
+{
+    if (forward) {
+        float front = hx * cj + hy * sj;
+        if (!(front > 0.0f))
+            return 0;
+    }
+    float off = hy * cj - hx * sj;
+    float frac;
+    if (family == 1) {
+        frac = (off - kmin) * kscale;
+    } else {
+        float twice = 2.0f * (off - dl0);
+        float chord2 = hr2 - 2.0f * dl0 * off + dl0 * dl0;
+        float curv = twice / chord2;
+        frac = (curv - kmin) * kscale;
+    }
+    if (frac >= 0.0f && frac < (float)nk) {
+        *bin = (int32_t)frac;
+        return 1;
+    }
+    return 0;
+}
+
+int64_t hough_oracle_associate(int64_t n_hits, const float *x, const float *y,
+                               int32_t n_d0, const float *d0, int32_t n_phi, const float *cos_phi,
+                               const float *sin_phi, int32_t n_kappa, float kappa_min, float kappa_scale,
+                               int32_t family, int32_t forward,
+                               int64_t n_cands, const int64_t *cand_votes, const int64_t *cand_cell,
+                               int64_t min_votes, int64_t cap, int64_t *out_cand, int64_t *out_hit)
+{
+    if (n_hits < 0 || n_d0 < 1 || n_phi < 1 || n_kappa < 1 || n_cands < 0 || cap < 0)
+        return -1;
+    if ((d0 == NULL && n_d0 != 1) || (family != 0 && family != 1) || (family == 1 && d0 != NULL))
+        return -1;
+    const int64_t cells = (int64_t)n_d0 * n_phi * n_kappa;
+    int64_t n_pairs = 0;
+    for (int64_t c = 0; c < n_cands; ++c) {
+        if (cand_votes[c] < min_votes)
+            continue;
+        const int64_t cell = cand_cell[c];
+        if (cell < 0 || cell >= cells)
+            return -1;
+        const int32_t lc = (int32_t)(cell / ((int64_t)n_phi * n_kappa));
+        const int32_t jc = (int32_t)((cell / n_kappa) % n_phi);
+        const int32_t kc = (int32_t)(cell % n_kappa);
+        for (int64_t h = 0; h < n_hits; ++h) {
+            const float hx = x[h];
+            const float hy = y[h];
+            const float hr2 = hx * hx + hy * hy;
+            int member = 0;
+            for (int dl = -1; dl <= 1 && !member; ++dl) {
+                const int32_t ll = lc + dl;
+                if (ll < 0 || ll >= n_d0)
+                    continue;
+                const float dl0 = d0 ? d0[ll] : 0.0f;
+                for (int dj = -1; dj <= 1 && !member; ++dj) {
+                    const int32_t jj = (jc + dj + n_phi) % n_phi;
+                    int32_t k;
+                    if (assoc_bin(hx, hy, hr2, family, forward, dl0, cos_phi[jj], sin_phi[jj],
+                                  kappa_min, kappa_scale, n_kappa, &k) && k >= kc - 1 && k <= kc + 1)
+                        member = 1;
+                }
+            }
+            if (!member)
+                continue;
+            if (n_pairs < cap) {
+                out_cand[n_pairs] = c;
+                out_hit[n_pairs] = h;
+            }
+            n_pairs += 1;
+        }
+    }
+    return n_pairs;
 }

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhough.so")
-SOURCES = ["vote.hip", "peaks.hip", "vertex.hip", "api.hip", "selftest.hip", "diag.hip", "tune.hip", "server.hip"]
+SOURCES = ["vote.hip", "peaks.hip", "vertex.hip", "assoc.hip", "api.hip", "selftest.hip", "diag.hip", "tune.hip", "server.hip"]
 ARCH = "gfx950"
 
 # -ffp-contract=off: the vote arithmetic is specified op by op (no FMA).

@@ -90,6 +90,7 @@ struct hough_ctx {
     float4 *hits = nullptr;       // [max_hits] hit records written by hit_prep
     uint2 *ranges = nullptr;      // [n_d0][max_hits] tile ranges per hit, when cull_ok
     uint2 *all_tiles = nullptr;   // one all-tiles entry: culling off
+    int32_t *cell_map = nullptr;  // [cells] hit association: 1 + candidate index per cell
 
     // batch descriptors
     size_t desc_bytes = 0;
@@ -130,7 +131,7 @@ void free_ctx(hough_ctx *c) {
     if (c->desc_host)
         (void)hipHostFree(c->desc_host);
     void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->hits, c->ranges, c->all_tiles,
-                   c->desc_dev, c->work_counter};
+                   c->desc_dev, c->work_counter, c->cell_map};
     for (void *p : dev)
         if (p)
             (void)hipFree(p);
@@ -538,6 +539,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     if (c->cull_ok)
         e = e ? e : dev_alloc(&c->ranges, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
     e = e ? e : dev_alloc(&c->all_tiles, 1);
+    e = e ? e : dev_alloc(&c->cell_map, static_cast<size_t>(g.cells));
     if (e == hipSuccess) {
         const uint2 all = make_uint2(kAllTiles, 0u);
         e = hipMemcpy(c->all_tiles, &all, sizeof(uint2), hipMemcpyHostToDevice);
@@ -670,6 +672,21 @@ hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int3
     HIP_TRY(launch_vertices(ctx->g, vg, n_events, reinterpret_cast<const Cand *>(cands), cand_off, n_found,
                             track_threshold, vertex_threshold, sorted_lists, reinterpret_cast<Cand *>(vout), vout_off,
                             n_vertices, vacc, static_cast<hipStream_t>(stream)));
+    return HOUGH_OK;
+}
+
+hough_status hough_associate(hough_ctx *ctx, const float *x, const float *y, int32_t n_hits,
+                             const hough_cand *cands, const int32_t *n_cands, int32_t cands_cap, int32_t min_votes,
+                             int32_t *pairs, int64_t cap, uint64_t *n_pairs, void *stream) {
+    if (!ctx || n_hits < 0 || cands_cap < 0 || cap < 0 || !n_cands || !n_pairs)
+        return HOUGH_EINVAL;
+    if ((n_hits > 0 && (!x || !y)) || (cands_cap > 0 && !cands) || (cap > 0 && !pairs))
+        return HOUGH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(n_pairs) & 7u)
+        return HOUGH_EINVAL;
+    HIP_TRY(launch_associate(ctx->g, x, y, n_hits, reinterpret_cast<const Cand *>(cands), n_cands, cands_cap,
+                             min_votes, ctx->cell_map, pairs, cap, reinterpret_cast<unsigned long long *>(n_pairs),
+                             static_cast<hipStream_t>(stream)));
     return HOUGH_OK;
 }
 

@@ -24,7 +24,7 @@ ACC_I32, ACC_U16 = 0, 1
 
 SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
-    "hough_vote_batch", "hough_vertices",
+    "hough_vote_batch", "hough_vertices", "hough_associate",
     "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
     "hough_autotune", "hough_tune_lookup",
     "hough_server_create", "hough_server_destroy", "hough_server_clock", "hough_server_submit",
@@ -133,6 +133,8 @@ def load(path: str = LIB_PATH):
     lib.hough_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.hough_diag_rates.restype = i32
     lib.hough_diag_rates.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.hough_associate.restype = i32
+    lib.hough_associate.argtypes = [vp, vp, vp, i32, vp, vp, i32, i32, vp, i64, vp, vp]
     lib.hough_vertices.restype = i32
     lib.hough_vertices.argtypes = [vp, ctypes.POINTER(_VertexGrid), i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp,
                                    vp]
@@ -327,6 +329,25 @@ class HoughContext:
                                        _stream_handle(stream)),
                "hough_vertices")
         return vout, voff, n_vertices, vacc
+
+    def associate(self, x, y, cands, n_cands, min_votes, cap=None, pairs=None, n_pairs=None, stream=None):
+        """Hit association of one event (hough_associate): the (candidate index, hit
+        index) pairs of candidates with at least min_votes votes.  cands [n, 2] int32
+        and n_cands [1] int32 on the device (hough_peaks' outputs).  Returns
+        (pairs [cap, 2] int32, n_pairs [1] int64); pairs are unordered.  cap (or
+        pairs) must be given: n_pairs reports the full count when it is too small."""
+        if cap is None:
+            if pairs is None:
+                raise ValueError("associate needs cap or a pairs buffer")
+            cap = pairs.shape[0]
+        if pairs is None:
+            pairs = torch.empty((max(int(cap), 1), 2), dtype=torch.int32, device=self.device)
+        if n_pairs is None:
+            n_pairs = torch.empty(1, dtype=torch.int64, device=self.device)
+        _check(self.lib.hough_associate(self.handle, _ptr(x), _ptr(y), int(x.numel()), _ptr(cands), _ptr(n_cands),
+                                        int(cands.shape[0]), int(min_votes), _ptr(pairs), int(cap), _ptr(n_pairs),
+                                        _stream_handle(stream)), "hough_associate")
+        return pairs, n_pairs
 
     def event_batch(self, hit_off, x, y, threshold, cand_off=None, cands=None, n_found=None,
                     n_votes=None, acc=None, want_votes=True, stream=None):

@@ -14,10 +14,12 @@ from .events import (
     track_hits, LAYERS_CM, BASE_SEED, pack_events, poisson_arrivals,
 )
 from .configs import CONFIGS, WorkloadConfig
+from .truth import match_candidates, efficiency
 
 __all__ = [
     "Grid", "make_grid", "make_straight_grid", "GRID_2D_SMALL", "GRID_2D", "GRID_3D", "GRID_STRAIGHT",
     "VertexGrid", "make_vertex_grid", "VERTEX_GRID",
     "Event", "Batch", "gen_config_event", "gen_batch", "gen_tracks_event",
     "track_hits", "LAYERS_CM", "BASE_SEED", "pack_events", "poisson_arrivals", "CONFIGS", "WorkloadConfig",
+    "match_candidates", "efficiency",
 ]

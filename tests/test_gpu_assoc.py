@@ -1,0 +1,133 @@
+"""GPU parity of the hit association (hough_associate) with the oracle's.
+
+The device writes each (candidate, hit) pair once, unordered; the sorted pair
+sets must equal the oracle's, which runs the same definition by brute force
+on the oracle's own candidate lists (no oracle input comes from the device).
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+hough = pytest.importorskip("paper_1311_2769_amd.hough")
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype)).to(_dev())
+
+
+def _find(x, y, grid, threshold):
+    if grid.family == "straight":
+        return oracle.find_straight(x, y, grid, threshold)
+    return oracle.find(x, y, grid, threshold)
+
+
+def _gpu_pairs(grid, x, y, votes, cells, min_votes, cap=None, n_cands=None):
+    ctx = hough.HoughContext(grid, device=_dev(), max_hits=max(len(x), 1))
+    cands = _t(np.stack([votes, cells], axis=1).reshape(-1, 2) if len(votes) else np.zeros((1, 2)), np.int32)
+    nc = _t([len(votes) if n_cands is None else n_cands], np.int32)
+    cap = cap if cap is not None else 1 << 22
+    pairs, n_pairs = ctx.associate(_t(x), _t(y), cands if len(votes) else cands[:0], nc, min_votes, cap=cap)
+    torch.cuda.synchronize()
+    n = int(n_pairs.item())
+    got = pairs[:min(n, cap)].cpu().numpy().astype(np.int64)
+    return n, got
+
+
+def _check(grid, x, y, threshold, min_votes, what, top=None):
+    _, _, v, c, n = _find(x, y, grid, threshold)
+    if top is not None:
+        v, c = v[:top], c[:top]
+    rc, rh = oracle.associate(x, y, grid, v, c, min_votes)
+    n_gpu, got = _gpu_pairs(grid, x, y, v, c, min_votes)
+    print(f"[assoc] {what}: {len(v)} candidates, {len(rc)} pairs", flush=True)
+    assert n_gpu == len(rc), what
+    order = np.lexsort((got[:, 1], got[:, 0]))
+    np.testing.assert_array_equal(got[order, 0], rc, err_msg=what)
+    np.testing.assert_array_equal(got[order, 1], rh, err_msg=what)
+    assert len(rc) > 0
+
+
+@pytest.mark.parametrize("forward", [False, True])
+def test_association_small_2d(forward):
+    wc = synth.CONFIGS[1]
+    ev = synth.gen_config_event(1)
+    grid = dataclasses.replace(wc.grid, forward=forward)
+    _check(grid, ev.x, ev.y, wc.threshold, wc.threshold, f"config 1 forward={forward}")
+
+
+def test_association_workload_2d_top_candidates():
+    wc = synth.CONFIGS[2]
+    ev = synth.gen_config_event(2)
+    _check(wc.grid, ev.x, ev.y, wc.threshold, 1, "config 2, 400 strongest candidates", top=400)
+
+
+def test_association_3d():
+    wc = synth.CONFIGS[3]
+    ev = synth.gen_config_event(3, 1)
+    sel = np.arange(0, ev.n_hits, 8)
+    _check(wc.grid, ev.x[sel], ev.y[sel], 3, 4, "config 3, every 8th hit", top=3000)
+
+
+def test_association_straight():
+    wc = synth.CONFIGS[6]
+    ev = synth.gen_config_event(6, 2)
+    sel = np.arange(0, ev.n_hits, 4)
+    _check(wc.grid, ev.x[sel], ev.y[sel], wc.threshold, wc.threshold, "straight, every 4th hit", top=2000)
+
+
+def test_association_truncation_and_empty_inputs():
+    wc = synth.CONFIGS[1]
+    ev = synth.gen_config_event(1)
+    _, _, v, c, n = oracle.find(ev.x, ev.y, wc.grid, wc.threshold)
+    rc, rh = oracle.associate(ev.x, ev.y, wc.grid, v, c, wc.threshold)
+    want = set(zip(rc.tolist(), rh.tolist()))
+    # a short pairs buffer: the full count, and distinct pairs of the full set
+    n_gpu, got = _gpu_pairs(wc.grid, ev.x, ev.y, v, c, wc.threshold, cap=100)
+    assert n_gpu == len(rc) and got.shape[0] == 100
+    pairs = set(map(tuple, got.tolist()))
+    assert len(pairs) == 100 and pairs <= want
+    # only the first n_cands candidates take part
+    n_gpu, got = _gpu_pairs(wc.grid, ev.x, ev.y, v, c, wc.threshold, n_cands=5)
+    rc5, rh5 = oracle.associate(ev.x, ev.y, wc.grid, v[:5], c[:5], wc.threshold)
+    assert n_gpu == len(rc5) and set(map(tuple, got.tolist())) == set(zip(rc5.tolist(), rh5.tolist()))
+    # no hits, no candidates, a threshold above every candidate
+    assert _gpu_pairs(wc.grid, ev.x[:0], ev.y[:0], v, c, 1)[0] == 0
+    assert _gpu_pairs(wc.grid, ev.x, ev.y, v[:0], c[:0], 1)[0] == 0
+    assert _gpu_pairs(wc.grid, ev.x, ev.y, v, c, int(v.max()) + 1)[0] == 0
+
+
+def test_association_on_device_candidates_gives_the_truth_report():
+    """The device's own candidate list (equal to the oracle's) feeds the association;
+    the efficiency report from the device pairs equals the oracle's."""
+    dev = _dev()
+    wc = synth.CONFIGS[1]
+    ev = synth.gen_config_event(1)
+    ctx = hough.HoughContext(wc.grid, device=dev, max_hits=ev.n_hits)
+    x, y = _t(ev.x), _t(ev.y)
+    acc, _ = ctx.vote(x, y)
+    out, nf = ctx.peaks(acc, wc.threshold)
+    pairs, n_pairs = ctx.associate(x, y, out, nf, wc.threshold, cap=1 << 16)
+    torch.cuda.synchronize()
+    n = int(n_pairs.item())
+    got = pairs[:n].cpu().numpy().astype(np.int64)
+    v, c, nfound = hough.cands_to_numpy(out, nf.item())
+    m, nh = synth.match_candidates(got[:, 0], got[:, 1], nfound, ev.label, wc.threshold)
+    _, _, rv, rcl, rn = oracle.find(ev.x, ev.y, wc.grid, wc.threshold)
+    rc, rh = oracle.associate(ev.x, ev.y, wc.grid, rv, rcl, wc.threshold)
+    rm, rnh = synth.match_candidates(rc, rh, rn, ev.label, wc.threshold)
+    np.testing.assert_array_equal(m, rm)
+    assert synth.efficiency(m, nh, ev.label, wc.threshold) == synth.efficiency(rm, rnh, ev.label, wc.threshold)

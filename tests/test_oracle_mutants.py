@@ -67,6 +67,15 @@ MUTANTS = {
     "straight_forward_backward": ("if (!(fwd > 0.0f))", "if (!(fwd < 0.0f))"),
     "straight_forward_operands": ("float fwd = xh * cos_phi[j] + yh * sin_phi[j];",
                                   "float fwd = yh * cos_phi[j] + xh * sin_phi[j];"),
+    "assoc_kappa_window_one_sided": ("k >= kc - 1 && k <= kc + 1", "k >= kc && k <= kc + 1"),
+    "assoc_phi_not_periodic": ("const int32_t jj = (jc + dj + n_phi) % n_phi;",
+                               "const int32_t jj = jc + dj < 0 || jc + dj >= n_phi ? jc : jc + dj;"),
+    "assoc_d0_window_dropped": ("for (int dl = -1; dl <= 1 && !member; ++dl) {",
+                                "for (int dl = 0; dl <= 0 && !member; ++dl) {"),
+    "assoc_forward_ignored": ("        if (!(front > 0.0f))\n            return 0;\n", ""),
+    "assoc_straight_uses_curvature": ("if (family == 1) {", "if (family == 2) {"),
+    "assoc_chord_sign": ("float chord2 = hr2 - 2.0f * dl0 * off + dl0 * dl0;",
+                         "float chord2 = hr2 + 2.0f * dl0 * off + dl0 * dl0;"),
 }
 
 RUNNER = r"""

@@ -708,3 +708,88 @@ def test_forward_option_straight_lines():
             continue
         acc, n = vote_straight(ev.x[i:i + 1], ev.y[i:i + 1], wide)
         np.testing.assert_array_equal(acc[0].sum(axis=1), (ahead > 0).astype(np.int64))
+
+
+# --------------------------------------------------------------------------------------
+# Hit association: the hits that vote inside a candidate's peak window
+# --------------------------------------------------------------------------------------
+
+def associate(x, y, grid, votes, cells, min_votes):
+    return oracle.associate(x, y, grid, votes, cells, min_votes, library=LIBRARY[0])
+
+
+def _window_members(grid, acc1, cell):
+    """Does a single hit's accumulator acc1 (n_d0, n_phi, n_kappa) hold a vote in the
+    3x3(x3) window of cell (phi periodic, d0 and kappa clipped)?"""
+    l, j, k = cell // (grid.n_phi * grid.n_kappa), (cell // grid.n_kappa) % grid.n_phi, cell % grid.n_kappa
+    rows = [(j + d) % grid.n_phi for d in (-1, 0, 1)]
+    sl = acc1[max(l - 1, 0):l + 2][:, rows][:, :, max(k - 1, 0):k + 2]
+    return sl.sum() > 0
+
+
+@pytest.mark.parametrize("which", ["2d", "3d", "straight", "forward"])
+def test_association_is_the_single_hit_votes_in_the_window(which):
+    """A hit belongs to a candidate exactly when its own vote (the vote routine run on that
+    hit alone) lands in the candidate's 3x3(x3) window -- checked pair by pair against
+    window sums of single-hit accumulators."""
+    if which == "3d":
+        grid = make_grid(64, 32, n_d0=5, d0_range=(-10.0, 10.0))
+        ev = synth.gen_config_event(3, 2)
+        sel = np.arange(0, ev.n_hits, 200)
+    elif which == "straight":
+        grid = synth.make_straight_grid(64, 48, (-12.0, 12.0))
+        ev = synth.gen_config_event(6, 0)
+        sel = np.arange(0, ev.n_hits, 120)
+    else:
+        grid = synth.GRID_2D_SMALL if which == "2d" else _forward(synth.GRID_2D_SMALL)
+        ev = synth.gen_config_event(1)
+        sel = np.arange(ev.n_hits)
+    x, y = ev.x[sel], ev.y[sel]
+    one = vote_straight if grid.family == "straight" else vote
+    acc, _ = one(x, y, grid)
+    votes_all, cells_all, n = peaks(acc, 2)
+    votes_all, cells_all = votes_all[:60], cells_all[:60]
+    pc, ph = associate(x, y, grid, votes_all, cells_all, 3)
+    got = set(zip(pc.tolist(), ph.tolist()))
+    singles = [one(x[i:i + 1], y[i:i + 1], grid)[0] for i in range(len(x))]
+    want = set()
+    for c, (v, cell) in enumerate(zip(votes_all, cells_all)):
+        if v < 3:
+            continue
+        for h, a1 in enumerate(singles):
+            if _window_members(grid, a1, int(cell)):
+                want.add((c, h))
+    assert len(want) > 0
+    assert got == want
+    # candidate order, hits ascending within a candidate
+    assert list(zip(pc.tolist(), ph.tolist())) == sorted(got)
+
+
+def test_association_of_a_clean_track_is_its_hits():
+    """A noise-free bin-centre track: its peak candidate (and, without the forward option,
+    its mirror) holds exactly the track's hits; with the forward option the mirror is gone."""
+    grid = synth.GRID_2D
+    d0, phi0, kappa = _bin_centre_track(grid, 0, 300, 200)
+    ev = synth.gen_tracks_event([d0], [phi0], [kappa])
+    cell = 300 * grid.n_kappa + 200
+    mirror = ((300 + grid.n_phi // 2) % grid.n_phi) * grid.n_kappa + grid.n_kappa - 1 - 200
+    pc, ph = associate(ev.x, ev.y, grid, [ev.n_hits, ev.n_hits], [cell, mirror], 1)
+    assert ph[pc == 0].tolist() == list(range(ev.n_hits))
+    assert ph[pc == 1].tolist() == list(range(ev.n_hits))
+    pc, ph = associate(ev.x, ev.y, _forward(grid), [ev.n_hits, ev.n_hits], [cell, mirror], 1)
+    assert ph[pc == 0].tolist() == list(range(ev.n_hits)) and (pc == 1).sum() == 0
+
+
+def test_association_threshold_and_empty_lists():
+    ev = synth.gen_config_event(1)
+    grid = synth.GRID_2D_SMALL
+    acc, _ = vote(ev.x, ev.y, grid)
+    v, c, n = peaks(acc, 5)
+    pc, ph = associate(ev.x, ev.y, grid, v, c, int(v.max()) + 1)
+    assert pc.size == 0
+    pc, ph = associate(ev.x, ev.y, grid, v, c, int(v.max()))
+    assert set(pc.tolist()) == set(np.nonzero(v == v.max())[0].tolist())
+    pc, ph = associate(ev.x[:0], ev.y[:0], grid, v, c, 1)
+    assert pc.size == 0
+    pc, ph = associate(ev.x, ev.y, grid, v[:0], c[:0], 1)
+    assert pc.size == 0
