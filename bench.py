@@ -57,6 +57,7 @@ def parse_args():
     ap.add_argument("--skip-3d", action="store_true", help="skip the displaced-vertex (3D) batch leg")
     ap.add_argument("--skip-straight", action="store_true", help="skip the straight-line batch leg")
     ap.add_argument("--skip-forward", action="store_true", help="skip the forward-hemisphere batch leg")
+    ap.add_argument("--skip-assoc", action="store_true", help="skip the hit-association / truth report leg")
     ap.add_argument("--serve-rates", default="1000,5000,20000",
                     help="offered rates (events/s) of the served stream; empty to skip")
     ap.add_argument("--serve-events", type=int, default=20000, help="measured arrivals per rate")
@@ -338,6 +339,50 @@ def forward_2d(hough, torch, dev, synth, batch, x, y, log_fn, reps=10):
             "votes_per_step": int(n_votes.sum().item()), "candidates_per_step": int(n_found.sum().item())}
 
 
+def association_report(hough, torch, dev, synth, log_fn, reps=5):
+    """Hit association of one event per workload on the device (every candidate
+    at or above the threshold), timed with HIP events on the stream it runs on,
+    and the truth report of its pairs: efficiency, fake rate and duplicates
+    (matched candidates per found track) with the threshold as the match
+    minimum.  A physics check of the workloads, not a parity figure."""
+    import dataclasses
+    out = []
+    for name, cfg, forward in (("config1_40trk_256x128", 1, False), ("config2_pileup_1024x512", 2, False),
+                               ("config2_pileup_1024x512_forward", 2, True), ("config3_displaced_3d", 3, False)):
+        wc = synth.CONFIGS[cfg]
+        grid = dataclasses.replace(wc.grid, forward=forward)
+        ev = synth.gen_config_event(cfg)
+        log_fn(f"association: {name}")
+        ctx = hough.HoughContext(grid, device=dev, max_hits=ev.n_hits)
+        x = torch.from_numpy(ev.x).to(dev)
+        y = torch.from_numpy(ev.y).to(dev)
+        acc, _ = ctx.vote(x, y)
+        cands, nf = ctx.peaks(acc, wc.threshold)
+        cap = 1 << 27                    # 1 GiB of pairs: the displaced event has about 108 M
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        n_pairs = torch.empty(1, dtype=torch.int64, device=dev)
+        ctx.associate(x, y, cands, nf, wc.threshold, pairs=pairs, n_pairs=n_pairs)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            ctx.associate(x, y, cands, nf, wc.threshold, pairs=pairs, n_pairs=n_pairs)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        n = int(n_pairs.item())
+        if n > cap:
+            raise RuntimeError(f"association of {name}: {n} pairs exceed the buffer")
+        got = pairs[:n].cpu().numpy().astype(np.int64)
+        n_cands = int(nf.item())
+        match, n_hits = synth.match_candidates(got[:, 0], got[:, 1], n_cands, ev.label, wc.threshold)
+        rep = synth.efficiency(match, n_hits, ev.label, wc.threshold)
+        out.append({"workload": name, "hits": ev.n_hits, "candidates": n_cands, "pairs": n,
+                    "ms": t0.elapsed_time(t1) / reps, **rep})
+        del pairs
+    return out
+
+
 def served_stream(args, hough, synth, batch, log_fn):
     """Open-loop served stream: Poisson arrivals of 80 % batch-workload 2D and
     20 % displaced 3D events at each offered rate, through the library's
@@ -511,6 +556,8 @@ def main():
         line_extra["straight_2d"] = straight_2d(hough, torch, dev, synth, log)
     if not args.skip_forward:
         line_extra["forward_2d"] = forward_2d(hough, torch, dev, synth, batch, x, y, log)
+    if not args.skip_assoc:
+        line_extra["association"] = association_report(hough, torch, dev, synth, log)
     served = served_stream(args, hough, synth, batch, log)
     if served is not None:
         line_extra["served"] = served

@@ -91,6 +91,7 @@ struct hough_ctx {
     uint2 *ranges = nullptr;      // [n_d0][max_hits] tile ranges per hit, when cull_ok
     uint2 *all_tiles = nullptr;   // one all-tiles entry: culling off
     int32_t *cell_map = nullptr;  // [cells] hit association: 1 + candidate index per cell
+    uint32_t *cell_bits = nullptr;  // hit association: bitmap of the cells that hold a candidate
 
     // batch descriptors
     size_t desc_bytes = 0;
@@ -131,7 +132,7 @@ void free_ctx(hough_ctx *c) {
     if (c->desc_host)
         (void)hipHostFree(c->desc_host);
     void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->hits, c->ranges, c->all_tiles,
-                   c->desc_dev, c->work_counter, c->cell_map};
+                   c->desc_dev, c->work_counter, c->cell_map, c->cell_bits};
     for (void *p : dev)
         if (p)
             (void)hipFree(p);
@@ -540,6 +541,8 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         e = e ? e : dev_alloc(&c->ranges, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
     e = e ? e : dev_alloc(&c->all_tiles, 1);
     e = e ? e : dev_alloc(&c->cell_map, static_cast<size_t>(g.cells));
+    e = e ? e : dev_alloc(&c->cell_bits, static_cast<size_t>(g.n_d0) * static_cast<size_t>(g.n_phi) *
+                                             static_cast<size_t>(assoc_row_words(g.n_kappa)));
     if (e == hipSuccess) {
         const uint2 all = make_uint2(kAllTiles, 0u);
         e = hipMemcpy(c->all_tiles, &all, sizeof(uint2), hipMemcpyHostToDevice);
@@ -685,7 +688,8 @@ hough_status hough_associate(hough_ctx *ctx, const float *x, const float *y, int
     if (reinterpret_cast<uintptr_t>(n_pairs) & 7u)
         return HOUGH_EINVAL;
     HIP_TRY(launch_associate(ctx->g, x, y, n_hits, reinterpret_cast<const Cand *>(cands), n_cands, cands_cap,
-                             min_votes, ctx->cell_map, pairs, cap, reinterpret_cast<unsigned long long *>(n_pairs),
+                             min_votes, ctx->cell_map, ctx->cell_bits, pairs, cap,
+                             reinterpret_cast<unsigned long long *>(n_pairs),
                              static_cast<hipStream_t>(stream)));
     return HOUGH_OK;
 }

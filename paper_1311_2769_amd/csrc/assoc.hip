@@ -10,13 +10,18 @@
 // range test the compare form), with the grid's family and forward option.
 //
 // Layout: the context's cell map holds, per cell, 1 + the index of the
-// candidate there (0: none).  One thread takes one (hit, d0 slice) and a run
-// of kAssocRows phi0 rows; for every vote it looks up the candidates in the
-// vote's window.  A pair is written once, by the first position of C's
-// window (dl, then dj, in increasing order) at which the hit's bin is within
-// one of kc: a thread that finds a match recomputes the hit's bins at the
-// earlier positions of that window.  Pairs go out through one atomic
-// reservation per wavefront.
+// candidate there (0: none), and a bitmap of the cells that hold one: per
+// (d0, phi0) row, bit kc + 1 of kAssocRowWords(n_kappa) dwords (about 1 MB for
+// the displaced grid, so it stays in L2).  One thread takes one (hit, d0
+// slice) and a run of kAssocRows phi0 rows; for every vote (l, j, k) it reads
+// the three bits k-1..k+1 of each window row (l - el, j - ej) from two dwords
+// of the bitmap and goes to the map only for a set bit.  A pair is written
+// once, by the first position of C's window (dl, then dj, in increasing
+// order) at which the hit's bin is within one of kc: a thread that finds a
+// match recomputes the hit's bins at the earlier positions of that window.
+// Each wavefront gathers its pairs in an LDS buffer and reserves room in the
+// output with one atomic per kAssocFlush pairs (a single counter taken per
+// pair by every wavefront serialised the displaced event's 10^8 pairs).
 #pragma clang fp contract(off)
 
 #include "hough_impl.h"
@@ -26,6 +31,19 @@ namespace {
 
 constexpr int kAssocRows = 64;      // phi0 rows per thread
 constexpr int kAssocThreads = 256;
+constexpr int kAssocWaves = kAssocThreads / 64;
+constexpr int kAssocBuf = 512;      // pairs staged per wavefront
+constexpr int kAssocFlush = kAssocBuf - 64;
+
+}  // namespace
+
+// Bitmap dwords per (d0, phi0) row: bits 0 .. n_kappa + 1, plus one dword so
+// that the pair of dwords holding bits k .. k + 2 never leaves the row.
+int64_t assoc_row_words(int32_t n_kappa) {
+    return (static_cast<int64_t>(n_kappa) + 2 + 31) / 32 + 1;
+}
+
+namespace {
 
 struct AssocArgs {
     GridArgs g;
@@ -33,6 +51,8 @@ struct AssocArgs {
     int32_t n_hits;
     int32_t rows_chunks;           // ceil(n_phi / kAssocRows)
     const int32_t *map;            // [cells] 1 + candidate index, 0: none
+    const uint32_t *bits;          // [n_d0 * n_phi][row_words] bit kc + 1: a candidate at kc
+    int32_t row_words;
     int32_t *pairs;                // [cap][2] (candidate, hit)
     int64_t cap;
     unsigned long long *n_pairs;
@@ -62,20 +82,46 @@ __device__ __forceinline__ int hit_bin(const GridArgs &g, float hx, float hy, fl
 }
 
 __global__ __launch_bounds__(kAssocThreads) void map_kernel(const Cand *cands, const int32_t *n_found, int32_t cap,
-                                                            int32_t min_votes, int64_t cells, int32_t *map) {
+                                                            int32_t min_votes, int64_t cells, int32_t n_kappa,
+                                                            int32_t row_words, int32_t *map, uint32_t *bits) {
     const int32_t n = min(*n_found, cap);
     for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
         const Cand cd = cands[c];
-        if (cd.votes >= min_votes && cd.cell >= 0 && cd.cell < cells)
+        if (cd.votes >= min_votes && cd.cell >= 0 && cd.cell < cells) {
             map[cd.cell] = c + 1;
+            const int64_t row = cd.cell / n_kappa;
+            const int b = cd.cell - static_cast<int32_t>(row * n_kappa) + 1;
+            atomicOr(&bits[row * row_words + (b >> 5)], 1u << (b & 31));
+        }
     }
 }
 
 __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
+    __shared__ int2 staged[kAssocWaves][kAssocBuf];
     const GridArgs &g = a.g;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per_hit = static_cast<int64_t>(g.n_d0) * a.rows_chunks;
     const int lane = threadIdx.x & 63;
+    int2 *buf = staged[threadIdx.x >> 6];
+    int fill = 0;                      // wave-uniform
+    // move the staged pairs to the output: one reservation for all of them
+    auto flush = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        unsigned long long base = 0;
+        if (lane == 0)
+            base = atomicAdd(a.n_pairs, static_cast<unsigned long long>(fill));
+        base = __shfl(base, 0);
+        for (int i = lane; i < fill; i += 64) {
+            const int64_t slot = static_cast<int64_t>(base) + i;
+            if (slot < a.cap) {
+                const int2 p = buf[i];
+                a.pairs[2 * slot] = p.x;
+                a.pairs[2 * slot + 1] = p.y;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        fill = 0;
+    };
     const bool live = t < per_hit * a.n_hits;
     const int h = live ? static_cast<int>(t / per_hit) : 0;
     const int rest = live ? static_cast<int>(t - static_cast<int64_t>(h) * per_hit) : 0;
@@ -100,66 +146,70 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
         // candidates in the window of the vote (l, j, k): C = (l - el, j - ej, k - ek)
         for (int el = el_lo; el <= el_hi; ++el) {
             for (int ej = -1; ej <= 1; ++ej) {
-                for (int ek = -1; ek <= 1; ++ek) {
-                    const int lc = l - el;
-                    int jc = j - ej;
-                    jc += jc < 0 ? np : 0;
-                    jc -= jc >= np ? np : 0;
-                    const int kc = k - ek;
+                const int lc = l - el;
+                int jc = j - ej;
+                jc += jc < 0 ? np : 0;
+                jc -= jc >= np ? np : 0;
+                // bits kc + 1 for kc = k - 1 .. k + 1 of row (lc, jc)
+                uint32_t pend = 0u;
+                if (k >= 0 && lc >= 0 && lc < g.n_d0) {
+                    const uint32_t *w = a.bits + (static_cast<int64_t>(lc) * np + jc) * a.row_words + (k >> 5);
+                    const uint64_t two = static_cast<uint64_t>(w[0]) | (static_cast<uint64_t>(w[1]) << 32);
+                    pend = static_cast<uint32_t>(two >> (k & 31)) & 7u;
+                }
+                while (__ballot(pend != 0u)) {
                     bool emit = false;
                     int cand = 0;
-                    if (k >= 0 && lc >= 0 && lc < g.n_d0 && kc >= 0 && kc < nk) {
+                    if (pend != 0u) {
+                        const int bit = __ffs(pend) - 1;        // kc = k - 1 + bit
+                        pend &= pend - 1u;
+                        const int kc = k - 1 + bit;
                         cand = a.map[lc * plane + static_cast<int64_t>(jc) * nk + kc] - 1;
-                        if (cand >= 0) {
-                            // the position (el, ej) of this vote in C's window; emit only when
-                            // no earlier position of the window has the hit within one of kc
-                            emit = true;
-                            for (int dl = -1; dl <= el && emit; ++dl) {
-                                const int ll = lc + dl;
-                                if (ll < 0 || ll >= g.n_d0)
-                                    continue;
-                                for (int dj = -1; dj <= 1; ++dj) {
-                                    if (dl == el && dj >= ej)
-                                        break;
-                                    int jj = jc + dj;
-                                    jj += jj < 0 ? np : 0;
-                                    jj -= jj >= np ? np : 0;
-                                    const int kk = hit_bin(g, hx, hy, hr2, ll, jj);
-                                    if (kk >= 0 && kk >= kc - 1 && kk <= kc + 1) {
-                                        emit = false;
-                                        break;
-                                    }
+                        // the position (el, ej) of this vote in C's window; emit only when
+                        // no earlier position of the window has the hit within one of kc
+                        emit = cand >= 0;
+                        for (int dl = -1; dl <= el && emit; ++dl) {
+                            const int ll = lc + dl;
+                            if (ll < 0 || ll >= g.n_d0)
+                                continue;
+                            for (int dj = -1; dj <= 1; ++dj) {
+                                if (dl == el && dj >= ej)
+                                    break;
+                                int jj = jc + dj;
+                                jj += jj < 0 ? np : 0;
+                                jj -= jj >= np ? np : 0;
+                                const int kk = hit_bin(g, hx, hy, hr2, ll, jj);
+                                if (kk >= 0 && kk >= kc - 1 && kk <= kc + 1) {
+                                    emit = false;
+                                    break;
                                 }
                             }
                         }
                     }
                     const uint64_t m = __ballot(emit);
-                    if (m) {
-                        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-                        unsigned long long base = 0;
-                        if (lane == leader)
-                            base = atomicAdd(a.n_pairs, static_cast<unsigned long long>(__popcll(m)));
-                        base = __shfl(base, leader);
-                        if (emit) {
-                            const int64_t slot = static_cast<int64_t>(base) + __popcll(m & ((1ull << lane) - 1ull));
-                            if (slot < a.cap) {
-                                a.pairs[2 * slot] = cand;
-                                a.pairs[2 * slot + 1] = h;
-                            }
-                        }
-                    }
+                    if (emit)
+                        buf[fill + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cand, h);
+                    fill += __popcll(m);
+                    if (fill > kAssocFlush)
+                        flush();
                 }
             }
         }
     }
+    if (fill > 0)
+        flush();
 }
 
 }  // namespace
 
 hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, int32_t n_hits, const Cand *cands,
-                            const int32_t *n_found, int32_t cands_cap, int32_t min_votes, int32_t *map,
+                            const int32_t *n_found, int32_t cands_cap, int32_t min_votes, int32_t *map, uint32_t *bits,
                             int32_t *pairs, int64_t cap, unsigned long long *n_pairs, hipStream_t stream) {
+    const int64_t row_words = assoc_row_words(g.n_kappa);
     hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(map), g.cells, stream);
+    if (e != hipSuccess)
+        return e;
+    e = launch_zero(bits, static_cast<int64_t>(g.n_d0) * g.n_phi * row_words, stream);
     if (e != hipSuccess)
         return e;
     e = launch_zero(reinterpret_cast<uint32_t *>(n_pairs), 2, stream);
@@ -169,7 +219,7 @@ hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, i
         const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((cands_cap + kAssocThreads - 1) / kAssocThreads,
                                                                          4096));
         hipLaunchKernelGGL(map_kernel, dim3(blocks), dim3(kAssocThreads), 0, stream, cands, n_found, cands_cap,
-                           min_votes, g.cells, map);
+                           min_votes, g.cells, g.n_kappa, static_cast<int32_t>(row_words), map, bits);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -183,6 +233,8 @@ hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, i
     a.n_hits = n_hits;
     a.rows_chunks = (g.n_phi + kAssocRows - 1) / kAssocRows;
     a.map = map;
+    a.bits = bits;
+    a.row_words = static_cast<int32_t>(row_words);
     a.pairs = pairs;
     a.cap = cap;
     a.n_pairs = n_pairs;
