@@ -5,6 +5,7 @@ bit-exact, at every launch shape, for single events and for batches.
 """
 
 import ctypes
+import dataclasses
 import math
 
 import numpy as np
@@ -589,3 +590,30 @@ def test_autotuner_picks_a_shape_records_it_and_changes_no_result(tmp_path):
     fresh = hough.HoughContext(g, max_events=6, max_hits=b.n_hits, tune_cache=cache)
     assert fresh.get_launch(1) == (rows, threads, 1)
     assert fresh.get_launch(0) == (r0, t0, s0)
+
+
+def test_sort_passes_follow_the_largest_event():
+    """The sort runs one pass per 8-bit digit that the batch's vote counts can reach
+    (bounded by its largest event).  A batch with a 70,000-hit event whose cells pass
+    2^16 votes needs the third pass; a small batch on the same context needs one, and
+    the two alternate through the context's cached graphs."""
+    g = synth.GRID_2D_SMALL
+    big = synth.gen_config_event(1)
+    # 70,000 copies of one hit: every cell of its curve gets 70,000 votes
+    hx = np.concatenate([np.full(70000, big.x[0], np.float32), big.x])
+    hy = np.concatenate([np.full(70000, big.y[0], np.float32), big.y])
+    ev_big = dataclasses.replace(big, x=hx, y=hy, label=np.zeros(hx.size, np.int32))
+    small = [synth.gen_config_event(1, i) for i in (1, 2)]
+    b_big = synth.pack_events([ev_big, small[0]])
+    b_small = synth.pack_events(small)
+    ctx = hough.HoughContext(g, max_events=2, max_hits=b_big.n_hits)
+    for b in (b_big, b_small, b_big, b_small):
+        res = _batch_results(ctx, b, 7)
+        for e, ev in enumerate(b.events):
+            _, rnv, rv, rc, rn = oracle.find(ev.x, ev.y, g, 7)
+            nv, nf, v, c = res[e]
+            print(f"[parity] sort passes: event of {ev.n_hits} hits, {rn} candidates, top {rv[:1]}", flush=True)
+            assert (nv, nf) == (rnv, rn)
+            np.testing.assert_array_equal(v, rv[:len(v)])
+            np.testing.assert_array_equal(c, rc[:len(c)])
+    assert oracle.find(ev_big.x, ev_big.y, g, 7)[2][0] > 65535
