@@ -13,6 +13,7 @@
 
 #include "hough.h"
 #include "hough_impl.h"
+#include "assoc.h"
 
 using namespace hough;
 

@@ -24,7 +24,7 @@
 // pair by every wavefront serialised the displaced event's 10^8 pairs).
 #pragma clang fp contract(off)
 
-#include "hough_impl.h"
+#include "assoc.h"
 
 namespace hough {
 namespace {

@@ -198,14 +198,6 @@ constexpr int32_t kVtxMaxCells = 16384;
 constexpr int32_t kVtxMaxPeaks = 4096;
 int32_t vertex_sort_size(int32_t n_x, int32_t n_y);
 bool vertex_grid_supported(int32_t n_x, int32_t n_y);   // the limits above and the workgroup's LDS
-// Hit association of one event (assoc.hip): map is the context's [cells]
-// int32 cell map, bits its [n_d0 * n_phi * assoc_row_words(n_kappa)] candidate
-// bitmap, n_pairs an 8-byte counter; all are cleared here.
-int64_t assoc_row_words(int32_t n_kappa);
-hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, int32_t n_hits, const Cand *cands,
-                            const int32_t *n_found, int32_t cands_cap, int32_t min_votes, int32_t *map, uint32_t *bits,
-                            int32_t *pairs, int64_t cap, unsigned long long *n_pairs, hipStream_t stream);
-
 hipError_t launch_vertices(const GridArgs &g, const hough_vertex_grid &vg, int32_t n_events, const Cand *cands,
                            const int64_t *cand_off, const int32_t *n_found, int32_t track_threshold,
                            int32_t vertex_threshold, int32_t sorted, Cand *vout, const int64_t *vout_off,

@@ -469,11 +469,22 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(SortWork w, int pass
     }
 }
 
-// Stable scatter of one chunk by the digit of this pass.
+// Stable scatter of one chunk by the digit of this pass.  A round takes up to
+// 2,048 consecutive elements, split into one run per wavefront (a
+// multiple of 64, at most 64 * kSortPer, shorter when the list is short so
+// that every wavefront has a share), lane by lane in sub-blocks of 64, all
+// loads issued first.  Each wavefront
+// ranks its elements within their digit on its own (a running count per digit
+// in LDS, updated by the first lane of each digit of a sub-block); one
+// barrier, a prefix over wavefronts per digit, a second barrier, and every
+// element goes to run[digit] + its wavefront's prefix + its rank.
+constexpr int kSortPer = 8;
+
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int pass) {
     constexpr int kWaves = kSortThreads / 64;
     __shared__ uint32_t run[kDigits];
     __shared__ uint32_t wcnt[kWaves][kDigits];
+    __shared__ uint32_t wpre[kWaves][kDigits];
     const int e = blockIdx.y;
     const int c = blockIdx.x;
     if (w.n_events_dev && e >= *w.n_events_dev)
@@ -498,6 +509,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int p
     }
     const int t = threadIdx.x;
     const int wave = t >> 6;
+    const int lane = t & 63;
     const uint32_t *hrow = w.hist + (static_cast<int64_t>(e) * w.hist_chunks + c) * kDigits;
     for (int i = t; i < kDigits; i += kSortThreads)
         run[i] = hrow[i];
@@ -524,45 +536,65 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int p
             count = min(kSortChunk, st.n_found - begin);
             src = buf + static_cast<int64_t>(e) * w.bound + begin;
         }
-        for (int b0 = 0; b0 < count; b0 += kSortThreads) {
-            for (int i = t; i < kWaves * kDigits; i += kSortThreads)
-                (&wcnt[0][0])[i] = 0u;
-            lds_barrier();
-            const int i = b0 + t;
-            const bool valid = i < count;
-            Cand cd{0, 0};
-            uint32_t digit = 0;
-            if (valid) {
-                cd = src[i];
-                digit = (sort_key(cd.votes) >> shift) & 0xffu;
-            }
-            uint64_t peers = __ballot(valid);
+        for (int b0 = 0; b0 < count;) {
+            const int rem = count - b0;
+            const int seg = min(64 * kSortPer, ((rem + kWaves - 1) / kWaves + 63) & ~63);
+            const int subs = seg >> 6;
+            // this wavefront's elements of the round, loaded at once
+            const int base = b0 + wave * seg + lane;
+            Cand cd[kSortPer];
 #pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
-                const bool set = (digit >> bit) & 1u;
-                const uint64_t bb = __ballot(set);
-                peers &= set ? bb : ~bb;
+            for (int k = 0; k < kSortPer; ++k) {
+                const int i = base + 64 * k;
+                cd[k] = (k < subs && i < count) ? src[i] : Cand{0, 0};
             }
-            const int rank = rank_below(peers);
-            if (valid && rank == 0)
-                wcnt[wave][digit] = static_cast<uint32_t>(__popcll(peers));
-            lds_barrier();
-            if (valid) {
-                uint32_t pre = run[digit];
-                for (int w2 = 0; w2 < wave; ++w2)
-                    pre += wcnt[w2][digit];
-                const int64_t pos = static_cast<int64_t>(pre) + rank;
-                if (pos < limit)
-                    dst[pos] = cd;
+            for (int d = lane; d < kDigits; d += 64)
+                wcnt[wave][d] = 0u;
+            __builtin_amdgcn_wave_barrier();
+            uint32_t digit[kSortPer] = {};
+            uint32_t rank[kSortPer] = {};
+#pragma unroll
+            for (int k = 0; k < kSortPer; ++k) {
+                if (k >= subs)
+                    break;                      // wave-uniform: short runs stop early
+                const bool valid = base + 64 * k < count;
+                digit[k] = valid ? (sort_key(cd[k].votes) >> shift) & 0xffu : 0u;
+                uint64_t peers = __ballot(valid);
+#pragma unroll
+                for (int bit = 0; bit < 8; ++bit) {
+                    const bool set = (digit[k] >> bit) & 1u;
+                    const uint64_t bb = __ballot(set);
+                    peers &= set ? bb : ~bb;
+                }
+                const int r = rank_below(peers);
+                const uint32_t before = valid ? wcnt[wave][digit[k]] : 0u;
+                __builtin_amdgcn_wave_barrier();
+                if (valid && r == 0)
+                    wcnt[wave][digit[k]] = before + static_cast<uint32_t>(__popcll(peers));
+                __builtin_amdgcn_wave_barrier();
+                rank[k] = valid ? before + static_cast<uint32_t>(r) : 0u;
             }
             lds_barrier();
-            for (int dd = t; dd < kDigits; dd += kSortThreads) {
-                uint32_t add = 0;
-                for (int w2 = 0; w2 < kWaves; ++w2)
-                    add += wcnt[w2][dd];
-                run[dd] += add;
+            // per digit: the prefix over wavefronts on top of run, and the new run
+            for (int d = t; d < kDigits; d += kSortThreads) {
+                uint32_t acc = run[d];
+#pragma unroll
+                for (int w2 = 0; w2 < kWaves; ++w2) {
+                    wpre[w2][d] = acc;
+                    acc += wcnt[w2][d];
+                }
+                run[d] = acc;
             }
             lds_barrier();
+#pragma unroll
+            for (int k = 0; k < kSortPer; ++k) {
+                if (k < subs && base + 64 * k < count) {
+                    const int64_t pos = static_cast<int64_t>(wpre[wave][digit[k]]) + rank[k];
+                    if (pos < limit)
+                        dst[pos] = cd[k];
+                }
+            }
+            b0 += kWaves * seg;
         }
     }
 }
