@@ -270,8 +270,13 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // falls in the band above an integer take the exact kf.  num: the
     // quotient's numerator (u in 2D), kept for the redo.
     const float near_band = g.near_band;
-    const float kf_off = g.kf_off;
+    float kf_off = g.kf_off;
     const float kscale2 = g.kscale2;
+    if constexpr (D3) {
+        // the 3D FMA already takes kscale2 from a scalar register: keep the
+        // offset in a vector one, or the compiler moves it there per hit pair
+        asm volatile("v_mov_b32 %0, %1" : "=v"(kf_off) : "s"(g.kf_off));
+    }
     auto bin_approx = [&](const float4 &h, int i, bool valid, auto bits, auto fwd, float &num, float &den,
                           bool &near) -> int {
         valid = ahead(h, i, valid, fwd);
