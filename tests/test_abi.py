@@ -54,6 +54,7 @@ def test_null_context_is_rejected_without_touching_the_device(lib):
     assert lib.hough_peaks(nul, nul, 1, nul, 0, nul, nul) == EINVAL
     assert lib.hough_event_batch(nul, 1, nul, nul, nul, 1, nul, nul, nul, nul, nul, nul) == EINVAL
     assert lib.hough_set_launch(nul, 0, 8, 256, 1) == EINVAL
+    assert lib.hough_associate(nul, nul, nul, 0, nul, nul, 0, 1, nul, 0, nul, nul) == EINVAL
     from paper_1311_2769_amd.hough import _Grid
     out = ctypes.c_void_p()
     assert lib.hough_ctx_create(None, None, None) == EINVAL
