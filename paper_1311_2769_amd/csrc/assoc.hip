@@ -18,7 +18,9 @@
 // of the bitmap and goes to the map only for a set bit.  A pair is written
 // once, by the first position of C's window (dl, then dj, in increasing
 // order) at which the hit's bin is within one of kc: a thread that finds a
-// match recomputes the hit's bins at the earlier positions of that window.
+// match looks at the earlier positions of that window -- its own previous
+// two rows from registers, other slices (and rows before its run) by
+// recomputing the hit's bins there.
 // Each wavefront gathers its pairs in an LDS buffer and reserves room in the
 // output with one atomic per kAssocFlush pairs (a single counter taken per
 // pair by every wavefront serialised the displaced event's 10^8 pairs).
@@ -136,13 +138,16 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
     const int64_t plane = static_cast<int64_t>(np) * nk;
     const int el_lo = g.n_d0 > 1 ? -1 : 0;
     const int el_hi = g.n_d0 > 1 ? 1 : 0;
+    int kp1 = -1, kp2 = -1;            // the hit's bins at rows j - 1 and j - 2 of this run
     // every lane runs the same number of rows, so the wavefront stays together
-    // for the reservations below
     for (int r = 0; r < kAssocRows; ++r) {
         const int j = j0 + r;
         const int k = j < j1 ? hit_bin(g, hx, hy, hr2, l, j) : -1;
-        if (__ballot(k >= 0) == 0)
+        if (__ballot(k >= 0) == 0) {
+            kp2 = kp1;
+            kp1 = k;
             continue;
+        }
         // candidates in the window of the vote (l, j, k): C = (l - el, j - ej, k - ek)
         for (int el = el_lo; el <= el_hi; ++el) {
             for (int ej = -1; ej <= 1; ++ej) {
@@ -175,10 +180,16 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
                             for (int dj = -1; dj <= 1; ++dj) {
                                 if (dl == el && dj >= ej)
                                     break;
-                                int jj = jc + dj;
-                                jj += jj < 0 ? np : 0;
-                                jj -= jj >= np ? np : 0;
-                                const int kk = hit_bin(g, hx, hy, hr2, ll, jj);
+                                int kk;
+                                const int back = ej - dj;      // rows before j, same slice
+                                if (dl == el && back <= r) {
+                                    kk = back == 1 ? kp1 : kp2;
+                                } else {
+                                    int jj = jc + dj;
+                                    jj += jj < 0 ? np : 0;
+                                    jj -= jj >= np ? np : 0;
+                                    kk = hit_bin(g, hx, hy, hr2, ll, jj);
+                                }
                                 if (kk >= 0 && kk >= kc - 1 && kk <= kc + 1) {
                                     emit = false;
                                     break;
@@ -195,6 +206,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
                 }
             }
         }
+        kp2 = kp1;
+        kp1 = k;
     }
     if (fill > 0)
         flush();
