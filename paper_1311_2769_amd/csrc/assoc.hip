@@ -11,16 +11,14 @@
 //
 // Layout: the context's cell map holds, per cell, 1 + the index of the
 // candidate there (0: none), and a bitmap of the cells that hold one: per
-// (d0, phi0) row, bit kc + 1 of kAssocRowWords(n_kappa) dwords (about 1 MB for
-// the displaced grid, so it stays in L2).  One thread takes one (hit, d0
-// slice) and a run of kAssocRows phi0 rows; for every vote (l, j, k) it reads
-// the three bits k-1..k+1 of each window row (l - el, j - ej) from two dwords
-// of the bitmap and goes to the map only for a set bit.  A pair is written
-// once, by the first position of C's window (dl, then dj, in increasing
-// order) at which the hit's bin is within one of kc: a thread that finds a
-// match looks at the earlier positions of that window -- its own previous
-// two rows from registers, other slices (and rows before its run) by
-// recomputing the hit's bins there.
+// (d0, phi0) row, bit kc + 1 of assoc_row_words(n_kappa) dwords (about 1 MB
+// for the displaced grid, so it stays in L2).  One thread takes one (hit, d0
+// slice l) and a run of kAssocRows phi0 rows, and owns the candidates of
+// those cells.  Sliding along the rows it keeps the hit's bins at the nine
+// window positions (slices l - 1 .. l + 1, rows jc - 1 .. jc + 1; three new
+// bins per row in 3D, one in 2D); the candidates the hit reaches are the
+// union of the positions' [b - 1, b + 1], read from two bitmap dwords per
+// position, so each pair is found once without looking at other threads.
 // Each wavefront gathers its pairs in an LDS buffer and reserves room in the
 // output with one atomic per kAssocFlush pairs (a single counter taken per
 // pair by every wavefront serialised the displaced event's 10^8 pairs).
@@ -136,78 +134,78 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
     const int nk = g.n_kappa;
     const int np = g.n_phi;
     const int64_t plane = static_cast<int64_t>(np) * nk;
-    const int el_lo = g.n_d0 > 1 ? -1 : 0;
-    const int el_hi = g.n_d0 > 1 ? 1 : 0;
-    int kp1 = -1, kp2 = -1;            // the hit's bins at rows j - 1 and j - 2 of this run
+    // The thread owns the candidates C = (l, jc, kc) of its slice and rows.
+    // The hit belongs to C when one of its bins b at the window positions
+    // (l + dl, jc + dj) has |b - kc| <= 1, so the kc it reaches from row jc
+    // form the union over the positions of [b - 1, b + 1]: each position adds
+    // the candidates of its three cells that no earlier position covered, and
+    // every pair comes out once.  bins[s][t]: slice l + s - 1, row jc + t - 1
+    // (-1: no vote there, or a slice outside the grid), slid along the rows.
+    int bins[3][3];
+    auto bin_at = [&](int s, int row) -> int {
+        const int ll = l + s - 1;
+        if (!live || ll < 0 || ll >= g.n_d0)
+            return -1;
+        row += row < 0 ? np : 0;
+        row -= row >= np ? np : 0;
+        return hit_bin(g, hx, hy, hr2, ll, row);
+    };
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        bins[s][0] = bin_at(s, j0 - 1);
+        bins[s][1] = bin_at(s, j0);
+    }
+    const uint32_t *brow0 = a.bits + static_cast<int64_t>(l) * np * a.row_words;
     // every lane runs the same number of rows, so the wavefront stays together
     for (int r = 0; r < kAssocRows; ++r) {
-        const int j = j0 + r;
-        const int k = j < j1 ? hit_bin(g, hx, hy, hr2, l, j) : -1;
-        if (__ballot(k >= 0) == 0) {
-            kp2 = kp1;
-            kp1 = k;
-            continue;
-        }
-        // candidates in the window of the vote (l, j, k): C = (l - el, j - ej, k - ek)
-        for (int el = el_lo; el <= el_hi; ++el) {
-            for (int ej = -1; ej <= 1; ++ej) {
-                const int lc = l - el;
-                int jc = j - ej;
-                jc += jc < 0 ? np : 0;
-                jc -= jc >= np ? np : 0;
-                // bits kc + 1 for kc = k - 1 .. k + 1 of row (lc, jc)
-                uint32_t pend = 0u;
-                if (k >= 0 && lc >= 0 && lc < g.n_d0) {
-                    const uint32_t *w = a.bits + (static_cast<int64_t>(lc) * np + jc) * a.row_words + (k >> 5);
-                    const uint64_t two = static_cast<uint64_t>(w[0]) | (static_cast<uint64_t>(w[1]) << 32);
-                    pend = static_cast<uint32_t>(two >> (k & 31)) & 7u;
-                }
-                while (__ballot(pend != 0u)) {
-                    bool emit = false;
-                    int cand = 0;
-                    if (pend != 0u) {
-                        const int bit = __ffs(pend) - 1;        // kc = k - 1 + bit
-                        pend &= pend - 1u;
-                        const int kc = k - 1 + bit;
-                        cand = a.map[lc * plane + static_cast<int64_t>(jc) * nk + kc] - 1;
-                        // the position (el, ej) of this vote in C's window; emit only when
-                        // no earlier position of the window has the hit within one of kc
-                        emit = cand >= 0;
-                        for (int dl = -1; dl <= el && emit; ++dl) {
-                            const int ll = lc + dl;
-                            if (ll < 0 || ll >= g.n_d0)
-                                continue;
-                            for (int dj = -1; dj <= 1; ++dj) {
-                                if (dl == el && dj >= ej)
-                                    break;
-                                int kk;
-                                const int back = ej - dj;      // rows before j, same slice
-                                if (dl == el && back <= r) {
-                                    kk = back == 1 ? kp1 : kp2;
-                                } else {
-                                    int jj = jc + dj;
-                                    jj += jj < 0 ? np : 0;
-                                    jj -= jj >= np ? np : 0;
-                                    kk = hit_bin(g, hx, hy, hr2, ll, jj);
-                                }
-                                if (kk >= 0 && kk >= kc - 1 && kk <= kc + 1) {
-                                    emit = false;
-                                    break;
-                                }
-                            }
-                        }
+        const int jc = j0 + r;
+        const bool own = jc < j1;
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+            bins[s][2] = own ? bin_at(s, jc + 1) : -1;
+        const uint32_t *brow = brow0 + static_cast<int64_t>(own ? jc : 0) * a.row_words;
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int kp = bins[p / 3][p % 3];
+            uint32_t pend = 0u;
+            if (own && kp >= 0) {
+                // bits kc + 1 for kc = kp - 1 .. kp + 1 of the row (l, jc)
+                const uint32_t *w = brow + (kp >> 5);
+                const uint64_t two = static_cast<uint64_t>(w[0]) | (static_cast<uint64_t>(w[1]) << 32);
+                pend = static_cast<uint32_t>(two >> (kp & 31)) & 7u;
+                // minus the cells an earlier position already reached
+                if (pend != 0u) {
+#pragma unroll
+                    for (int q = 0; q < p; ++q) {
+                        const int kq = bins[q / 3][q % 3];
+                        const int o = kq - kp;         // its cells are kp + o - 1 .. kp + o + 1
+                        if (kq >= 0 && o >= -2 && o <= 2)
+                            pend &= ~(o >= 0 ? (7u << o) : (7u >> -o));
                     }
-                    const uint64_t m = __ballot(emit);
-                    if (emit)
-                        buf[fill + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cand, h);
-                    fill += __popcll(m);
-                    if (fill > kAssocFlush)
-                        flush();
                 }
             }
+            while (__ballot(pend != 0u)) {
+                bool emit = false;
+                int cand = 0;
+                if (pend != 0u) {
+                    const int kc = kp - 1 + (__ffs(pend) - 1);
+                    pend &= pend - 1u;
+                    cand = a.map[l * plane + static_cast<int64_t>(jc) * nk + kc] - 1;
+                    emit = cand >= 0;
+                }
+                const uint64_t m = __ballot(emit);
+                if (emit)
+                    buf[fill + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cand, h);
+                fill += __popcll(m);
+                if (fill > kAssocFlush)
+                    flush();
+            }
         }
-        kp2 = kp1;
-        kp1 = k;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            bins[s][0] = bins[s][1];
+            bins[s][1] = bins[s][2];
+        }
     }
     if (fill > 0)
         flush();
