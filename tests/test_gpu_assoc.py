@@ -131,3 +131,14 @@ def test_association_on_device_candidates_gives_the_truth_report():
     rm, rnh = synth.match_candidates(rc, rh, rn, ev.label, wc.threshold)
     np.testing.assert_array_equal(m, rm)
     assert synth.efficiency(m, nh, ev.label, wc.threshold) == synth.efficiency(rm, rnh, ev.label, wc.threshold)
+
+
+@pytest.mark.parametrize("shape", [(100, 48, 1), (3, 16, 1), (70, 20, 5)])
+def test_association_odd_grids(shape):
+    """Row counts that are not a multiple of the kernel's 64-row runs (a partial last
+    run, the periodic wrap inside a run), the smallest n_phi, and a 3D grid."""
+    n_phi, n_kappa, n_d0 = shape
+    grid = synth.make_grid(n_phi, n_kappa, n_d0=n_d0, d0_range=(-6.0, 6.0) if n_d0 > 1 else None,
+                           kappa_half_range_inv_cm=5.0)
+    ev = synth.gen_config_event(1, 3)
+    _check(grid, ev.x, ev.y, 3, 3, f"grid {shape}")
