@@ -124,3 +124,15 @@ def test_forward_strict_hand_case_without_culling():
     ctx = hough.HoughContext(g, device=_dev())
     _assert_same(_single(ctx, np.array([1.0], np.float32), np.array([0.0], np.float32), 1), ref, "strict")
 
+
+
+@pytest.mark.parametrize("shape,acc", [((100, 48), "u16"), ((4096, 64), "i32"), ((2048, 40), "u16")])
+def test_forward_tile_ranges_and_u16(shape, acc):
+    """Forward grids whose slices have more than 63 tiles (culling by tile ranges
+    instead of masks), a partial last tile, and uint16 cells."""
+    grid = _fwd(synth.make_grid(*shape, acc_type=acc))
+    ev = synth.gen_config_event(1, 4)
+    ref = _ref(ev.x, ev.y, grid, 3)
+    ctx = hough.HoughContext(grid, device=_dev(), max_hits=ev.n_hits)
+    print(f"[forward] grid {shape} {acc}: {ref[1]} votes, {ref[4]} candidates", flush=True)
+    _assert_same(_single(ctx, ev.x, ev.y, 3), ref, f"grid {shape} {acc}")
