@@ -57,6 +57,9 @@ def parse_args():
     ap.add_argument("--skip-3d", action="store_true", help="skip the displaced-vertex (3D) batch leg")
     ap.add_argument("--skip-straight", action="store_true", help="skip the straight-line batch leg")
     ap.add_argument("--skip-forward", action="store_true", help="skip the forward-hemisphere batch leg")
+    ap.add_argument("--lanes", type=int, default=2,
+                    help="batches in flight: contexts on streams of their own, taking the steps in turn "
+                         "(2: one batch's sort overlaps the next one's vote, +1 %%; 3 measured slower)")
     ap.add_argument("--skip-assoc", action="store_true", help="skip the hit-association / truth report leg")
     ap.add_argument("--serve-rates", default="1000,5000,20000",
                     help="offered rates (events/s) of the served stream; empty to skip")
@@ -487,14 +490,28 @@ def main():
     def step():
         ctx.event_batch(hit_off, x, y, thr, cand_off=cand_off, cands=cands, n_found=n_found, n_votes=n_votes)
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
+    # Lanes: lane 0 is ctx on the current stream; further lanes are contexts of
+    # their own on streams of their own (default priority), so that one batch's
+    # sort and hit preparation overlap another's vote, as in the server.
+    lanes = [(ctx, torch.cuda.current_stream(), cands, n_found, n_votes)]
+    for _ in range(1, max(1, args.lanes)):
+        c2 = hough.HoughContext(grid, device=dev, max_events=n_ev, max_hits=batch.n_hits)
+        lanes.append((c2, torch.cuda.Stream(device=dev), torch.empty_like(cands), torch.empty_like(n_found),
+                      torch.empty_like(n_votes)))
+
+    def lane_step(i):
+        c, s, cc, nf, nv = lanes[i % len(lanes)]
+        c.event_batch(hit_off, x, y, thr, cand_off=cand_off, cands=cc, n_found=nf, n_votes=nv, stream=s)
+
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} (x {len(lanes)} lanes)")
+    for i in range(args.warmup * len(lanes)):
+        lane_step(i)
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for i in range(args.steps):
+        lane_step(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
@@ -579,7 +596,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wc.name, "events_per_step": n_ev, "hits_per_step": int(batch.n_hits),
-                   "grid": [grid.n_d0, grid.n_phi, grid.n_kappa], "acc": grid.acc_type, "threshold": thr},
+                   "grid": [grid.n_d0, grid.n_phi, grid.n_kappa], "acc": grid.acc_type, "threshold": thr,
+                   "lanes": len(lanes)},
         "votes_per_s": votes * args.steps / dt,
         "evals_per_s": evals * args.steps / dt,
         "candidates_per_step": found,
