@@ -7,8 +7,8 @@
  * compatible with, and the local maxima above a threshold become track
  * candidates.  Section 3 notes that prompt curved tracks need two parameters
  * (phi0, kappa) and displaced curved tracks three (d0, phi0, kappa); both are
- * served here.  Section 4 notes the computation for each hit is independent
- * of all other hits, which is the parallelism the kernels exploit.
+ * served here.  Section 4 points out that no hit's votes depend on any other
+ * hit: that independence is the parallelism the kernels use.
  *
  * Track model (transverse plane, cm).  Hypothesis (d0, phi0, kappa) is the
  * circle whose point of closest approach to the origin is

@@ -16,6 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhough.so")
+OBJ_DIR = os.path.join(ROOT, "_build", "libhough")
 SOURCES = ["vote.hip", "peaks.hip", "vertex.hip", "assoc.hip", "api.hip", "selftest.hip", "diag.hip", "tune.hip", "server.hip"]
 ARCH = "gfx950"
 
@@ -40,10 +41,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build(verbose: bool = False) -> str:
-    out_tmp = LIB + ".tmp"
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc(), *FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", out_tmp, *srcs]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,6 +51,22 @@ def build(verbose: bool = False) -> str:
     noise = [l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip()]
     if verbose and noise:
         sys.stderr.write("\n".join(noise) + "\n")
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to an object (in parallel) and link the library."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    cc = hipcc()
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    objs = [os.path.join(OBJ_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    cmds = [[cc, *compile_flags, "-c", "-I", INCLUDE, "-I", CSRC, "-o", o, os.path.join(CSRC, s)]
+            for s, o in zip(SOURCES, objs)]
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        list(pool.map(lambda c: _run(c, verbose), cmds))
+    out_tmp = LIB + ".tmp"
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs], verbose)
     os.replace(out_tmp, LIB)
     return LIB
 

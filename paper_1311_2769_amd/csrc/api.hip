@@ -164,7 +164,7 @@ hipError_t hit_prep(const hough_ctx *c, const VoteShape &s, bool fused, const fl
                     int64_t n_hits, const int64_t *n_hits_dev, hipStream_t stream) {
     return launch_hit_prep(c->g, vote_tile_geom(c->g, s, fused), x, y, n_hits, n_hits_dev, c->hits,
                            c->cull_ok ? c->ranges : nullptr, c->max_hits, c->cull_ok, use_masks(c, s, fused),
-                           stream);
+                           nullptr, stream);
 }
 
 SortWork sort_work(const hough_ctx *c, bool fused_layout) {
@@ -379,6 +379,68 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
 
 void set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
 
+namespace hough {
+
+hough_status grid_setup(const hough_grid *grid, GridArgs *out) {
+    if (!grid || !out)
+        return HOUGH_EINVAL;
+    if (grid->n_phi < 3 || grid->n_kappa < 1 || grid->n_d0 < 1 || !grid->cos_phi || !grid->sin_phi)
+        return HOUGH_EINVAL;
+    if (grid->n_d0 > 1 && !grid->d0)
+        return HOUGH_EINVAL;
+    if (grid->family != HOUGH_CURVED && grid->family != HOUGH_STRAIGHT)
+        return HOUGH_EINVAL;
+    if (grid->family == HOUGH_STRAIGHT && (grid->n_d0 != 1 || grid->d0 != nullptr))
+        return HOUGH_EINVAL;
+    if (grid->forward != 0 && grid->forward != 1)
+        return HOUGH_EINVAL;
+    if (grid->acc_type != HOUGH_ACC_I32 && grid->acc_type != HOUGH_ACC_U16)
+        return HOUGH_EINVAL;
+    const bool u16 = grid->acc_type == HOUGH_ACC_U16;
+    if (u16 && (grid->n_kappa & 1))
+        return HOUGH_EINVAL;
+    const int64_t cells = static_cast<int64_t>(grid->n_d0) * grid->n_phi * grid->n_kappa;
+    if (cells > 0x7fffffffLL)
+        return HOUGH_EINVAL;
+    GridArgs g{};
+    g.cos_phi = grid->cos_phi;
+    g.sin_phi = grid->sin_phi;
+    g.d0 = grid->d0;
+    g.n_d0 = grid->n_d0;
+    g.n_phi = grid->n_phi;
+    g.n_kappa = grid->n_kappa;
+    // kappa_min = +0 is stored as -0: kf = (kappa - kappa_min) * kappa_scale
+    // then differs only for kappa = -0, where it is +0 instead of -0 (both vote
+    // bin 0), and is never -0 when kappa_scale >= 1 (see the vote's range test).
+    g.kappa_min = (grid->kappa_min == 0.0f) ? -0.0f : grid->kappa_min;
+    g.kappa_scale = grid->kappa_scale;
+    g.bin_bits = grid->kappa_scale >= 1.0f ? 1 : 0;
+    g.near_band = -1.0f;
+    g.kf_off = 0.0f;
+    g.kscale2 = 2.0f * grid->kappa_scale;
+    g.straight = grid->family == HOUGH_STRAIGHT ? 1 : 0;
+    g.forward = grid->forward;
+    g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
+    g.cells = cells;
+    g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;
+    float band = 0.0f, off = 0.0f;
+    if (vote_near_band(g, &band, &off)) {
+        g.near_band = band;
+        g.kf_off = off;
+    }
+    *out = g;
+    return HOUGH_OK;
+}
+
+int32_t default_tile_rows(const GridArgs &g) {
+    // 64 rows while two such workgroups still fit a CU's LDS (n_kappa <= 256:
+    // each hit is staged half as often; the displaced batch votes 6 % faster),
+    // else 32.  The forward kernels come in 32-row tiles.
+    return (g.n_kappa <= 256 && g.forward == 0) ? 64 : 32;
+}
+
+}  // namespace hough
+
 void ctx_grid(const hough_ctx *ctx, hough_grid *out) { *out = ctx->grid; }
 
 extern "C" {
@@ -402,24 +464,10 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     if (!out || !grid)
         return HOUGH_EINVAL;
     *out = nullptr;
-    if (grid->n_phi < 3 || grid->n_kappa < 1 || grid->n_d0 < 1 || !grid->cos_phi || !grid->sin_phi)
-        return HOUGH_EINVAL;
-    if (grid->n_d0 > 1 && !grid->d0)
-        return HOUGH_EINVAL;
-    if (grid->family != HOUGH_CURVED && grid->family != HOUGH_STRAIGHT)
-        return HOUGH_EINVAL;
-    if (grid->family == HOUGH_STRAIGHT && (grid->n_d0 != 1 || grid->d0 != nullptr))
-        return HOUGH_EINVAL;
-    if (grid->forward != 0 && grid->forward != 1)
-        return HOUGH_EINVAL;
-    if (grid->acc_type != HOUGH_ACC_I32 && grid->acc_type != HOUGH_ACC_U16)
+    GridArgs ga{};
+    if (grid_setup(grid, &ga) != HOUGH_OK)
         return HOUGH_EINVAL;
     const bool u16 = grid->acc_type == HOUGH_ACC_U16;
-    if (u16 && (grid->n_kappa & 1))
-        return HOUGH_EINVAL;
-    const int64_t cells = static_cast<int64_t>(grid->n_d0) * grid->n_phi * grid->n_kappa;
-    if (cells > 0x7fffffffLL)
-        return HOUGH_EINVAL;
     hough_ctx_opts o{};
     if (opts)
         o = *opts;
@@ -441,44 +489,15 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         delete c;
         return device_error(hipErrorNoDevice, "hipGetDevice");
     }
-    GridArgs &g = c->g;
-    g.cos_phi = grid->cos_phi;
-    g.sin_phi = grid->sin_phi;
-    g.d0 = grid->d0;
-    g.n_d0 = grid->n_d0;
-    g.n_phi = grid->n_phi;
-    g.n_kappa = grid->n_kappa;
-    // kappa_min = +0 is stored as -0: kf = (kappa - kappa_min) * kappa_scale
-    // then differs only for kappa = -0, where it is +0 instead of -0 (both vote
-    // bin 0), and is never -0 when kappa_scale >= 1 (see the vote's range test).
-    g.kappa_min = (grid->kappa_min == 0.0f) ? -0.0f : grid->kappa_min;
-    g.kappa_scale = grid->kappa_scale;
-    g.bin_bits = grid->kappa_scale >= 1.0f ? 1 : 0;
-    g.near_band = -1.0f;
-    g.kf_off = 0.0f;
-    g.kscale2 = 2.0f * grid->kappa_scale;
-    g.straight = grid->family == HOUGH_STRAIGHT ? 1 : 0;
-    g.forward = grid->forward;
-    g.row_dwords = u16 ? grid->n_kappa / 2 : grid->n_kappa;
-    g.cells = cells;
-    g.acc_dwords = static_cast<int64_t>(grid->n_d0) * grid->n_phi * g.row_dwords;
-    {
-        float band = 0.0f, off = 0.0f;
-        if (vote_near_band(g, &band, &off)) {
-            g.near_band = band;
-            g.kf_off = off;
-        }
-    }
+    c->g = ga;
+    const GridArgs &g = c->g;
     c->fused_batch = !u16 && grid->d0 == nullptr;
 
     // Default launch shapes (the autotuner may replace them).
     hipDeviceProp_t prop{};
     (void)hipGetDeviceProperties(&prop, c->device);
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    // Tile height: 64 rows while two such workgroups still fit a CU's LDS
-    // (n_kappa <= 256: each hit is staged half as often; the displaced batch
-    // votes 6 % faster), else 32.  The forward kernels come in 32-row tiles.
-    const int32_t rows = (g.n_kappa <= 256 && g.forward == 0) ? 64 : 32;
+    const int32_t rows = default_tile_rows(g);
     c->shape_single = VoteShape{rows, 512, u16 ? 1 : 4};
     c->shape_batch = VoteShape{rows, 512, 1};
     if (!vote_shape_supported(c->shape_single, u16, g.n_kappa, g.forward != 0) ||
@@ -809,11 +828,10 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
         ctx->graphs.push_back(GraphEntry{key, exec});
     }
     HIP_TRY(hipGraphLaunch(exec, s));
-    if (changed) {
-        // The graph's first node copies the pinned block; it is free once the graph is done.
-        HIP_TRY(hipEventRecord(ctx->desc_done, s));
-        ctx->desc_in_flight = true;
-    }
+    // Every replay's first node copies the pinned block, changed or not, so
+    // the block may be rewritten only after the latest replay has read it.
+    HIP_TRY(hipEventRecord(ctx->desc_done, s));
+    ctx->desc_in_flight = true;
     return HOUGH_OK;
 }
 

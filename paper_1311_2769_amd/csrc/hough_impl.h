@@ -152,6 +152,12 @@ int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
 TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused);
 int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);
 
+// The rules of hough_ctx_create for a grid, and its kernel form (EINVAL when
+// the grid is rejected).  api.hip.
+hough_status grid_setup(const hough_grid *grid, GridArgs *out);
+// Default tile height of a grid's vote kernels.
+int32_t default_tile_rows(const GridArgs &g);
+
 hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *n_votes,
                        hipStream_t stream);
 // Batch form: state of all max_events slots, n_votes of the live events, work counter.
@@ -166,10 +172,18 @@ hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
 // kappa_scale) with approximate bins.  With
 // ranges: ranges[l*range_stride + h] holds the two tile ranges of slice l
 // outside which hit h cannot vote.  n_hits_dev, when given, overrides n_hits
-// (which then only sizes the grid).
+// (which then only sizes the grid).  table_ok, when given, is a device flag
+// read by the kernel: zero makes every entry take every tile and every record
+// the division operator, as if div_fast were false (a phi0 table that does not
+// hold the bin centres); nullptr means the caller has checked the table.
 hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x, const float *y, int64_t n_hits,
                            const int64_t *n_hits_dev, float4 *hits, uint2 *ranges, int64_t range_stride,
-                           bool div_fast, bool masks, hipStream_t stream);
+                           bool div_fast, bool masks, const int32_t *table_ok, hipStream_t stream);
+// Device check of a phi0 table against the bin centres (j + 1/2) 2 pi / n_phi
+// (angle within 1e-6 rad, norm within 1e-6 of 1, n_phi <= 32768): writes 1 or
+// 0 to *ok.  One workgroup; allocates nothing.
+hipError_t launch_table_check(const float *cos_phi, const float *sin_phi, int32_t n_phi, int32_t *ok,
+                              hipStream_t stream);
 
 // One event: hits [0, n_hits).
 hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,

@@ -742,6 +742,8 @@ struct PrepArgs {
     int32_t forward;            // forward-hemisphere option: the first arc only
     float dlo, dhi;             // straight: the d0 range, rounded outwards
     int32_t mask_mode;          // write 64-bit tile masks instead of ranges (tiles <= kMaskTiles)
+    const int32_t *table_ok;    // device flag: the phi0 table holds the bin centres (else no arcs and no
+                                // fast division), or nullptr when the host has checked the table
 };
 
 // The tiles of a cyclic range as bits of a mask (T <= kMaskTiles).
@@ -841,6 +843,9 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     const float yf = p.y[i];
     const float r2 = xf * xf + yf * yf;
     const int l_begin = blockIdx.y * kPrepSlices;
+    // Arcs and the fast division rest on a table of bin centres; without one
+    // every (hit, slice) takes every tile and the division operator.
+    const bool table = p.table_ok == nullptr || *p.table_ok != 0;
     if (l_begin == 0) {
         float4 rec = make_float4(xf, yf, r2, 0.0f);
         if (p.straight) {
@@ -849,7 +854,7 @@ __global__ void hit_prep_kernel(PrepArgs p) {
             // lands in the same bin), and the approximate bins fma(u, w, off)
             // with w = kappa_scale
             rec = make_float4(xf, yf, 1.0f, p.w_scale);
-        } else if (p.div_fast && p.d0 == nullptr) {
+        } else if (p.div_fast && table && p.d0 == nullptr) {
             const float half = 0.5f * r2;
             if (quot_den_ok(half))
                 rec = make_float4(xf, yf, half, quot_recip(half) * p.w_scale);
@@ -858,6 +863,12 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     }
     if (!p.ranges)
         return;
+    if (!table) {
+        const int l_stop = p.straight ? 1 : min(l_begin + kPrepSlices, p.d0 ? p.n_d0 : 1);
+        for (int l = l_begin; l < l_stop; ++l)
+            p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = hit_entry(make_uint2(kAllTiles, 0u), p);
+        return;
+    }
     const float r = sqrtf(r2);
     const bool r_ok = r >= 0x1.0p-30f && r <= 0x1.0p30f;     // false for NaN
     const float inv_r = arc_rcp(r_ok ? r : 1.0f);
@@ -920,6 +931,30 @@ __global__ void hit_prep_kernel(PrepArgs p) {
             out.y |= kFastDiv;
         p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = hit_entry(out, p);
     }
+}
+
+// Is row j's (cos, sin) the bin centre (j + 1/2) 2 pi / n_phi, within 1e-6 rad
+// in angle and 1e-6 in norm (fp64)?  One workgroup; thread 0 writes the flag.
+__global__ __launch_bounds__(1024) void table_check_kernel(const float *cos_phi, const float *sin_phi,
+                                                           int32_t n_phi, int32_t *ok) {
+    const double two_pi = 6.283185307179586;
+    int bad = n_phi > 32768 ? 1 : 0;
+    for (int j = threadIdx.x; j < n_phi && !bad; j += blockDim.x) {
+        const double c = cos_phi[j];
+        const double sn = sin_phi[j];
+        const double want = (static_cast<double>(j) + 0.5) * two_pi / static_cast<double>(n_phi);
+        double diff = fmod(atan2(sn, c) - want, two_pi);
+        if (diff > two_pi / 2)
+            diff -= two_pi;
+        if (diff < -two_pi / 2)
+            diff += two_pi;
+        const double norm = hypot(c, sn);
+        if (!(fabs(diff) < 1e-6) || !(fabs(norm - 1.0) < 1e-6))
+            bad = 1;
+    }
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0)
+        *ok = bad ? 0 : 1;
 }
 
 __global__ void prep_kernel(EventState *state, int32_t n_events, unsigned long long *n_votes) {
@@ -1096,7 +1131,7 @@ int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s) {
 
 hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x, const float *y, int64_t n_hits,
                            const int64_t *n_hits_dev, float4 *hits, uint2 *ranges, int64_t range_stride,
-                           bool div_fast, bool masks, hipStream_t stream) {
+                           bool div_fast, bool masks, const int32_t *table_ok, hipStream_t stream) {
     if (n_hits <= 0)
         return hipSuccess;
     PrepArgs p{};
@@ -1116,6 +1151,7 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     p.div_fast = div_fast ? 1 : 0;
     p.w_scale = g.near_band > 0.0f ? g.kappa_scale : 1.0f;
     p.mask_mode = masks && ranges && tg.tiles <= kMaskTiles ? 1 : 0;
+    p.table_ok = table_ok;
     const double kmin = g.kappa_min;
     const double kmax = static_cast<double>(g.kappa_min) + static_cast<double>(g.n_kappa) / g.kappa_scale;
     const double K = fmax(fabs(kmin), fabs(kmax)) * (1.0 + 1e-3);
@@ -1142,6 +1178,12 @@ hipError_t launch_hit_prep(const GridArgs &g, const TileGeom &tg, const float *x
     const unsigned blocks = static_cast<unsigned>((n_hits + 255) / 256);
     const unsigned groups = ranges ? static_cast<unsigned>((g.n_d0 + kPrepSlices - 1) / kPrepSlices) : 1u;
     hipLaunchKernelGGL(hit_prep_kernel, dim3(blocks, groups), dim3(256), 0, stream, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_check(const float *cos_phi, const float *sin_phi, int32_t n_phi, int32_t *ok,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(table_check_kernel, dim3(1), dim3(1024), 0, stream, cos_phi, sin_phi, n_phi, ok);
     return hipGetLastError();
 }
 

@@ -397,6 +397,45 @@ def test_batch_graph_replay_with_changing_descriptors():
             np.testing.assert_array_equal(got[:, 1], c)
 
 
+def test_batches_enqueued_back_to_back_without_a_host_sync():
+    """Calls A, A, B on one context and stream with no synchronisation between them: the
+    second A replays A's graph, whose first node reads the pinned descriptor block, so B
+    may rewrite that block only after that replay has read it.  Every result must equal
+    the single-event path."""
+    print("[parity] batches A, A, B back to back", flush=True)
+    g = synth.GRID_2D_SMALL
+    evs = [synth.gen_config_event(1, i) for i in range(16)]
+    single = hough.HoughContext(g)
+    ref = {}
+    for i, ev in enumerate(evs):
+        _, nv1, v, c, n = _gpu_find(single, ev.x, ev.y, 7)
+        ref[i] = (nv1, n, v, c)
+    ctx = hough.HoughContext(g, max_events=16, max_hits=20000)
+    cap = 4096
+    sels = {"A": [0, 1, 2, 3, 4, 5, 6, 7], "B": [8, 9, 10, 11, 12, 13, 14, 15, 1, 2]}
+    bufs = {}
+    for name, sel in sels.items():
+        b = synth.events.pack_events([evs[i] for i in sel])
+        bufs[name] = (b, _t(b.x), _t(b.y), torch.empty((len(sel) * cap, 2), dtype=torch.int32, device=_dev()),
+                      torch.empty(len(sel), dtype=torch.int32, device=_dev()),
+                      torch.empty(len(sel), dtype=torch.int64, device=_dev()))
+    torch.cuda.synchronize()
+    for rep in range(6):
+        for name in ("A", "A", "B"):
+            b, x, y, cands, nf, nv = bufs[name]
+            cand_off = np.arange(b.n_events + 1, dtype=np.int64) * cap
+            ctx.event_batch(b.hit_off, x, y, 7, cand_off=cand_off, cands=cands, n_found=nf, n_votes=nv)
+        torch.cuda.synchronize()
+        for name, sel in sels.items():
+            b, x, y, cands, nf, nv = bufs[name]
+            got_nf, got_nv, got = nf.cpu().numpy(), nv.cpu().numpy(), cands.cpu().numpy()
+            for k, i in enumerate(sel):
+                nv1, n, v, c = ref[i]
+                assert (int(got_nv[k]), int(got_nf[k])) == (nv1, n), (rep, name, k)
+                np.testing.assert_array_equal(got[k * cap:k * cap + n, 1], c, err_msg=f"{rep} {name} {k}")
+                np.testing.assert_array_equal(got[k * cap:k * cap + n, 0], v, err_msg=f"{rep} {name} {k}")
+
+
 # --------------------------------------------------------------------------------------
 # Culling: the tile masks must never drop a vote
 # --------------------------------------------------------------------------------------
