@@ -793,3 +793,104 @@ def test_association_threshold_and_empty_lists():
     assert pc.size == 0
     pc, ph = associate(ev.x, ev.y, grid, v[:0], c[:0], 1)
     assert pc.size == 0
+
+
+# --------------------------------------------------------------------------------------
+# The binary32 operation order (reading 5 of the vote: one rounding per operation, in
+# the order C parses the formula, no contraction, correctly rounded division)
+# --------------------------------------------------------------------------------------
+
+FP32_ORDER = os.path.join(os.path.dirname(__file__), "golden", "fp32_order.json")
+
+
+def _fp32_cases():
+    with open(FP32_ORDER) as f:
+        return json.load(f)
+
+
+def _hx(s):
+    return np.float32(float.fromhex(s))
+
+
+def _one_row_grid(case, g, family="curved"):
+    """A grid of one phi0 row (and one d0 slice) holding the case's table values."""
+    d0 = None
+    if family == "curved" and float.fromhex(case["d0"]) != 0.0:
+        d0 = [_hx(case["d0"])]
+    if family == "curved":
+        grid = _grid_from_tables(1, g["n_kappa"], _hx(g["kappa_min"]), _hx(g["kappa_scale"]),
+                                 [_hx(case["cos"])], [_hx(case["sin"])], d0)
+    else:
+        grid = _grid_from_tables(1, g["n_d0"], _hx(g["d0_min"]), _hx(g["d0_scale"]),
+                                 [_hx(case["cos"])], [_hx(case["sin"])])
+        grid = dataclasses.replace(grid, family="straight")
+    return grid
+
+
+def _voted_bin(acc):
+    nz = np.flatnonzero(acc.reshape(-1))
+    assert len(nz) <= 1 and (len(nz) == 0 or acc.reshape(-1)[nz[0]] == 1)
+    return int(nz[0]) if len(nz) else None
+
+
+def test_fp32_order_curved_votes():
+    """Hits whose kappa bin flips under a reordered, contracted, reciprocal or
+    binary64 evaluation vote the bin that exact rational arithmetic with one
+    binary32 rounding per operation gives (tests/golden/make_fp32_order.py)."""
+    doc = _fp32_cases()
+    wrong = []
+    for i, case in enumerate(doc["curved"]):
+        grid = _one_row_grid(case, doc["grids"][case["grid"]])
+        acc, _ = vote([_hx(case["x"])], [_hx(case["y"])], grid)
+        if _voted_bin(acc) != case["bin"]:
+            wrong.append((i, _voted_bin(acc), case["bin"], sorted(case["separates"])))
+    assert not wrong, wrong
+
+
+def test_fp32_order_straight_votes():
+    doc = _fp32_cases()
+    wrong = []
+    for i, case in enumerate(doc["straight"]):
+        grid = _one_row_grid(case, doc["grids"][case["grid"]], family="straight")
+        acc, _ = vote_straight([_hx(case["x"])], [_hx(case["y"])], grid)
+        if _voted_bin(acc) != case["bin"]:
+            wrong.append((i, _voted_bin(acc), case["bin"], sorted(case["separates"])))
+    assert not wrong, wrong
+
+
+def test_fp32_order_vertex_votes():
+    """One line (a candidate of a one-cell track grid holding the case's d0,
+    cos and sin) against one column (or row) centre of the vertex grid."""
+    doc = _fp32_cases()
+    wrong = []
+    for i, case in enumerate(doc["vertex"]):
+        g = doc["grids"][case["grid"]]
+        tgrid = _grid_from_tables(1, 1, -1.0, 1.0, [_hx(case["cos"])], [_hx(case["sin"])], [_hx(case["d0"])])
+        col = case["mode"] == "column"
+        centre = [_hx(case["centre"])]
+        vg = synth.VertexGrid(
+            n_x=1 if col else g["n_x"], n_y=g["n_y"] if col else 1,
+            x_centre=np.asarray(centre if col else np.zeros(g["n_x"]), np.float32),
+            y_centre=np.asarray(np.zeros(g["n_y"]) if col else centre, np.float32),
+            x_min=_hx(g["x_min"]), x_scale=_hx(g["x_scale"]), y_min=_hx(g["y_min"]), y_scale=_hx(g["y_scale"]))
+        vacc, _ = vertex_vote([10], [0], 1, tgrid, vg)
+        got = _voted_bin(vacc)
+        if got != case["bin"]:
+            wrong.append((i, got, case["bin"], sorted(case["separates"])))
+    assert not wrong, wrong
+
+
+def test_fp32_order_association():
+    """The association recomputes the vote: a case's hit lies in the windows of
+    candidates one bin below and one bin above its bin, and a bin flipped either
+    way leaves one of the two windows."""
+    doc = _fp32_cases()
+    wrong = []
+    for family in ("curved", "straight"):
+        for i, case in enumerate(doc[family]):
+            grid = _one_row_grid(case, doc["grids"][case["grid"]], family)
+            b = case["bin"]
+            c_idx, h_idx = associate([_hx(case["x"])], [_hx(case["y"])], grid, [9, 9], [b - 1, b + 1], 1)
+            if list(c_idx) != [0, 1] or list(h_idx) != [0, 0]:
+                wrong.append((family, i, list(c_idx), sorted(case["separates"])))
+    assert not wrong, wrong
