@@ -242,6 +242,37 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
                               const float *x, const float *y, void *acc, uint64_t *n_votes,
                               void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one event's
+ * vote, peak search and sort without a context -- bit for bit hough_vote then
+ * hough_peaks on a context of this grid.
+ *   grid:     as for hough_ctx_create (its tables are read by this call's
+ *             kernels only); x, y: [dev][n_hits] fp32 hits.
+ *   acc:      [dev] n_d0*n_phi*n_kappa cells of the grid's type, 4-byte
+ *             aligned, overwritten (the peak search reads it back).
+ *   out:      [dev][cap] sorted candidates (NULL when cap == 0); n_found: [dev]
+ *             int32 full count; n_votes: [dev] uint64 (8-byte aligned) or NULL.
+ * Scratch (hit records, tile masks or ranges, per-event state, sort buffers)
+ * is one fixed device array of HOUGH_NOALLOC_SCRATCH_BYTES inside the library,
+ * held on every device it runs on until the process ends; the call allocates
+ * and frees nothing.  It needs about 16 + 8*n_d0 bytes per hit plus 16 bytes
+ * per candidate the grid can hold (cells/4 for 2D, cells/8 for 3D): the
+ * workload grids fit with their events (a 1024x512 event of 64k hits uses
+ * about 4 MiB, a 64x512x256 event of 35k hits about 50 MiB).  Every call on a
+ * device shares that device's array and leaves its contents behind (each call
+ * rewrites what it reads); calls that overlap in time on one device -- on two
+ * streams or from two threads -- race on it and give wrong results.  The first
+ * call on each device looks the array's address up there (a symbol query, no
+ * allocation).  Asynchronous on stream.
+ * EINVAL (nothing enqueued; hough_last_error says which): the grid rules of
+ * hough_ctx_create, null pointers, negative sizes, misaligned acc or n_votes,
+ * uint16 with more than 65535 hits, or an event and grid whose scratch exceeds
+ * HOUGH_NOALLOC_SCRATCH_BYTES.  EDEVICE on a HIP failure. */
+#define HOUGH_NOALLOC_SCRATCH_BYTES (64u << 20)
+hough_status hough_event_noalloc(const hough_grid *grid, const float *x, const float *y, int32_t n_hits,
+                                 int32_t threshold, void *acc, hough_cand *out, int32_t cap,
+                                 int32_t *n_found, uint64_t *n_votes, void *stream);
+
 /* Launch-shape controls (used by the autotuner and tests; results never
  * depend on them).  which: 0 = single-event vote, 1 = batched vote.
  * rows: phi0 rows per workgroup tile; threads: workgroup size (256/512/1024);

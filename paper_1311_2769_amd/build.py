@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhough.so")
 OBJ_DIR = os.path.join(ROOT, "_build", "libhough")
-SOURCES = ["vote.hip", "peaks.hip", "vertex.hip", "assoc.hip", "api.hip", "selftest.hip", "diag.hip", "tune.hip", "server.hip"]
+SOURCES = ["vote.hip", "peaks.hip", "vertex.hip", "assoc.hip", "api.hip", "noalloc.hip", "selftest.hip", "diag.hip",
+           "tune.hip", "server.hip"]
 ARCH = "gfx950"
 
 # -ffp-contract=off: the vote arithmetic is specified op by op (no FMA).

@@ -24,7 +24,7 @@ ACC_I32, ACC_U16 = 0, 1
 
 SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
-    "hough_vote_batch", "hough_vertices", "hough_associate",
+    "hough_vote_batch", "hough_vertices", "hough_associate", "hough_event_noalloc",
     "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
     "hough_autotune", "hough_tune_lookup",
     "hough_server_create", "hough_server_destroy", "hough_server_clock", "hough_server_submit",
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH):
     lib.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
     lib.hough_event_batch.restype = i32
     lib.hough_event_batch.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hough_event_noalloc.restype = i32
+    lib.hough_event_noalloc.argtypes = [ctypes.POINTER(_Grid), vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]
     lib.hough_vote_batch.restype = i32
     lib.hough_vote_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.hough_set_launch.restype = i32
@@ -208,6 +210,39 @@ class GridSpec:
     def max_candidates(self):
         """Upper bound on candidates of one event: no two candidates are neighbours."""
         return ((self.n_d0 + 1) // 2 if self.n_d0 > 1 else 1) * (self.n_phi // 2) * ((self.n_kappa + 1) // 2)
+
+
+class DeviceGrid:
+    """A grid's fp32 bin tables on a device and the hough_grid that points at them
+    (for the calls that take a grid rather than a context)."""
+
+    def __init__(self, grid, device="cuda"):
+        self.spec = grid if isinstance(grid, GridSpec) else GridSpec.from_grid(grid)
+        self.device = torch.device(device)
+        s = self.spec
+        self.cos_phi = torch.from_numpy(s.cos_phi.copy()).to(self.device)
+        self.sin_phi = torch.from_numpy(s.sin_phi.copy()).to(self.device)
+        self.d0 = None if s.d0 is None else torch.from_numpy(s.d0.copy()).to(self.device)
+        self.struct = _Grid(s.n_d0, s.n_phi, s.n_kappa, s.kappa_min, s.kappa_scale, self.cos_phi.data_ptr(),
+                            self.sin_phi.data_ptr(), None if self.d0 is None else self.d0.data_ptr(),
+                            ACC_U16 if s.acc_u16 else ACC_I32, 1 if s.straight else 0, 1 if s.forward else 0)
+
+
+def event_noalloc(dgrid, x, y, threshold, acc, out, n_found, n_votes=None, stream=None):
+    """hough_event_noalloc: one event's vote, peaks and sort with the library's fixed
+    scratch (no context).  dgrid: a DeviceGrid; acc, out [cap, 2] int32, n_found [1]
+    int32 and n_votes [1] int64 (or None) are the caller's device tensors."""
+    lib = load()
+    n = int(x.numel())
+    if y.numel() != n or x.dtype != torch.float32 or y.dtype != torch.float32:
+        raise ValueError("x, y must be fp32 tensors of equal length")
+    if acc.numel() != dgrid.spec.cells or acc.element_size() != (2 if dgrid.spec.acc_u16 else 4):
+        raise ValueError("accumulator has the wrong size or type")
+    cap = int(out.shape[0]) if out is not None else 0
+    _check(lib.hough_event_noalloc(ctypes.byref(dgrid.struct), _ptr(x), _ptr(y), n, int(threshold), _ptr(acc),
+                                   _ptr(out) if cap else None, cap, _ptr(n_found), _ptr(n_votes),
+                                   _stream_handle(stream)), "hough_event_noalloc")
+    return acc, out, n_found, n_votes
 
 
 class VertexGridSpec:
