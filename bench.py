@@ -4,10 +4,13 @@
 One step = one batch of 256 uneven prompt-track events (200-8,000 tracks
 each, about 2k-100k hits, 1024 phi0 x 512 kappa int32 accumulators,
 threshold 7) through the whole path: vote, peak search and sorted candidate
-lists, launched as one captured graph (hough_event_batch).  Hits are resident
-in HBM before the timed region.  The line also carries the per-event-launch
-rate on the same events, the dominant kernel against its roofline and the
-CPU oracle timed on a bounded sample.
+lists, launched as one captured graph (hough_event_batch) with the launch
+shape the autotuner picks.  For `value` the hits are resident in HBM before
+the timed region and the candidates stay there.  The line also carries the
+same batches with the host transfers (pinned hits in, every stored candidate
+back), the per-event-launch rates on the same events, the served stream, the
+dominant kernel against its roofline and the CPU oracle timed on a bounded
+sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -26,13 +29,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs at up to 2.4 GHz, 64 fp32 lanes per CU per clock for
-# one non-fused, non-packed fp32 operation (157.3 TFLOP/s counts a packed
-# FMA as four flops per lane).
-PEAK_FP32_OPS = 256 * 64 * 2.4e9          # 39.3e12 single fp32 operations / s
-PEAK_LDS_ATOMIC = 256 * 64 * 2.4e9        # 39.3e12 dword atomics / s if every bank retires one per clock
-FLOPS_PER_EVAL_2D = 7                     # u: 2 mul + 1 sub; 2u: 1 mul; divide: 1; kf: 1 sub + 1 mul
-FLOPS_PER_HIT_2D = 3                      # r^2: 2 mul + 1 add
+# MI355X: 256 CUs at up to 2.4 GHz, 64 lanes per CU issuing one unpacked
+# VALU operation per clock (the 157.3 TFLOP/s fp32 figure counts a packed FMA
+# as four flops per lane; packed fp32 is off in this build).
+PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 39.3e12 VALU lane-operations / s
+# VALU instructions per evaluated (hit, phi0 row) pair in the 2D vote loop of
+# the built kernel (approximate bins): u = y c - x s (2 mul, 1 sub), the bin
+# estimate (1 fma), its clamp (1 min), the band test (fract, compare), the
+# conversion (1 cvt) and the LDS address (1 shift-add).  The exact redo, one
+# wave-uniform branch away, runs for a few per cent of pairs.
+VALU_PER_PAIR_2D = 9
 VERTEX_TRACK_THRESHOLD = 300              # track candidates that vote in the second transform
 VERTEX_THRESHOLD = 4                      # vertex candidates: lines meeting in a cell
 
@@ -60,8 +66,13 @@ def parse_args():
     ap.add_argument("--lanes", type=int, default=2,
                     help="batches in flight: contexts on streams of their own, taking the steps in turn "
                          "(2: one batch's sort overlaps the next one's vote, +1 %%; 3 measured slower)")
+    ap.add_argument("--e2e-lanes", type=int, default=3,
+                    help="batches in flight in the leg with host transfers (copies in, compute and "
+                         "copies out of different batches overlap)")
+    ap.add_argument("--e2e-steps", type=int, default=20, help="timed steps of the leg with host transfers")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--skip-assoc", action="store_true", help="skip the hit-association / truth report leg")
-    ap.add_argument("--serve-rates", default="1000,5000,20000",
+    ap.add_argument("--serve-rates", default="1000,5000,8000,10000,12000,20000",
                     help="offered rates (events/s) of the served stream; empty to skip")
     ap.add_argument("--serve-events", type=int, default=20000, help="measured arrivals per rate")
     ap.add_argument("--serve-warmup", type=int, default=1000, help="arrivals per rate before the measured ones")
@@ -83,23 +94,30 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per launch of the vote kernel from the committed counter
-    summary, or None when it is missing or was taken from other sources."""
+def counter_fields():
+    """Per-dispatch counters of the vote kernel from the committed summary:
+    (HBM bytes per launch, VALU wave-instructions per launch), each None when
+    missing or taken from other kernel sources."""
     try:
         with open(COUNTERS) as f:
             fields = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
     except OSError:
-        return None
+        return None, None
     fields = {k.strip().strip("-* `"): v.strip().strip("` ") for k, v in fields.items()}
+    if fields.get("kernel_source_sha256") != kernel_digest():
+        return None, None
+    traffic = valu = None
     try:
-        if fields.get("kernel_source_sha256") != kernel_digest():
-            return None
         fetch = float(fields["fetch_kib_per_dispatch"]) * float(fields["fetch_scale"])
         write = float(fields["write_kib_per_dispatch"]) * float(fields["write_scale"])
+        traffic = 1024.0 * (fetch + write)
     except (KeyError, ValueError):
-        return None
-    return 1024.0 * (fetch + write)
+        pass
+    try:
+        valu = float(fields["valu_insts_per_dispatch"])
+    except (KeyError, ValueError):
+        pass
+    return traffic, valu
 
 
 def _oracle_events(args):
@@ -121,13 +139,15 @@ def _oracle_events(args):
 def cpu_baseline(batch, grid, threshold, budget_s, max_workers=16):
     """The oracle as it stands on the host's cores: one thread over the
     batch's events in order, then independent events spread over a pool of
-    worker processes (one event per process at a time)."""
+    worker processes (one event per process at a time), one per core the job
+    may use: the cores this process may run on, at most max_workers (the
+    host share a one-GPU job is given, whatever the machine has)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     evs = [(ev.x, ev.y) for ev in batch.events]
     n1, dt1 = _oracle_events((evs, grid, threshold, budget_s))
-    workers = max(1, min(max_workers, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
-                         else (os.cpu_count() or 1)))
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(max_workers, allowed))
     chunks = [evs[i::workers] for i in range(workers)]
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
         res = list(pool.map(_oracle_events, [(c, grid, threshold, budget_s) for c in chunks]))
@@ -142,52 +162,171 @@ def cpu_baseline(batch, grid, threshold, budget_s, max_workers=16):
     return {"value": rate, "unit": "events/s", "cores": workers, "kind": "oracle",
             "sample": f"{done} of the {batch.n_events} batch events split over {workers} worker processes "
                       f"(about {budget_s:.0f} s each), vote + peaks + sort per event; host CPU {cpu}",
+            "host_nproc": os.cpu_count(), "host_cores_allowed": allowed, "cpu_model": cpu,
             "single_thread": {"value": n1 / dt1, "events": n1, "seconds": dt1}}
 
 
-def per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off, events_per_s):
-    """Per-event launches (hough_vote + hough_peaks) on the same resident
-    events, and a closed loop with host round trips per event."""
+def per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off, shape):
+    """One event per call on the same events: resident (hits already in HBM,
+    candidates left there) and closed-loop with the host transfers of each
+    event (pinned hits in, n_found and exactly the stored candidates out, then
+    the next event), each through hough_vote + hough_peaks and through
+    hough_event_batch of one event (one graph replay per event)."""
     log("per-event launches")
     n_ev = batch.n_events
-    single = hough.HoughContext(grid, device=dev, max_hits=int(np.diff(hit_off).max()))
+    most = int(np.diff(hit_off).max())
+    single = hough.HoughContext(grid, device=dev, max_hits=most)
+    one = hough.HoughContext(grid, device=dev, max_events=1, max_hits=most)
+    if shape:
+        one.set_launch(1, shape[0], shape[1])
     acc1 = single.new_acc()
     out1 = torch.empty((cap, 2), dtype=torch.int32, device=dev)
     nf1 = torch.empty(1, dtype=torch.int32, device=dev)
     nv1 = torch.empty(1, dtype=torch.int64, device=dev)
+    one_off = np.array([0, cap], np.int64)
     views = [(x[hit_off[e]:hit_off[e + 1]], y[hit_off[e]:hit_off[e + 1]]) for e in range(n_ev)]
-    for xe, ye in views[:4]:
+
+    def two_calls(xe, ye):
         single.vote(xe, ye, acc1, nv1)
         single.peaks(acc1, thr, cap, out1, nf1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for xe, ye in views:
-        single.vote(xe, ye, acc1, nv1)
-        single.peaks(acc1, thr, cap, out1, nf1)
-    torch.cuda.synchronize()
-    per_event_rate = n_ev / (time.perf_counter() - t0)
-    # closed loop with host round trips: pinned H2D hits -> vote -> peaks -> D2H list -> sync
-    lat = []
+
+    def graph_call(xe, ye):
+        n = int(xe.numel())
+        one.event_batch(np.array([0, n], np.int64), xe, ye, thr, cand_off=one_off, cands=out1, n_found=nf1,
+                        n_votes=nv1)
+
+    out = {}
+    for name, call in (("vote_peaks", two_calls), ("graph_of_one", graph_call)):
+        for xe, ye in views[:4]:
+            call(xe, ye)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for xe, ye in views:
+            call(xe, ye)
+        torch.cuda.synchronize()
+        resident = n_ev / (time.perf_counter() - t0)
+        # closed loop with host round trips
+        hx = torch.from_numpy(batch.x).pin_memory()
+        hy = torch.from_numpy(batch.y).pin_memory()
+        host_out = torch.empty((cap, 2), dtype=torch.int32).pin_memory()
+        host_nf = torch.empty(1, dtype=torch.int32).pin_memory()
+        xd = torch.empty(most, dtype=torch.float32, device=dev)
+        yd = torch.empty_like(xd)
+        stream = torch.cuda.current_stream()
+        lat = []
+        t_all = time.perf_counter()
+        for e in range(n_ev):
+            a, b = int(hit_off[e]), int(hit_off[e + 1])
+            ts = time.perf_counter()
+            xd[:b - a].copy_(hx[a:b], non_blocking=True)
+            yd[:b - a].copy_(hy[a:b], non_blocking=True)
+            call(xd[:b - a], yd[:b - a])
+            host_nf.copy_(nf1, non_blocking=True)
+            stream.synchronize()
+            n = min(int(host_nf[0]), cap)
+            if n > 0:
+                host_out[:n].copy_(out1[:n], non_blocking=True)
+                stream.synchronize()
+            lat.append(time.perf_counter() - ts)
+        closed = n_ev / (time.perf_counter() - t_all)
+        lat_ms = 1e3 * np.array(lat)
+        out[name] = {"resident_events_per_s": resident, "transfers_events_per_s": closed,
+                     "transfers_p50_ms": float(np.percentile(lat_ms, 50)),
+                     "transfers_p99_ms": float(np.percentile(lat_ms, 99)), "events": n_ev}
+    return out
+
+
+def end_to_end(args, hough, torch, dev, batch, grid, thr, cap, shape):
+    """The batch workload with its host transfers: each step copies the
+    batch's hits in from pinned host memory, runs hough_event_batch_packed,
+    brings cand_start and n_found back, and then -- the total known -- every
+    stored candidate in one copy.  e2e_lanes batches are in flight on streams
+    of their own, so one batch's copies overlap another's compute."""
+    from collections import deque
+    L = max(1, args.e2e_lanes)
+    n_ev = batch.n_events
+    H = int(batch.n_hits)
+    hit_off = batch.hit_off
+    cand_off = np.arange(n_ev + 1, dtype=np.int64) * cap
     hx = torch.from_numpy(batch.x).pin_memory()
     hy = torch.from_numpy(batch.y).pin_memory()
-    host_out = torch.empty((cap, 2), dtype=torch.int32).pin_memory()
-    xd = torch.empty(int(np.diff(hit_off).max()), dtype=torch.float32, device=dev)
-    yd = torch.empty_like(xd)
-    for e in range(min(args.latency_events, n_ev)):
-        a, b = int(hit_off[e]), int(hit_off[e + 1])
-        ts = time.perf_counter()
-        xd[:b - a].copy_(hx[a:b], non_blocking=True)
-        yd[:b - a].copy_(hy[a:b], non_blocking=True)
-        single.vote(xd[:b - a], yd[:b - a], acc1, nv1)
-        single.peaks(acc1, thr, cap, out1, nf1)
-        n = int(nf1.item())
-        host_out[:n].copy_(out1[:n])
-        lat.append(time.perf_counter() - ts)
-    lat_ms = 1e3 * np.array(lat)
-    return {"events_per_s": per_event_rate, "batched_speedup": events_per_s / per_event_rate,
-            "closed_loop_p50_ms": float(np.percentile(lat_ms, 50)),
-            "closed_loop_p99_ms": float(np.percentile(lat_ms, 99)),
-            "closed_loop_events": len(lat)}
+    log(f"host transfers: {L} batches in flight")
+
+    class Lane:
+        pass
+
+    lanes = []
+    for _ in range(L):
+        ln = Lane()
+        ln.ctx = hough.HoughContext(grid, device=dev, max_events=n_ev, max_hits=H)
+        if shape:
+            ln.ctx.set_launch(1, shape[0], shape[1])
+        ln.stream = torch.cuda.Stream(device=dev)
+        ln.x = torch.empty(H, dtype=torch.float32, device=dev)
+        ln.y = torch.empty_like(ln.x)
+        ln.cands = torch.empty((int(cand_off[-1]), 2), dtype=torch.int32, device=dev)
+        ln.start = torch.empty(n_ev + 1, dtype=torch.int64, device=dev)
+        ln.nf = torch.empty(n_ev, dtype=torch.int32, device=dev)
+        ln.nv = torch.empty(n_ev, dtype=torch.int64, device=dev)
+        ln.h_start = torch.empty(n_ev + 1, dtype=torch.int64).pin_memory()
+        ln.h_nf = torch.empty(n_ev, dtype=torch.int32).pin_memory()
+        ln.h_cands = None
+        ln.ev1 = torch.cuda.Event()
+        ln.done = torch.cuda.Event()
+        ln.used = False
+        lanes.append(ln)
+
+    def phase1(ln):
+        if ln.used:
+            ln.done.synchronize()           # its last candidates have reached the host
+        ln.used = True
+        with torch.cuda.stream(ln.stream):
+            ln.x.copy_(hx, non_blocking=True)
+            ln.y.copy_(hy, non_blocking=True)
+            ln.ctx.event_batch_packed(hit_off, ln.x, ln.y, thr, cand_off=cand_off, cands=ln.cands,
+                                      cand_start=ln.start, n_found=ln.nf, n_votes=ln.nv, stream=ln.stream)
+            ln.h_start.copy_(ln.start, non_blocking=True)
+            ln.h_nf.copy_(ln.nf, non_blocking=True)
+            ln.ev1.record(ln.stream)
+
+    def phase2(ln):
+        ln.ev1.synchronize()
+        total = int(ln.h_start[-1])
+        if ln.h_cands is None or ln.h_cands.shape[0] < total:
+            ln.h_cands = torch.empty((max(total, 1), 2), dtype=torch.int32).pin_memory()
+        with torch.cuda.stream(ln.stream):
+            if total > 0:
+                ln.h_cands[:total].copy_(ln.cands[:total], non_blocking=True)
+            ln.done.record(ln.stream)
+        return total
+
+    def run(steps):
+        pending = deque()
+        total = 0
+        for i in range(steps):
+            ln = lanes[i % L]
+            phase1(ln)
+            pending.append(ln)
+            if len(pending) >= L:
+                total = phase2(pending.popleft())
+        while pending:
+            total = phase2(pending.popleft())
+        for ln in lanes:
+            ln.done.synchronize()
+        return total
+
+    run(L)                                  # warm-up: graphs, pinned buffers
+    torch.cuda.synchronize()
+    steps = max(1, args.e2e_steps)
+    t0 = time.perf_counter()
+    total = run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nf = lanes[0].h_nf.numpy().astype(np.int64)
+    return {"events_per_s": n_ev * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps, "lanes": L,
+            "h2d_bytes_per_step": 8 * H, "d2h_bytes_per_step": 8 * int(total) + 12 * n_ev + 8,
+            "candidates_per_step": int(total), "n_found_per_step": int(nf.sum()),
+            "pcie_gbs": (8 * H + 8 * int(total)) * steps / dt / 1e9}
 
 
 def displaced_3d(hough, torch, dev, synth, log_fn, n_events=8, reps=10):
@@ -404,8 +543,9 @@ def served_stream(args, hough, synth, batch, log_fn):
     pool_y = np.concatenate([ev.y for ev in pool])
     grids = [synth.CONFIGS[4].grid, synth.CONFIGS[3].grid]
     thr = [synth.CONFIGS[4].threshold, synth.CONFIGS[3].threshold]
+    # every event's candidates are copied back to the host before its completion time is taken
     srv = hough.Server(grids, thr, lanes=2, batch_events=[64, 8], batch_hits=[1 << 22, 1 << 19], deadline_ms=2.0,
-                       queue_limit=4096, keep_candidates=False)
+                       queue_limit=4096, keep_candidates=True)
     out = []
     deadline_s = 2e-3
     try:
@@ -428,7 +568,7 @@ def served_stream(args, hough, synth, batch, log_fn):
             t_wall = time.time()
             limit = 60 + 3 * n / rate
             while th.is_alive() or len(res) < n:
-                res += srv.poll(wait_ms=20, cand_cap=0)
+                res += srv.poll(wait_ms=20, cand_cap=1 << 22, with_cands=False)
                 if not th.is_alive():
                     accepted = int((status["s"] == 0).sum())
                     if len(res) >= accepted:
@@ -444,12 +584,15 @@ def served_stream(args, hough, synth, batch, log_fn):
             span = max(r["t_done"] for r in ok) - t_first
             refused = int((status["s"][warm:] != 0).sum())
             votes = sum(int(r["n_votes"]) for r in ok)
+            stored = sum(int(r["n_stored"]) for r in ok)
+            found = sum(min(int(r["n_found"]), 1 << 62) for r in ok)
             out.append({"offered_per_s": rate, "warmup_events": warm, "events": n - warm, "completed": len(ok),
                         "refused": refused, "deadline_misses": int((wait > deadline_s).sum()),
                         "achieved_events_per_s": len(ok) / span, "votes_per_s": votes / span,
                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                         "mean_batch_events": float(np.mean([r["batch_events"] for r in ok])),
-                        "share_3d": float(kind[warm:].mean())})
+                        "share_3d": float(kind[warm:].mean()), "candidates_to_host": stored,
+                        "candidates_found": found})
     finally:
         srv.close()
     return out
@@ -490,12 +633,27 @@ def main():
     def step():
         ctx.event_batch(hit_off, x, y, thr, cand_off=cand_off, cands=cands, n_found=n_found, n_votes=n_votes)
 
+    # Launch shape: the autotuner times every batch shape on these resident
+    # events (whole hough_event_batch calls) and keeps the fastest.
+    shape = None
+    tuned = {"tuned": False}
+    if not args.no_tune:
+        log("autotuning the batch launch shape")
+        rows, threads, _, best_ms = ctx.autotune(1, hit_off, x, y, thr, cand_off=cand_off, cands=cands,
+                                                 n_found=n_found, reps=5)
+        shape = (rows, threads)
+        tuned = {"tuned": True, "tune_best_ms": best_ms}
+    rows, threads, _ = ctx.get_launch(1)
+    tuned.update({"rows": rows, "threads": threads})
+
     # Lanes: lane 0 is ctx on the current stream; further lanes are contexts of
     # their own on streams of their own (default priority), so that one batch's
     # sort and hit preparation overlap another's vote, as in the server.
     lanes = [(ctx, torch.cuda.current_stream(), cands, n_found, n_votes)]
     for _ in range(1, max(1, args.lanes)):
         c2 = hough.HoughContext(grid, device=dev, max_events=n_ev, max_hits=batch.n_hits)
+        if shape:
+            c2.set_launch(1, *shape)
         lanes.append((c2, torch.cuda.Stream(device=dev), torch.empty_like(cands), torch.empty_like(n_found),
                       torch.empty_like(n_votes)))
 
@@ -524,7 +682,7 @@ def main():
     # Dominant kernel: the batch's vote kernel (fused with the peak search for
     # this grid), timed with HIP events the library records around it on the
     # stream it is launched on (timing mode launches the same kernels without
-    # the graph).
+    # the graph), with the (hit, row) pairs it evaluates counted on the device.
     log("timing the vote kernel")
     k_launch = max(3, args.steps)
     ctx.set_timing(True)
@@ -534,29 +692,32 @@ def main():
         v_ms, t_ms = ctx.get_timing()
         vote_list.append(v_ms)
         total_list.append(t_ms)
+    pairs = ctx.get_work()
     ctx.set_timing(False)
     vote_ms = float(np.mean(vote_list[1:]))
     assert int(n_votes.sum().item()) == votes
-    flops = evals * FLOPS_PER_EVAL_2D + int(batch.n_hits) * FLOPS_PER_HIT_2D
-    achieved = flops / (vote_ms * 1e-3)
+    t_vote = vote_ms * 1e-3
+    achieved = pairs * VALU_PER_PAIR_2D / t_vote
     log("throughput probes")
     lds_peak_meas, valu_peak_meas = hough.diag_rates()
-    traffic = counter_traffic()
+    traffic, valu_insts = counter_fields()
+    vote_rate = votes / t_vote
     roofline = {"bound": "alu", "kernel": "vote_kernel (batched, persistent, fused peak search)",
-                "achieved": achieved / 1e12,
-                "peak": PEAK_FP32_OPS / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_OPS,
-                "traffic": traffic,
+                "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "T VALU-ops/s",
+                "frac": achieved / PEAK_VALU_OPS, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "peak_measured": valu_peak_meas / 1e12, "frac_of_measured": achieved / valu_peak_meas,
+                "work_per_launch": {"evaluated_pairs": pairs, "valu_per_pair": VALU_PER_PAIR_2D,
+                                    "pairs_uncut": evals, "evaluated_share": pairs / evals, "votes": votes,
+                                    "hits": int(batch.n_hits)},
                 "launch_ms": vote_ms, "batch_ms_timing_mode": float(np.mean(total_list[1:])),
-                "work_per_launch": {"evaluations": evals, "fp32_ops": flops, "votes": votes,
-                                    "hits": int(batch.n_hits)}}
+                "peak_measured": valu_peak_meas / 1e12, "frac_of_measured": achieved / valu_peak_meas,
+                "lds_atomic": {"achieved": vote_rate / 1e12, "peak_measured": lds_peak_meas / 1e12,
+                               "unit": "T atomics/s", "frac_of_measured": vote_rate / lds_peak_meas}}
     if traffic:
-        roofline["hbm_gbs"] = traffic / (vote_ms * 1e-3) / 1e9
-    vote_rate = votes / (vote_ms * 1e-3)
-    lds = {"achieved": vote_rate / 1e12, "peak": PEAK_LDS_ATOMIC / 1e12, "unit": "T atomics/s",
-           "frac": vote_rate / PEAK_LDS_ATOMIC, "peak_measured": lds_peak_meas / 1e12,
-           "frac_of_measured": vote_rate / lds_peak_meas}
+        roofline["hbm_gbs"] = traffic / t_vote / 1e9
+    if valu_insts:
+        # all VALU work of the launch (loop, staging, peak search), from the counters
+        roofline["valu_issue_frac"] = valu_insts * 64 / t_vote / PEAK_VALU_OPS
 
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
@@ -566,7 +727,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    line_extra = {}
+    line_extra = {"resident": {"events_per_s": events_per_s, "ms_per_step": ms_step,
+                               "note": "hits in HBM before the timed region, candidates left there"}}
+    if args.e2e_steps > 0:
+        e2e = end_to_end(args, hough, torch, dev, batch, grid, thr, cap, shape)
+        e2e["n_found_matches_resident"] = e2e["n_found_per_step"] == found
+        line_extra["with_host_transfers"] = e2e
     if not args.skip_3d:
         line_extra["displaced_3d"] = displaced_3d(hough, torch, dev, synth, log)
     if not args.skip_straight:
@@ -578,9 +744,20 @@ def main():
     served = served_stream(args, hough, synth, batch, log)
     if served is not None:
         line_extra["served"] = served
+        ok = [r for r in served if r["refused"] == 0 and r["achieved_events_per_s"] >= 0.97 * r["offered_per_s"]]
+        if ok:
+            best = max(ok, key=lambda r: r["offered_per_s"])
+            line_extra["served_sustained"] = {"offered_per_s": best["offered_per_s"],
+                                              "achieved_events_per_s": best["achieved_events_per_s"],
+                                              "p99_ms": best["p99_ms"]}
     if not args.skip_per_event:
-        line_extra["per_event_launch"] = per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off,
-                                                   events_per_s)
+        pe = per_event(args, hough, torch, dev, batch, grid, thr, cap, x, y, hit_off, shape)
+        best_res = max(v["resident_events_per_s"] for v in pe.values())
+        best_tr = max(v["transfers_events_per_s"] for v in pe.values())
+        pe["batched_speedup_resident"] = events_per_s / best_res
+        if "with_host_transfers" in line_extra:
+            pe["batched_speedup_with_transfers"] = line_extra["with_host_transfers"]["events_per_s"] / best_tr
+        line_extra["per_event_launch"] = pe
 
     line = {
         "metric": "events/s (batched vote + peaks + sorted candidates, one graph per 256-event batch)",
@@ -597,12 +774,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": wc.name, "events_per_step": n_ev, "hits_per_step": int(batch.n_hits),
                    "grid": [grid.n_d0, grid.n_phi, grid.n_kappa], "acc": grid.acc_type, "threshold": thr,
-                   "lanes": len(lanes)},
+                   "lanes": len(lanes), "launch": tuned},
         "votes_per_s": votes * args.steps / dt,
         "evals_per_s": evals * args.steps / dt,
         "candidates_per_step": found,
         "roofline": roofline,
-        "lds_atomic_roofline": lds,
     }
     line.update(line_extra)
     if not args.no_cpu:

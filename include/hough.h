@@ -206,9 +206,10 @@ hough_status hough_vertices(hough_ctx *ctx, const hough_vertex_grid *vgrid, int3
  *   pairs:     [dev][cap][2] int32 (candidate index, hit index), each pair once,
  *              in no particular order; the first min(*n_pairs, cap) are written.
  *   n_pairs:   [dev] uint64 (8-byte aligned), the full number of pairs.
- * Uses the context's cell map (cells int32): calls on one context must not
- * overlap.  Allocates nothing; asynchronous on stream.  EINVAL: null required
- * pointers, negative sizes, a misaligned n_pairs. */
+ * Uses the context's cell map (cells int32) and hit records: calls on one
+ * context must not overlap.  Allocates nothing; asynchronous on stream.
+ * EINVAL: null required pointers, negative sizes, n_hits above the context's
+ * max_hits, a misaligned n_pairs. */
 hough_status hough_associate(hough_ctx *ctx, const float *x, const float *y, int32_t n_hits,
                              const hough_cand *cands, const int32_t *n_cands, int32_t cands_cap, int32_t min_votes,
                              int32_t *pairs, int64_t cap, uint64_t *n_pairs, void *stream);
@@ -231,6 +232,24 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
                                const float *x, const float *y, int32_t threshold,
                                void *acc, hough_cand *cands, const int64_t *cand_off,
                                int32_t *n_found, uint64_t *n_votes, void *stream);
+
+/* hough_event_batch with the stored lists packed back to back, so that one
+ * copy moves a whole batch's candidates (Section 4's per-event independence
+ * leaves the lists' order to the caller).  Event e's list -- the first
+ * min(n_found[e], cand_off[e+1] - cand_off[e]) candidates of its sorted list,
+ * exactly what hough_event_batch stores at cands[cand_off[e]] -- is written at
+ * cands[cand_start[e]], with cand_start[e] the sum of the earlier events'
+ * stored counts; cand_start[n_events] is the total.  Every list lies inside
+ * [0, cand_off[n_events]), so cands needs no more room than for
+ * hough_event_batch.
+ *   cand_start: [dev][n_events+1] int64 (8-byte aligned), overwritten.
+ * Everything else, including EINVAL, as for hough_event_batch (also for a
+ * null or misaligned cand_start). */
+hough_status hough_event_batch_packed(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off,
+                                      const float *x, const float *y, int32_t threshold,
+                                      void *acc, hough_cand *cands, const int64_t *cand_off,
+                                      int64_t *cand_start, int32_t *n_found, uint64_t *n_votes,
+                                      void *stream);
 
 /* Vote a batch of independent events (the vote half of hough_event_batch,
  * without the peak search and without a captured graph): acc receives every
@@ -321,6 +340,12 @@ hough_status hough_tune_lookup(const char *cache_path, const char *device, const
  * batch). */
 hough_status hough_set_timing(hough_ctx *ctx, int32_t enable);
 hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms);
+/* Work of the last timed batch (measurement only): the (hit, phi0 row) pairs
+ * its vote kernel evaluated -- each hit staged into a tile times the rows of
+ * that tile, halo rows included.  The culling arcs leave out the rows where a
+ * hit cannot vote, so this is less than hits * n_d0 * n_phi.  Waits for the
+ * batch.  EINVAL before any timed batch. */
+hough_status hough_get_work(hough_ctx *ctx, uint64_t *evaluated_pairs);
 
 /* ------------------------------------------------------------------------
  * Served stream (a trigger-farm node; Sections 1-2: events arrive
@@ -344,6 +369,9 @@ typedef struct {
     int32_t queue_limit;             /* pending events before submit refuses (default 4096) */
     int32_t keep_candidates;         /* 0: results carry counts only */
     const char *tune_cache;          /* passed to every lane's context */
+    double batch_timeout_ms;         /* longest wait for a batch to complete (default 10000): past it
+                                        the batch's events are returned with HOUGH_EDEVICE and the
+                                        lane takes new work behind it on its stream */
 } hough_server_opts;
 
 typedef struct {

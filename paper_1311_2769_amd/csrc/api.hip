@@ -44,13 +44,13 @@ struct BatchHeader {
 };
 
 struct GraphKey {
-    const void *x, *y, *acc, *cands, *n_found, *n_votes;
+    const void *x, *y, *acc, *cands, *n_found, *n_votes, *cand_start;
     int32_t threshold;
     int64_t hit_bucket;
     uint32_t key_mask;      // sort-key digits that can differ (sets the sort passes)
     bool operator==(const GraphKey &o) const {
         return x == o.x && y == o.y && acc == o.acc && cands == o.cands && n_found == o.n_found &&
-               n_votes == o.n_votes && threshold == o.threshold && hit_bucket == o.hit_bucket &&
+               n_votes == o.n_votes && cand_start == o.cand_start && threshold == o.threshold && hit_bucket == o.hit_bucket &&
                key_mask == o.key_mask;
     }
 };
@@ -93,6 +93,7 @@ struct hough_ctx {
     uint2 *all_tiles = nullptr;   // one all-tiles entry: culling off
     int32_t *cell_map = nullptr;  // [cells] hit association: 1 + candidate index per cell
     uint32_t *cell_bits = nullptr;  // hit association: bitmap of the cells that hold a candidate
+    int32_t *assoc_hist = nullptr;  // hit association: azimuth bucket counts and offsets
 
     // batch descriptors
     size_t desc_bytes = 0;
@@ -110,6 +111,7 @@ struct hough_ctx {
     // timing mode: batches run without a graph, with events around the vote
     bool timing = false;
     bool timed_once = false;
+    unsigned long long *pairs = nullptr;   // timing mode: (hit, row) pairs the last timed vote evaluated
     hipEvent_t ev_start = nullptr, ev_vote0 = nullptr, ev_vote1 = nullptr, ev_end = nullptr;
 };
 
@@ -133,7 +135,7 @@ void free_ctx(hough_ctx *c) {
     if (c->desc_host)
         (void)hipHostFree(c->desc_host);
     void *dev[] = {c->state, c->stage, c->cnt0, c->hist, c->tmp0, c->acc_ws, c->hits, c->ranges, c->all_tiles,
-                   c->desc_dev, c->work_counter, c->cell_map, c->cell_bits};
+                   c->desc_dev, c->work_counter, c->cell_map, c->cell_bits, c->pairs, c->assoc_hist};
     for (void *p : dev)
         if (p)
             (void)hipFree(p);
@@ -337,8 +339,8 @@ int64_t hit_bucket(int64_t hits) {
 // tile masks, vote (fused with the peak search for 2D int32), sort.  With
 // `timed`, events bracket the whole sequence and the vote kernel.
 hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const float *y, int32_t threshold,
-                         void *acc, hough_cand *cands, int32_t *n_found, uint64_t *n_votes, int64_t bucket,
-                         uint32_t key_mask, bool timed) {
+                         void *acc, hough_cand *cands, int32_t *n_found, uint64_t *n_votes, int64_t *cand_start,
+                         int64_t bucket, uint32_t key_mask, bool timed) {
     DevDesc dd = device_descriptors(ctx);
     const VoteShape &vs = ctx->shape_batch;
     const bool fused = ctx->fused_batch;
@@ -348,6 +350,7 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
     w.out = cands;
     w.n_found = n_found;
     w.n_events_dev = &dd.hdr->n_events;
+    w.cand_start = cand_start;
     auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
     uint32_t *acc_dw = static_cast<uint32_t *>(acc);
     hipError_t ce = hipSuccess;
@@ -360,10 +363,13 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
     if (ce == hipSuccess && timed)
         ce = hipEventRecord(ctx->ev_vote0, cs);
     uint32_t *a = (fused || acc_dw) ? acc_dw : ctx->acc_ws;
+    if (ce == hipSuccess && timed)
+        ce = launch_zero(reinterpret_cast<uint32_t *>(ctx->pairs), 2, cs);
     if (ce == hipSuccess)
         ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, vs, fused), dd.desc,
                                &dd.hdr->n_items, dd.items, ctx->max_items, ctx->work_counter,
-                               ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs);
+                               ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs,
+                               timed ? ctx->pairs : nullptr);
     if (ce == hipSuccess && timed)
         ce = hipEventRecord(ctx->ev_vote1, cs);
     if (ce == hipSuccess && !fused)
@@ -573,6 +579,8 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     }
     e = e ? e : dev_alloc(&c->desc_dev, c->desc_bytes);
     e = e ? e : dev_alloc(&c->work_counter, 1);
+    e = e ? e : dev_alloc(&c->assoc_hist, kAssocBuckets);
+    e = e ? e : dev_alloc(&c->pairs, 1);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&c->desc_host), c->desc_bytes, hipHostMallocDefault);
     if (e == hipSuccess)
@@ -645,6 +653,16 @@ hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms) {
     return HOUGH_OK;
 }
 
+hough_status hough_get_work(hough_ctx *ctx, uint64_t *evaluated_pairs) {
+    if (!ctx || !ctx->timed_once || !evaluated_pairs)
+        return HOUGH_EINVAL;
+    HIP_TRY(hipEventSynchronize(ctx->ev_end));
+    unsigned long long v = 0;
+    HIP_TRY(hipMemcpy(&v, ctx->pairs, sizeof v, hipMemcpyDeviceToHost));
+    *evaluated_pairs = v;
+    return HOUGH_OK;
+}
+
 hough_status hough_get_launch(const hough_ctx *ctx, int32_t which, int32_t *rows, int32_t *threads,
                               int32_t *split) {
     if (!ctx || (which != 0 && which != 1))
@@ -711,8 +729,10 @@ hough_status hough_associate(hough_ctx *ctx, const float *x, const float *y, int
         return HOUGH_EINVAL;
     if (reinterpret_cast<uintptr_t>(n_pairs) & 7u)
         return HOUGH_EINVAL;
+    if (n_hits > ctx->max_hits)
+        return HOUGH_EINVAL;
     HIP_TRY(launch_associate(ctx->g, x, y, n_hits, reinterpret_cast<const Cand *>(cands), n_cands, cands_cap,
-                             min_votes, ctx->cell_map, ctx->cell_bits, pairs, cap,
+                             min_votes, ctx->cell_map, ctx->cell_bits, ctx->hits, ctx->assoc_hist, pairs, cap,
                              reinterpret_cast<unsigned long long *>(n_pairs),
                              static_cast<hipStream_t>(stream)));
     return HOUGH_OK;
@@ -762,10 +782,17 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
     return HOUGH_OK;
 }
 
-hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
-                               const float *y, int32_t threshold, void *acc, hough_cand *cands,
-                               const int64_t *cand_off, int32_t *n_found, uint64_t *n_votes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// hough_event_batch, with packed lists when cand_start is given.
+hough_status event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x, const float *y,
+                         int32_t threshold, void *acc, hough_cand *cands, const int64_t *cand_off,
+                         int64_t *cand_start, int32_t *n_found, uint64_t *n_votes, void *stream) {
     if (!cand_off || !n_found || check_batch(ctx, n_events, hit_off, x, y) != HOUGH_OK)
+        return HOUGH_EINVAL;
+    if (cand_start && (reinterpret_cast<uintptr_t>(cand_start) & 7u))
         return HOUGH_EINVAL;
     if (cand_off[0] != 0)
         return HOUGH_EINVAL;
@@ -785,7 +812,7 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
 
     const int64_t bucket = hit_bucket(hit_off[n_events]);
     const uint32_t key_mask = batch_key_mask(ctx, n_events, hit_off);
-    GraphKey key{x, y, acc, cands, n_found, n_votes, threshold, bucket, key_mask};
+    GraphKey key{x, y, acc, cands, n_found, n_votes, cand_start, threshold, bucket, key_mask};
     hipGraphExec_t exec = nullptr;
     for (auto &ge : ctx->graphs)
         if (ge.key == key)
@@ -794,7 +821,8 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
         // Direct launches with events around the vote (no graph).
         if (changed)
             HIP_TRY(hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, s));
-        HIP_TRY(enqueue_batch(ctx, s, x, y, threshold, acc, cands, n_found, n_votes, bucket, key_mask, true));
+        HIP_TRY(enqueue_batch(ctx, s, x, y, threshold, acc, cands, n_found, n_votes, cand_start, bucket, key_mask,
+                              true));
         ctx->timed_once = true;
         if (changed) {
             HIP_TRY(hipEventRecord(ctx->desc_done, s));
@@ -807,7 +835,8 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, ctx->desc_bytes, hipMemcpyHostToDevice, cs);
         if (ce == hipSuccess)
-            ce = enqueue_batch(ctx, cs, x, y, threshold, acc, cands, n_found, n_votes, bucket, key_mask, false);
+            ce = enqueue_batch(ctx, cs, x, y, threshold, acc, cands, n_found, n_votes, cand_start, bucket, key_mask,
+                               false);
         hipGraph_t graph = nullptr;
         hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (ce != hipSuccess) {
@@ -833,6 +862,27 @@ hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *
     HIP_TRY(hipEventRecord(ctx->desc_done, s));
     ctx->desc_in_flight = true;
     return HOUGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hough_status hough_event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
+                               const float *y, int32_t threshold, void *acc, hough_cand *cands,
+                               const int64_t *cand_off, int32_t *n_found, uint64_t *n_votes, void *stream) {
+    return event_batch(ctx, n_events, hit_off, x, y, threshold, acc, cands, cand_off, nullptr, n_found, n_votes,
+                       stream);
+}
+
+hough_status hough_event_batch_packed(hough_ctx *ctx, int32_t n_events, const int64_t *hit_off, const float *x,
+                                      const float *y, int32_t threshold, void *acc, hough_cand *cands,
+                                      const int64_t *cand_off, int64_t *cand_start, int32_t *n_found,
+                                      uint64_t *n_votes, void *stream) {
+    if (!cand_start)
+        return HOUGH_EINVAL;
+    return event_batch(ctx, n_events, hit_off, x, y, threshold, acc, cands, cand_off, cand_start, n_found, n_votes,
+                       stream);
 }
 
 }  // extern "C"

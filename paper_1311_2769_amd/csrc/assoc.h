@@ -8,11 +8,16 @@ namespace hough {
 // Bitmap dwords per (d0, phi0) row of the association's candidate bitmap.
 int64_t assoc_row_words(int32_t n_kappa);
 
+// Azimuth buckets of the hit order the association works in.
+constexpr int kAssocBuckets = 1024;
+
 // Hit association of one event: map is the context's [cells] int32 cell map,
 // bits its [n_d0 * n_phi * assoc_row_words(n_kappa)] candidate bitmap,
-// n_pairs an 8-byte counter; all are cleared here.
+// sorted room for n_hits hit records, hist kAssocBuckets int32, n_pairs an
+// 8-byte counter; all are cleared or written here.
 hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, int32_t n_hits, const Cand *cands,
                             const int32_t *n_found, int32_t cands_cap, int32_t min_votes, int32_t *map, uint32_t *bits,
-                            int32_t *pairs, int64_t cap, unsigned long long *n_pairs, hipStream_t stream);
+                            float4 *sorted, int32_t *hist, int32_t *pairs, int64_t cap,
+                            unsigned long long *n_pairs, hipStream_t stream);
 
 }  // namespace hough

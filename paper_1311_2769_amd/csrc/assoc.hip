@@ -12,16 +12,21 @@
 // Layout: the context's cell map holds, per cell, 1 + the index of the
 // candidate there (0: none), and a bitmap of the cells that hold one: per
 // (d0, phi0) row, bit kc + 1 of assoc_row_words(n_kappa) dwords (about 1 MB
-// for the displaced grid, so it stays in L2).  One thread takes one (hit, d0
-// slice l) and a run of kAssocRows phi0 rows, and owns the candidates of
-// those cells.  Sliding along the rows it keeps the hit's bins at the nine
-// window positions (slices l - 1 .. l + 1, rows jc - 1 .. jc + 1; three new
-// bins per row in 3D, one in 2D); the candidates the hit reaches are the
-// union of the positions' [b - 1, b + 1], read from two bitmap dwords per
-// position, so each pair is found once without looking at other threads.
-// Each wavefront gathers its pairs in an LDS buffer and reserves room in the
-// output with one atomic per kAssocFlush pairs (a single counter taken per
-// pair by every wavefront serialised the displaced event's 10^8 pairs).
+// for the displaced grid, so it stays in L2).
+//
+// Work: hits are first put in azimuth order (a counting sort into the
+// context's hit records), so that the lanes of a wavefront are hits of
+// similar direction, whose votes fall in similar cells.  A thread then takes
+// one hit and a run of R phi0 rows and walks the d0 slices upwards, keeping
+// the hit's kappa bins of three slices (l - 1, l, l + 1) over rows
+// j0 - 1 .. j0 + R in registers: every bin is computed once per thread, one
+// new slice per step.  For a candidate row (l, jc) the hit's nine window bins
+// b_p give the kappa bins it can reach, the union of [b_p - 1, b_p + 1]: the
+// bitmap is read over [min b_p - 1, max b_p + 1], and each candidate found
+// there is kept when some |b_p - kc| <= 1 -- so each (candidate, hit) pair is
+// found once, by the thread that owns the candidate's row.  Each wavefront
+// gathers its pairs in LDS and reserves room in the output with one atomic
+// per kAssocFlush pairs.
 #pragma clang fp contract(off)
 
 #include "assoc.h"
@@ -29,16 +34,16 @@
 namespace hough {
 namespace {
 
-constexpr int kAssocRows = 64;      // phi0 rows per thread
 constexpr int kAssocThreads = 256;
 constexpr int kAssocWaves = kAssocThreads / 64;
 constexpr int kAssocBuf = 512;      // pairs staged per wavefront
 constexpr int kAssocFlush = kAssocBuf - 64;
+constexpr int kSortBuckets = kAssocBuckets;
 
 }  // namespace
 
 // Bitmap dwords per (d0, phi0) row: bits 0 .. n_kappa + 1, plus one dword so
-// that the pair of dwords holding bits k .. k + 2 never leaves the row.
+// that the pair of dwords holding any 32 consecutive bits never leaves the row.
 int64_t assoc_row_words(int32_t n_kappa) {
     return (static_cast<int64_t>(n_kappa) + 2 + 31) / 32 + 1;
 }
@@ -47,9 +52,8 @@ namespace {
 
 struct AssocArgs {
     GridArgs g;
-    const float *x, *y;
+    const float4 *sorted;          // [n_hits] (x, y, x*x + y*y, hit index) in azimuth order
     int32_t n_hits;
-    int32_t rows_chunks;           // ceil(n_phi / kAssocRows)
     const int32_t *map;            // [cells] 1 + candidate index, 0: none
     const uint32_t *bits;          // [n_d0 * n_phi][row_words] bit kc + 1: a candidate at kc
     int32_t row_words;
@@ -81,6 +85,48 @@ __device__ __forceinline__ int hit_bin(const GridArgs &g, float hx, float hy, fl
     return (kf >= 0.0f && kf < static_cast<float>(g.n_kappa)) ? static_cast<int>(kf) : -1;
 }
 
+// Azimuth bucket of a hit (NaN and the origin go to bucket 0).
+__device__ __forceinline__ int azimuth_bucket(float x, float y) {
+    const float a = atan2f(y, x);                      // [-pi, pi]
+    const float f = (a + 3.14159274f) * (kSortBuckets / 6.28318548f);
+    const int b = f >= 0.0f ? static_cast<int>(f) : 0;  // NaN compares false
+    return min(b, kSortBuckets - 1);
+}
+
+__global__ __launch_bounds__(kAssocThreads) void azimuth_hist_kernel(const float *x, const float *y, int32_t n,
+                                                                      int32_t *hist) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        atomicAdd(&hist[azimuth_bucket(x[i], y[i])], 1);
+}
+
+// Exclusive offsets of the buckets, in place (one workgroup of kSortBuckets threads).
+__global__ __launch_bounds__(kSortBuckets) void azimuth_scan_kernel(int32_t *hist) {
+    __shared__ int32_t s[kSortBuckets];
+    const int t = threadIdx.x;
+    const int v = hist[t];
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kSortBuckets; off <<= 1) {
+        const int w = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += w;
+        __syncthreads();
+    }
+    hist[t] = s[t] - v;
+}
+
+__global__ __launch_bounds__(kAssocThreads) void azimuth_scatter_kernel(const float *x, const float *y, int32_t n,
+                                                                         int32_t *offs, float4 *sorted) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float hx = x[i];
+    const float hy = y[i];
+    const int pos = atomicAdd(&offs[azimuth_bucket(hx, hy)], 1);
+    sorted[pos] = make_float4(hx, hy, hx * hx + hy * hy, __int_as_float(i));
+}
+
 __global__ __launch_bounds__(kAssocThreads) void map_kernel(const Cand *cands, const int32_t *n_found, int32_t cap,
                                                             int32_t min_votes, int64_t cells, int32_t n_kappa,
                                                             int32_t row_words, int32_t *map, uint32_t *bits) {
@@ -96,11 +142,12 @@ __global__ __launch_bounds__(kAssocThreads) void map_kernel(const Cand *cands, c
     }
 }
 
+// R phi0 rows per thread; D3: the grid has a d0 axis (slices l - 1 .. l + 1
+// take part in a window), else one slice.
+template <int R, bool D3>
 __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
     __shared__ int2 staged[kAssocWaves][kAssocBuf];
     const GridArgs &g = a.g;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t per_hit = static_cast<int64_t>(g.n_d0) * a.rows_chunks;
     const int lane = threadIdx.x & 63;
     int2 *buf = staged[threadIdx.x >> 6];
     int fill = 0;                      // wave-uniform
@@ -122,89 +169,111 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
         __builtin_amdgcn_wave_barrier();
         fill = 0;
     };
-    const bool live = t < per_hit * a.n_hits;
-    const int h = live ? static_cast<int>(t / per_hit) : 0;
-    const int rest = live ? static_cast<int>(t - static_cast<int64_t>(h) * per_hit) : 0;
-    const int l = rest / a.rows_chunks;
-    const int j0 = (rest - l * a.rows_chunks) * kAssocRows;
-    const int j1 = live ? min(j0 + kAssocRows, g.n_phi) : j0;
-    const float hx = live ? a.x[h] : 0.0f;
-    const float hy = live ? a.y[h] : 0.0f;
-    const float hr2 = hx * hx + hy * hy;
-    const int nk = g.n_kappa;
     const int np = g.n_phi;
+    const int nk = g.n_kappa;
+    const int n_d0 = g.n_d0;
+    const int j0 = blockIdx.x * R;
+    const int i = blockIdx.y * kAssocThreads + threadIdx.x;
+    const bool live = i < a.n_hits;
+    const float4 rec = live ? a.sorted[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int h = __float_as_int(rec.w);
     const int64_t plane = static_cast<int64_t>(np) * nk;
-    // The thread owns the candidates C = (l, jc, kc) of its slice and rows.
-    // The hit belongs to C when one of its bins b at the window positions
-    // (l + dl, jc + dj) has |b - kc| <= 1, so the kc it reaches from row jc
-    // form the union over the positions of [b - 1, b + 1]: each position adds
-    // the candidates of its three cells that no earlier position covered, and
-    // every pair comes out once.  bins[s][t]: slice l + s - 1, row jc + t - 1
-    // (-1: no vote there, or a slice outside the grid), slid along the rows.
-    int bins[3][3];
-    auto bin_at = [&](int s, int row) -> int {
-        const int ll = l + s - 1;
-        if (!live || ll < 0 || ll >= g.n_d0)
-            return -1;
-        row += row < 0 ? np : 0;
-        row -= row >= np ? np : 0;
-        return hit_bin(g, hx, hy, hr2, ll, row);
+
+    // bins of slice ll over ring rows j0 - 1 .. j0 + R (-1: no vote, or a
+    // slice outside the grid)
+    auto fill_slice = [&](int ll, int (&B)[R + 2]) {
+        const bool ok = live && ll >= 0 && ll < n_d0;
+#pragma unroll
+        for (int k = 0; k < R + 2; ++k) {
+            int row = j0 - 1 + k;
+            row += row < 0 ? np : 0;
+            row -= row >= np ? np : 0;
+            B[k] = ok ? hit_bin(g, rec.x, rec.y, rec.z, ll, row) : -1;
+        }
     };
+    int B0[R + 2], B1[R + 2], B2[R + 2];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        bins[s][0] = bin_at(s, j0 - 1);
-        bins[s][1] = bin_at(s, j0);
-    }
-    const uint32_t *brow0 = a.bits + static_cast<int64_t>(l) * np * a.row_words;
-    // every lane runs the same number of rows, so the wavefront stays together
-    for (int r = 0; r < kAssocRows; ++r) {
-        const int jc = j0 + r;
-        const bool own = jc < j1;
+    for (int k = 0; k < R + 2; ++k)
+        B0[k] = -1;
+    fill_slice(0, B1);
+    if constexpr (D3)
+        fill_slice(1, B2);
+    else
 #pragma unroll
-        for (int s = 0; s < 3; ++s)
-            bins[s][2] = own ? bin_at(s, jc + 1) : -1;
-        const uint32_t *brow = brow0 + static_cast<int64_t>(own ? jc : 0) * a.row_words;
+        for (int k = 0; k < R + 2; ++k)
+            B2[k] = -1;
+
+    for (int l = 0; l < n_d0; ++l) {
+        // column extremes over the three slices: the largest bin (invalid -1
+        // never wins) and, as unsigned, the smallest valid one (-1 is the
+        // largest unsigned value)
+        int cmax[R + 2];
+        uint32_t cmin[R + 2];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) {
-            const int kp = bins[p / 3][p % 3];
-            uint32_t pend = 0u;
-            if (own && kp >= 0) {
-                // bits kc + 1 for kc = kp - 1 .. kp + 1 of the row (l, jc)
-                const uint32_t *w = brow + (kp >> 5);
-                const uint64_t two = static_cast<uint64_t>(w[0]) | (static_cast<uint64_t>(w[1]) << 32);
-                pend = static_cast<uint32_t>(two >> (kp & 31)) & 7u;
-                // minus the cells an earlier position already reached
-                if (pend != 0u) {
+        for (int k = 0; k < R + 2; ++k) {
+            cmax[k] = max(max(B0[k], B1[k]), B2[k]);
+            cmin[k] = min(min(static_cast<uint32_t>(B0[k]), static_cast<uint32_t>(B1[k])),
+                          static_cast<uint32_t>(B2[k]));
+        }
+        const uint32_t *brow0 = a.bits + static_cast<int64_t>(l) * np * a.row_words;
 #pragma unroll
-                    for (int q = 0; q < p; ++q) {
-                        const int kq = bins[q / 3][q % 3];
-                        const int o = kq - kp;         // its cells are kp + o - 1 .. kp + o + 1
-                        if (kq >= 0 && o >= -2 && o <= 2)
-                            pend &= ~(o >= 0 ? (7u << o) : (7u >> -o));
+        for (int r = 0; r < R; ++r) {
+            const int jc = j0 + r;
+            const int vmax = max(max(cmax[r], cmax[r + 1]), cmax[r + 2]);
+            const uint32_t vmin_u = min(min(cmin[r], cmin[r + 1]), cmin[r + 2]);
+            const bool any = jc < np && vmax >= 0;
+            // candidates of row (l, jc) in [vmin - 1, vmax + 1], 32 bins at a time
+            const int k_lo = any ? max(static_cast<int>(vmin_u) - 1, 0) : 0;
+            const int k_hi = any ? min(vmax + 1, nk - 1) : -1;
+            const uint32_t *brow = brow0 + static_cast<int64_t>(any ? jc : 0) * a.row_words;
+            for (int base = k_lo; __ballot(base <= k_hi); base += 32) {
+                uint32_t pend = 0u;
+                if (base <= k_hi) {
+                    // bits kc + 1 for kc = base .. base + 31
+                    const int bit = base + 1;
+                    const uint32_t *w = brow + (bit >> 5);
+                    const uint64_t two = static_cast<uint64_t>(w[0]) | (static_cast<uint64_t>(w[1]) << 32);
+                    pend = static_cast<uint32_t>(two >> (bit & 31));
+                    const int width = k_hi - base + 1;
+                    if (width < 32)
+                        pend &= (1u << width) - 1u;
+                }
+                while (__ballot(pend != 0u)) {
+                    bool emit = false;
+                    int cand = 0;
+                    if (pend != 0u) {
+                        const int kc = base + (__ffs(pend) - 1);
+                        pend &= pend - 1u;
+                        // kept when a window bin is within one of kc
+                        bool near = false;
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) {
+                            near |= B0[r + t] >= 0 && abs(B0[r + t] - kc) <= 1;
+                            near |= B1[r + t] >= 0 && abs(B1[r + t] - kc) <= 1;
+                            near |= B2[r + t] >= 0 && abs(B2[r + t] - kc) <= 1;
+                        }
+                        if (near) {
+                            cand = a.map[l * plane + static_cast<int64_t>(jc) * nk + kc] - 1;
+                            emit = cand >= 0;
+                        }
                     }
+                    const uint64_t m = __ballot(emit);
+                    if (emit)
+                        buf[fill + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cand, h);
+                    fill += __popcll(m);
+                    if (fill > kAssocFlush)
+                        flush();
                 }
-            }
-            while (__ballot(pend != 0u)) {
-                bool emit = false;
-                int cand = 0;
-                if (pend != 0u) {
-                    const int kc = kp - 1 + (__ffs(pend) - 1);
-                    pend &= pend - 1u;
-                    cand = a.map[l * plane + static_cast<int64_t>(jc) * nk + kc] - 1;
-                    emit = cand >= 0;
-                }
-                const uint64_t m = __ballot(emit);
-                if (emit)
-                    buf[fill + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cand, h);
-                fill += __popcll(m);
-                if (fill > kAssocFlush)
-                    flush();
             }
         }
+        if constexpr (D3) {
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            bins[s][0] = bins[s][1];
-            bins[s][1] = bins[s][2];
+            for (int k = 0; k < R + 2; ++k) {
+                B0[k] = B1[k];
+                B1[k] = B2[k];
+            }
+            if (l + 1 < n_d0)
+                fill_slice(l + 2, B2);
         }
     }
     if (fill > 0)
@@ -215,7 +284,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
 
 hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, int32_t n_hits, const Cand *cands,
                             const int32_t *n_found, int32_t cands_cap, int32_t min_votes, int32_t *map, uint32_t *bits,
-                            int32_t *pairs, int64_t cap, unsigned long long *n_pairs, hipStream_t stream) {
+                            float4 *sorted, int32_t *hist, int32_t *pairs, int64_t cap,
+                            unsigned long long *n_pairs, hipStream_t stream) {
     const int64_t row_words = assoc_row_words(g.n_kappa);
     hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(map), g.cells, stream);
     if (e != hipSuccess)
@@ -237,23 +307,34 @@ hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, i
     }
     if (n_hits == 0)
         return hipSuccess;
+    // hits in azimuth order
+    e = launch_zero(reinterpret_cast<uint32_t *>(hist), kSortBuckets, stream);
+    if (e != hipSuccess)
+        return e;
+    const unsigned hb = static_cast<unsigned>((n_hits + kAssocThreads - 1) / kAssocThreads);
+    hipLaunchKernelGGL(azimuth_hist_kernel, dim3(hb), dim3(kAssocThreads), 0, stream, x, y, n_hits, hist);
+    hipLaunchKernelGGL(azimuth_scan_kernel, dim3(1), dim3(kSortBuckets), 0, stream, hist);
+    hipLaunchKernelGGL(azimuth_scatter_kernel, dim3(hb), dim3(kAssocThreads), 0, stream, x, y, n_hits, hist, sorted);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
     AssocArgs a{};
     a.g = g;
-    a.x = x;
-    a.y = y;
+    a.sorted = sorted;
     a.n_hits = n_hits;
-    a.rows_chunks = (g.n_phi + kAssocRows - 1) / kAssocRows;
     a.map = map;
     a.bits = bits;
     a.row_words = static_cast<int32_t>(row_words);
     a.pairs = pairs;
     a.cap = cap;
     a.n_pairs = n_pairs;
-    const int64_t threads = static_cast<int64_t>(n_hits) * g.n_d0 * a.rows_chunks;
-    const int64_t blocks = (threads + kAssocThreads - 1) / kAssocThreads;
-    if (blocks > 0x7fffffffLL)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(assoc_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kAssocThreads), 0, stream, a);
+    const bool d3 = g.n_d0 > 1;
+    const int R = d3 ? 8 : 16;
+    const dim3 grid(static_cast<unsigned>((g.n_phi + R - 1) / R), hb);
+    if (d3)
+        hipLaunchKernelGGL((assoc_kernel<8, true>), grid, dim3(kAssocThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((assoc_kernel<16, false>), grid, dim3(kAssocThreads), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -99,6 +99,8 @@ struct SortWork {
     int32_t *n_found;         // caller's [events]
     uint32_t key_mask;        // sort-key bits that can differ within an event (sets the passes)
     const int32_t *n_events_dev;  // batch: live event count on the device, or nullptr
+    int64_t *cand_start;      // batch, packed lists: [events+1] list offsets written after the
+                              // first scan (each list follows the previous one), or nullptr
 };
 
 // Hit inputs of a vote launch, as written by hit_prep: one record per hit
@@ -186,8 +188,11 @@ hipError_t launch_table_check(const float *cos_phi, const float *sin_phi, int32_
                               hipStream_t stream);
 
 // One event: hits [0, n_hits).
+// pairs (measurement only): when given, the launch adds the (hit, phi0 row)
+// pairs it evaluates -- staged hits times tile rows -- to *pairs.
 hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,
-                              int32_t n_hits, uint32_t *acc, unsigned long long *n_votes, hipStream_t stream);
+                              int32_t n_hits, uint32_t *acc, unsigned long long *n_votes, hipStream_t stream,
+                              unsigned long long *pairs = nullptr);
 // Many events: tile work items over events described by desc; the live item
 // count is read on the device.  With a work counter (reset beforehand) the
 // launch is persistent: persistent_groups workgroups pull items in order.
@@ -197,7 +202,7 @@ hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const Vote
                              const EventDesc *desc, const int32_t *n_items_dev, const WorkItem *items,
                              int32_t max_items, int32_t *work_counter, int32_t persistent_groups, uint32_t *acc,
                              unsigned long long *n_votes, const SortWork *w, int32_t threshold,
-                             hipStream_t stream);
+                             hipStream_t stream, unsigned long long *pairs = nullptr);
 
 int32_t peak_blocks_per_event(const GridArgs &g);
 int32_t peak_block_cap(const GridArgs &g);

@@ -469,6 +469,41 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(SortWork w, int pass
     }
 }
 
+// Packed lists (batch): event e's stored list, min(n_found, its capacity)
+// candidates, starts where event e - 1's ends, so a batch's lists fill
+// out[0, cand_start[n_events]) and one copy moves them all.  One workgroup,
+// after the pass-0 scan has fixed every n_found and before any scatter writes
+// the output; each thread sums a run of consecutive events, and a scan over
+// the threads turns the sums into offsets.
+constexpr int kPackThreads = 1024;
+
+__global__ __launch_bounds__(kPackThreads) void pack_kernel(SortWork w, int32_t max_events) {
+    __shared__ int64_t part[kPackThreads];
+    const int n = w.n_events_dev ? min(*w.n_events_dev, max_events) : max_events;
+    const int t = threadIdx.x;
+    const int per = (n + kPackThreads - 1) / kPackThreads;
+    const int begin = min(n, t * per);
+    const int end = min(n, begin + per);
+    int64_t sum = 0;
+    for (int e = begin; e < end; ++e)
+        sum += min(w.state[e].n_found, w.desc[e].cand_cap);
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < kPackThreads; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int e = begin; e < end; ++e) {
+        w.cand_start[e] = run;
+        run += min(w.state[e].n_found, w.desc[e].cand_cap);
+    }
+    if (t == kPackThreads - 1)
+        w.cand_start[n] = part[t];
+}
+
 // Stable scatter of one chunk by the digit of this pass.  A round takes up to
 // 2,048 consecutive elements, split into one run per wavefront (a
 // multiple of 64, at most 64 * kSortPer, shorter when the list is short so
@@ -497,7 +532,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(SortWork w, int p
     int64_t limit;
     if (last) {
         if (w.desc) {
-            dst = reinterpret_cast<Cand *>(w.out) + w.desc[e].cand_begin;
+            dst = reinterpret_cast<Cand *>(w.out) + (w.cand_start ? w.cand_start[e] : w.desc[e].cand_begin);
             limit = w.desc[e].cand_cap;
         } else {
             dst = reinterpret_cast<Cand *>(w.out);
@@ -667,6 +702,8 @@ hipError_t launch_sort(const SortWork &w, int32_t n_events, hipStream_t stream) 
         if (pass > 0)
             hipLaunchKernelGGL(hist_kernel, dim3(later_chunks, n_events), dim3(kSortThreads), 0, stream, w, pass);
         hipLaunchKernelGGL(scan_kernel, dim3(n_events), dim3(kScanThreads), 0, stream, w, pass);
+        if (pass == 0 && w.cand_start && w.desc)
+            hipLaunchKernelGGL(pack_kernel, dim3(1), dim3(kPackThreads), 0, stream, w, n_events);
         const unsigned chunks = pass == 0 ? first_chunks : later_chunks;
         hipLaunchKernelGGL(scatter_kernel, dim3(chunks, n_events), dim3(kSortThreads), 0, stream, w, pass);
         hipError_t e = hipGetLastError();

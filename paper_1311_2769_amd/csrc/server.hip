@@ -36,6 +36,7 @@
 #include <thread>
 #include <vector>
 
+#include "dispatch.h"
 #include "hough.h"
 #include "hough_impl.h"
 
@@ -67,6 +68,7 @@ struct Lane {
     int64_t cap = 0;                 // candidate capacity per event
     float *x_d = nullptr, *y_d = nullptr;
     hough_cand *c_d = nullptr;
+    int64_t *start_d = nullptr;      // packed list offsets of the batch in flight
     int32_t *nf_d = nullptr;
     uint64_t *nv_d = nullptr;
     float *x_h = nullptr, *y_h = nullptr;     // pinned
@@ -93,6 +95,7 @@ struct hough_server {
     double deadline_s = 0.002;
     int32_t queue_limit = 4096;
     bool keep_candidates = true;
+    double wait_limit_s = 10.0;             // longest wait for a batch before it fails
     std::vector<std::unique_ptr<Lane>> lanes;
 
     std::mutex mu;
@@ -120,6 +123,36 @@ void set_error(hough_server *s, const char *what, hipError_t e) {
         s->error = std::string(what) + ": " + hipGetErrorString(e);
 }
 
+// Bounded completion waits: poll the event (or stream) until it completes, a
+// HIP error comes back, or limit_s seconds pass -- then an error, which
+// fails the batch's events with HOUGH_EDEVICE instead of blocking the lane
+// forever (hipErrorLaunchTimeOut stands for that limit).  Sleeps between
+// polls grow from 10 us to 50 us, which bounds the delay a poll adds to an
+// event's latency.
+template <typename Query>
+hipError_t wait_bounded(Query query, double limit_s) {
+    const auto t_end = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                          std::chrono::duration<double>(limit_s));
+    auto nap = std::chrono::microseconds(10);
+    while (true) {
+        const hipError_t q = query();
+        if (q != hipErrorNotReady)
+            return q;
+        if (Clock::now() >= t_end)
+            return hipErrorLaunchTimeOut;   // reported as the batch time limit
+        std::this_thread::sleep_for(nap);
+        nap = std::min(nap * 2, std::chrono::microseconds(50));
+    }
+}
+
+hipError_t wait_event(hipEvent_t ev, double limit_s) {
+    return wait_bounded([&] { return hipEventQuery(ev); }, limit_s);
+}
+
+hipError_t wait_stream(hipStream_t st, double limit_s) {
+    return wait_bounded([&] { return hipStreamQuery(st); }, limit_s);
+}
+
 template <typename T>
 hipError_t dmalloc(T **p, size_t n) {
     return hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(T));
@@ -134,7 +167,7 @@ void free_lane(Lane *l) {
     if (l->ctx)
         hough_ctx_destroy(l->ctx);
     for (void *p : {static_cast<void *>(l->x_d), static_cast<void *>(l->y_d), static_cast<void *>(l->c_d),
-                    static_cast<void *>(l->nf_d), static_cast<void *>(l->nv_d)})
+                    static_cast<void *>(l->start_d), static_cast<void *>(l->nf_d), static_cast<void *>(l->nv_d)})
         if (p)
             (void)hipFree(p);
     for (void *p : {static_cast<void *>(l->x_h), static_cast<void *>(l->y_h), static_cast<void *>(l->c_h),
@@ -179,9 +212,10 @@ hipError_t launch_batch(hough_server *s, Lane *l) {
     if (e != hipSuccess)
         return e;
     l->t_launch = s->now();
-    const hough_status st = hough_event_batch(l->ctx, n, l->hit_off.data(), l->x_d, l->y_d,
-                                              s->thresholds[l->grid], nullptr, l->c_d, l->cand_off.data(),
-                                              l->nf_d, l->nv_d, l->stream);
+    // packed lists: the completion thread copies a whole batch's candidates at once
+    const hough_status st = hough_event_batch_packed(l->ctx, n, l->hit_off.data(), l->x_d, l->y_d,
+                                                     s->thresholds[l->grid], nullptr, l->c_d, l->cand_off.data(),
+                                                     l->start_d, l->nf_d, l->nv_d, l->stream);
     if (st != HOUGH_OK)
         return hipErrorLaunchFailure;
     e = hipMemcpyAsync(l->nf_h, l->nf_d, n * sizeof(int32_t), hipMemcpyDeviceToHost, l->stream);
@@ -204,45 +238,32 @@ void dispatcher_main(hough_server *s) {
             s->cv_lane.notify_all();
             break;
         }
-        double wake = -1.0;          // earliest deadline to wake for, if any
+        // the policy (dispatch.h) over the current queues and lanes
+        std::vector<serve::LaneState> view(s->lanes.size());
+        for (size_t k = 0; k < s->lanes.size(); ++k) {
+            const Lane &l = *s->lanes[k];
+            view[k] = serve::LaneState{l.grid, l.busy, l.max_events, l.max_hits};
+        }
+        std::vector<int64_t> qlen(static_cast<size_t>(n_grids));
+        for (int g = 0; g < n_grids; ++g)
+            qlen[g] = static_cast<int64_t>(s->pending[g].size());
+        const serve::Choice ch = serve::choose(
+            n_grids, qlen.data(), s->pending_hits.data(),
+            [&](int g, int64_t i) { return static_cast<int64_t>(s->pending[g][i]->x.size()); },
+            [&](int g, int64_t i) { return s->pending[g][i]->t_submit; }, view.data(),
+            static_cast<int>(view.size()), s->now(), s->deadline_s, s->stop);
+        const double wake = ch.wake;
         Lane *pick = nullptr;
-        for (int g = 0; g < n_grids && !pick; ++g) {
-            auto &q = s->pending[g];
-            if (q.empty())
-                continue;
-            Lane *free_lane = nullptr;
-            bool any_busy = false;
-            for (auto &lp : s->lanes) {
-                if (lp->grid != g)
-                    continue;
-                if (lp->busy)
-                    any_busy = true;
-                else if (!free_lane)
-                    free_lane = lp.get();
-            }
-            if (!free_lane)
-                continue;
-            const double age = s->now() - q.front()->t_submit;
-            const bool go = !any_busy || s->stop || age >= s->deadline_s ||
-                            2 * s->pending_hits[g] >= free_lane->max_hits ||
-                            static_cast<int64_t>(q.size()) >= free_lane->max_events;
-            if (!go) {
-                const double at = q.front()->t_submit + s->deadline_s;
-                wake = wake < 0 ? at : std::min(wake, at);
-                continue;
-            }
-            // admit events in arrival order while they fit the lane's slots and pool
-            int64_t hits = 0;
-            while (!q.empty() && static_cast<int32_t>(free_lane->batch.size()) < free_lane->max_events &&
-                   hits + static_cast<int64_t>(q.front()->x.size()) <= free_lane->max_hits) {
-                hits += static_cast<int64_t>(q.front()->x.size());
-                s->pending_hits[g] -= static_cast<int64_t>(q.front()->x.size());
-                free_lane->batch.push_back(std::move(q.front()));
+        if (ch.lane >= 0) {
+            pick = s->lanes[ch.lane].get();
+            auto &q = s->pending[ch.grid];
+            for (int32_t k = 0; k < ch.take; ++k) {
+                s->pending_hits[ch.grid] -= static_cast<int64_t>(q.front()->x.size());
+                pick->batch.push_back(std::move(q.front()));
                 q.pop_front();
                 --s->n_pending;
             }
-            free_lane->busy = true;
-            pick = free_lane;
+            pick->busy = true;
         }
         if (!pick) {
             if (wake >= 0) {
@@ -275,16 +296,16 @@ void lane_main(hough_server *s, Lane *l) {
         const int32_t n = static_cast<int32_t>(l->batch.size());
         hipError_t e = l->launch_err;
         if (e == hipSuccess)
-            e = hipEventSynchronize(l->done);
-        // exactly n_found (at most the slice capacity) candidates per event
-        for (int32_t k = 0; k < n && e == hipSuccess && s->keep_candidates; ++k) {
-            const int64_t m = std::min<int64_t>(std::max(l->nf_h[k], 0), l->cap);
-            if (m > 0)
-                e = hipMemcpyAsync(l->c_h + l->cand_off[k], l->c_d + l->cand_off[k], m * sizeof(hough_cand),
-                                   hipMemcpyDeviceToHost, l->stream);
-        }
+            e = wait_event(l->done, s->wait_limit_s);
+        // The lists are packed: event k's min(n_found, cap) candidates follow
+        // event k-1's, so one copy brings the whole batch's lists back.
+        std::vector<int64_t> start(static_cast<size_t>(n) + 1, 0);
+        for (int32_t k = 0; k < n && e == hipSuccess; ++k)
+            start[k + 1] = start[k] + std::min<int64_t>(std::max(l->nf_h[k], 0), l->cap);
+        if (e == hipSuccess && s->keep_candidates && start[n] > 0)
+            e = hipMemcpyAsync(l->c_h, l->c_d, start[n] * sizeof(hough_cand), hipMemcpyDeviceToHost, l->stream);
         if (e == hipSuccess)
-            e = hipStreamSynchronize(l->stream);
+            e = wait_stream(l->stream, s->wait_limit_s);
         const double t_done = s->now();
         std::vector<Result> out(n);
         for (int32_t k = 0; k < n; ++k) {
@@ -300,9 +321,8 @@ void lane_main(hough_server *s, Lane *l) {
             r.info.t_submit = ev.t_submit;
             r.info.t_launch = l->t_launch;
             r.info.t_done = t_done;
-            const int64_t m = (e == hipSuccess && s->keep_candidates)
-                                  ? std::min<int64_t>(std::max(l->nf_h[k], 0), l->cap) : 0;
-            r.cands.assign(l->c_h + l->cand_off[k], l->c_h + l->cand_off[k] + m);
+            const int64_t m = (e == hipSuccess && s->keep_candidates) ? start[k + 1] - start[k] : 0;
+            r.cands.assign(l->c_h + start[k], l->c_h + start[k] + m);
         }
         if (e != hipSuccess)
             set_error(s, "server batch completion", e);
@@ -338,6 +358,9 @@ hough_status hough_server_create(hough_server **out, const hough_server_opts *o)
     s->deadline_s = (o->deadline_ms > 0 ? o->deadline_ms : 2.0) * 1e-3;
     s->queue_limit = o->queue_limit > 0 ? o->queue_limit : 4096;
     s->keep_candidates = o->keep_candidates != 0;
+    if (o->batch_timeout_ms < 0)
+        return (delete s, HOUGH_EINVAL);
+    s->wait_limit_s = (o->batch_timeout_ms > 0 ? o->batch_timeout_ms : 10000.0) * 1e-3;
     s->pending.resize(o->n_grids);
     s->pending_hits.assign(o->n_grids, 0);
     hough_status st = HOUGH_OK;
@@ -369,6 +392,7 @@ hough_status hough_server_create(hough_server **out, const hough_server_opts *o)
             he = he ? he : dmalloc(&l->x_d, H);
             he = he ? he : dmalloc(&l->y_d, H);
             he = he ? he : dmalloc(&l->c_d, static_cast<size_t>(E) * cap);
+            he = he ? he : dmalloc(&l->start_d, static_cast<size_t>(E) + 1);
             he = he ? he : dmalloc(&l->nf_d, E);
             he = he ? he : dmalloc(&l->nv_d, E);
             he = he ? he : hmalloc(&l->x_h, H);
@@ -427,7 +451,8 @@ hough_status hough_server_submit(hough_server *s, int64_t tag, int32_t grid, con
     for (auto &l : s->lanes)
         if (l->grid == grid)
             pool = l->max_hits;
-    if (n_hits > pool || (s->grids[grid].acc_type == HOUGH_ACC_U16 && n_hits > 65535))
+    const bool u16 = s->grids[grid].acc_type == HOUGH_ACC_U16;
+    if (serve::admit(n_hits, pool, u16, 0, 1) == serve::Admit::never_fits)
         return HOUGH_EINVAL;         // can never be admitted
     auto ev = std::make_unique<Event>();
     ev->tag = tag;
@@ -438,7 +463,7 @@ hough_status hough_server_submit(hough_server *s, int64_t tag, int32_t grid, con
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop)
             return HOUGH_EINVAL;
-        if (s->n_pending >= s->queue_limit) {
+        if (serve::admit(n_hits, pool, u16, s->n_pending, s->queue_limit) == serve::Admit::queue_full) {
             ++s->refused;
             return HOUGH_EBUSY;
         }

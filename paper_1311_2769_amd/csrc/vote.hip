@@ -94,6 +94,7 @@ struct VoteArgs {
     unsigned long long *n_votes;
     SortWork w;                 // fused: staging lists
     int32_t threshold;          // fused
+    unsigned long long *pairs;  // measurement: (hit, row) pairs evaluated, added per tile, or nullptr
 };
 
 constexpr int kHitBlock = 512;   // hit records examined per block
@@ -409,6 +410,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     if (h_begin < h_end)
         fetch(h_begin);
     int parity = 0;
+    int kept_here = 0;                           // hits this wavefront staged (pair counting only)
     int carry = 0;                               // fast hits carried into this block
     float4 carry_v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // this thread's carried hit (tid < carry)
     for (int64_t b0 = h_begin; b0 < h_end; b0 += kHitBlock, parity ^= 1) {
@@ -424,6 +426,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             const bool fast = D3 ? (pr[q].y & kFastDiv) != 0u : ph[q].w != 0.0f;
             const uint64_t mf = __ballot(keep && fast);
             const uint64_t ms = __ballot(keep && !fast);
+            kept_here += __popcll(mf | ms);
             int bf = 0, bs = 0;
             if (lane == 0 && mf)
                 bf = atomicAdd(&ts.n_kept[parity][0], __popcll(mf));
@@ -456,6 +459,10 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         carry = carry_next;
     }
     lds_barrier();
+    // Every staged hit is evaluated once per row of the tile (halo rows
+    // included); rows past the grid take NaN constants and are not counted.
+    if (a.pairs && lane == 0 && kept_here > 0)
+        atomicAdd(a.pairs, static_cast<unsigned long long>(kept_here) * static_cast<unsigned long long>(len));
 
     const int rd = g.row_dwords;
     unsigned long long votes = 0;
@@ -1213,8 +1220,10 @@ hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream) {
 }
 
 hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,
-                              int32_t n_hits, uint32_t *acc, unsigned long long *n_votes, hipStream_t stream) {
+                              int32_t n_hits, uint32_t *acc, unsigned long long *n_votes, hipStream_t stream,
+                              unsigned long long *pairs) {
     VoteArgs a{};
+    a.pairs = pairs;
     a.g = g;
     fill_inputs(a, in);
     a.n_hits = n_hits;
@@ -1235,8 +1244,9 @@ hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const Vote
                              const EventDesc *desc, const int32_t *n_items_dev, const WorkItem *items,
                              int32_t max_items, int32_t *work_counter, int32_t persistent_groups, uint32_t *acc,
                              unsigned long long *n_votes, const SortWork *w, int32_t threshold,
-                             hipStream_t stream) {
+                             hipStream_t stream, unsigned long long *pairs) {
     VoteArgs a{};
+    a.pairs = pairs;
     a.g = g;
     fill_inputs(a, in);
     a.split = 1;

@@ -24,8 +24,9 @@ ACC_I32, ACC_U16 = 0, 1
 
 SYMBOLS = (
     "hough_ctx_create", "hough_ctx_destroy", "hough_vote", "hough_peaks", "hough_event_batch",
+    "hough_event_batch_packed",
     "hough_vote_batch", "hough_vertices", "hough_associate", "hough_event_noalloc",
-    "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing",
+    "hough_set_launch", "hough_get_launch", "hough_set_timing", "hough_get_timing", "hough_get_work",
     "hough_autotune", "hough_tune_lookup",
     "hough_server_create", "hough_server_destroy", "hough_server_clock", "hough_server_submit",
     "hough_server_replay", "hough_server_poll", "hough_server_stats",
@@ -64,7 +65,7 @@ class _ServerOpts(ctypes.Structure):
                 ("lanes", ctypes.c_int32), ("batch_events", ctypes.c_void_p), ("batch_hits", ctypes.c_void_p),
                 ("event_candidates", ctypes.c_void_p), ("deadline_ms", ctypes.c_double),
                 ("queue_limit", ctypes.c_int32), ("keep_candidates", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("batch_timeout_ms", ctypes.c_double)]
 
 
 class _Served(ctypes.Structure):
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.hough_event_batch.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     lib.hough_event_noalloc.restype = i32
     lib.hough_event_noalloc.argtypes = [ctypes.POINTER(_Grid), vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]
+    lib.hough_event_batch_packed.restype = i32
+    lib.hough_event_batch_packed.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.hough_vote_batch.restype = i32
     lib.hough_vote_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.hough_set_launch.restype = i32
@@ -112,6 +115,8 @@ def load(path: str = LIB_PATH):
     lib.hough_set_timing.argtypes = [vp, i32]
     lib.hough_get_timing.restype = i32
     lib.hough_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+    lib.hough_get_work.restype = i32
+    lib.hough_get_work.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.hough_autotune.restype = i32
     lib.hough_autotune.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp, i32, ctypes.c_char_p, vp,
                                    ctypes.POINTER(ctypes.c_float)]
@@ -404,6 +409,30 @@ class HoughContext:
             _stream_handle(stream)), "hough_event_batch")
         return cands, cand_off, n_found, n_votes
 
+    def event_batch_packed(self, hit_off, x, y, threshold, cand_off=None, cands=None, cand_start=None,
+                           n_found=None, n_votes=None, acc=None, want_votes=True, stream=None):
+        """hough_event_batch_packed: as event_batch, with event e's stored list at
+        cands[cand_start[e]] and the lists back to back.  Returns (cands, cand_start,
+        n_found, n_votes); cand_start[-1] is the total stored."""
+        hit_off = np.ascontiguousarray(hit_off, dtype=np.int64)
+        n_events = hit_off.shape[0] - 1
+        if cand_off is None:
+            cand_off = np.arange(n_events + 1, dtype=np.int64) * self.spec.max_candidates()
+        cand_off = np.ascontiguousarray(cand_off, dtype=np.int64)
+        if cands is None:
+            cands = torch.empty((max(int(cand_off[-1]), 1), 2), dtype=torch.int32, device=self.device)
+        if cand_start is None:
+            cand_start = torch.empty(n_events + 1, dtype=torch.int64, device=self.device)
+        if n_found is None:
+            n_found = torch.empty(n_events, dtype=torch.int32, device=self.device)
+        if n_votes is None and want_votes:
+            n_votes = torch.empty(n_events, dtype=torch.int64, device=self.device)
+        _check(self.lib.hough_event_batch_packed(
+            self.handle, n_events, hit_off.ctypes.data_as(ctypes.c_void_p), _ptr(x), _ptr(y), int(threshold),
+            _ptr(acc), _ptr(cands), cand_off.ctypes.data_as(ctypes.c_void_p), _ptr(cand_start), _ptr(n_found),
+            _ptr(n_votes), _stream_handle(stream)), "hough_event_batch_packed")
+        return cands, cand_start, n_found, n_votes
+
     def vote_batch(self, hit_off, x, y, acc=None, n_votes=None, stream=None):
         hit_off = np.ascontiguousarray(hit_off, dtype=np.int64)
         n_events = hit_off.shape[0] - 1
@@ -455,6 +484,12 @@ class HoughContext:
         v, t = ctypes.c_float(), ctypes.c_float()
         _check(self.lib.hough_get_timing(self.handle, ctypes.byref(v), ctypes.byref(t)), "hough_get_timing")
         return v.value, t.value
+
+    def get_work(self):
+        """(hit, phi0 row) pairs the last timed batch's vote evaluated (waits for it)."""
+        v = ctypes.c_uint64()
+        _check(self.lib.hough_get_work(self.handle, ctypes.byref(v)), "hough_get_work")
+        return int(v.value)
 
     def get_launch(self, which):
         vals = [ctypes.c_int32() for _ in range(3)]
@@ -539,7 +574,7 @@ class Server:
 
     def __init__(self, grids, thresholds, *, device="cuda", lanes=2, batch_events=None, batch_hits=None,
                  event_candidates=None, deadline_ms=2.0, queue_limit=4096, keep_candidates=True,
-                 tune_cache=None):
+                 tune_cache=None, batch_timeout_ms=0.0):
         self.lib = load()
         self.device = torch.device(device)
         self.specs = [g if isinstance(g, GridSpec) else GridSpec.from_grid(g) for g in grids]
@@ -568,7 +603,8 @@ class Server:
         opts = _ServerOpts(n, ctypes.cast(structs, ctypes.c_void_p), ctypes.cast(thr, ctypes.c_void_p), int(lanes),
                            arr(batch_events, ctypes.c_int32), arr(batch_hits, ctypes.c_int64),
                            arr(event_candidates, ctypes.c_int64), float(deadline_ms), int(queue_limit),
-                           1 if keep_candidates else 0, tune_cache.encode() if tune_cache else None)
+                           1 if keep_candidates else 0, tune_cache.encode() if tune_cache else None,
+                           float(batch_timeout_ms))
         self._keep.append(thr)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -620,10 +656,12 @@ class Server:
                "hough_server_replay")
         return status
 
-    def poll(self, max_out=4096, cand_cap=1 << 22, wait_ms=0):
+    def poll(self, max_out=4096, cand_cap=1 << 22, wait_ms=0, with_cands=True):
         """Finished events: a list of dicts (tag, grid, status, n_hits,
         n_found, n_votes, batch_events, t_submit, t_launch, t_done and the
-        candidates as an int32 [n, 2] array of (votes, cell))."""
+        candidates as an int32 [n, 2] array of (votes, cell), unless
+        with_cands is false).  After a device failure the failed events come
+        back with status HOUGH_EDEVICE."""
         out = (_Served * max_out)()
         buf = np.empty((max(cand_cap, 1), 2), np.int32)
         n = ctypes.c_int32()
@@ -635,8 +673,10 @@ class Server:
             res.append({"tag": r.tag, "grid": r.grid, "status": r.status, "n_hits": r.n_hits,
                         "n_found": r.n_found, "n_votes": r.n_votes, "batch_events": r.batch_events,
                         "t_submit": r.t_submit, "t_launch": r.t_launch, "t_done": r.t_done,
-                        "cands": buf[r.cand_offset:r.cand_offset + r.n_stored].copy()})
-        _check(st, "hough_server_poll")
+                        "n_stored": r.n_stored,
+                        "cands": buf[r.cand_offset:r.cand_offset + r.n_stored].copy() if with_cands else None})
+        if st != HOUGH_EDEVICE:
+            _check(st, "hough_server_poll")
         return res
 
     def stats(self):

@@ -40,6 +40,14 @@ def _oracle(key, x, y, grid, thr):
     return _ORACLE_CACHE[key]
 
 
+def _oracle_many(events, grid, thr, workers=8):
+    """oracle.find of every event, several at a time (the oracle's C calls release
+    the interpreter lock; each call stays single-threaded)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        return list(pool.map(lambda ev: oracle.find(ev.x, ev.y, grid, thr), events))
+
+
 def _gpu_find(ctx, x, y, thr, cap=None):
     acc, nv = ctx.vote(_t(x), _t(y))
     out, nf = ctx.peaks(acc, thr, cap)
@@ -361,12 +369,45 @@ def test_full_batch_equals_single_event_launches_and_is_repeatable():
         for e in range(256):
             assert again[e][0] == first[e][0] and again[e][1] == first[e][1]
             np.testing.assert_array_equal(again[e][3], first[e][3])
-    # sampled events of the full batch against the oracle
-    for e in (0, 77, 255):
-        ev = b.events[e]
-        ra, rnv, rv, rc, rn = oracle.find(ev.x, ev.y, g, 7)
-        assert first[e][0] == rnv and first[e][1] == rn
-        np.testing.assert_array_equal(first[e][3], rc)
+    # every event of the full batch against the oracle
+    print("[parity] the 256 batch events against the oracle", flush=True)
+    refs = _oracle_many(b.events, g, 7)
+    for e, (ra, rnv, rv, rc, rn) in enumerate(refs):
+        assert first[e][0] == rnv and first[e][1] == rn, f"event {e}"
+        np.testing.assert_array_equal(first[e][2], rv, err_msg=f"event {e}: votes")
+        np.testing.assert_array_equal(first[e][3], rc, err_msg=f"event {e}: cells")
+
+
+def test_packed_batch_lists_are_the_batch_lists_back_to_back():
+    """hough_event_batch_packed stores each event's list, as hough_event_batch does, but at
+    the running sum of the earlier stored counts: with roomy capacities, and with
+    capacities short enough to truncate some events."""
+    print("[parity] packed batch lists", flush=True)
+    b = synth.gen_batch(4, 40)
+    g = synth.GRID_2D
+    ctx = hough.HoughContext(g, max_events=40, max_hits=b.n_hits)
+    x, y = _t(b.x), _t(b.y)
+    ref = _batch_results(ctx, b, 7)
+    short = np.array([500 + 1700 * (e % 7) if e % 2 else 131072 for e in range(40)], np.int64)
+    for caps in (None, short):
+        cand_off = None
+        if caps is not None:
+            cand_off = np.zeros(41, np.int64)
+            cand_off[1:] = np.cumsum(caps)
+        cands, start, nf, nv = ctx.event_batch_packed(b.hit_off, x, y, 7, cand_off=cand_off)
+        torch.cuda.synchronize()
+        start, nf, cc = start.cpu().numpy(), nf.cpu().numpy(), cands.cpu().numpy()
+        room = np.full(40, ctx.spec.max_candidates(), np.int64) if caps is None else caps
+        stored = np.minimum(nf.astype(np.int64), room)
+        assert start[0] == 0 and np.array_equal(np.diff(start), stored)
+        for e in range(40):
+            nv_e, nf_e, v, c = ref[e]
+            assert int(nf[e]) == nf_e
+            got = cc[start[e]:start[e + 1]]
+            np.testing.assert_array_equal(got[:, 0], v[:stored[e]], err_msg=f"event {e}")
+            np.testing.assert_array_equal(got[:, 1], c[:stored[e]], err_msg=f"event {e}")
+        if caps is not None:
+            assert (nf > caps).any() and (nf <= caps).any()
 
 
 def test_batch_graph_replay_with_changing_descriptors():

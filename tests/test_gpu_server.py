@@ -52,11 +52,14 @@ def test_results_match_each_event_alone():
     grids, thr = [synth.GRID_2D, synth.GRID_3D], [7, 5]
     ctxs = [hough.HoughContext(g, max_hits=70000) for g in grids]
     ref = [_alone(ctxs[g], ev, thr[g]) for g, ev in evs]
-    # the oracle agrees on one 2D event (the single-event path is pinned elsewhere)
-    g0 = next(i for i, (g, _) in enumerate(evs) if g == 0)
-    ra, rnv, rv, rc, rn = oracle.find(evs[g0][1].x, evs[g0][1].y, grids[0], 7)
-    assert ref[g0][0] == rnv and ref[g0][1] == rn
-    np.testing.assert_array_equal(ref[g0][2][:, 1], rc)
+    # the oracle agrees on every event of the mix, 2D and displaced 3D
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        oref = list(pool.map(lambda ge: oracle.find(ge[1].x, ge[1].y, grids[ge[0]], thr[ge[0]]), evs))
+    for i, (ra, rnv, rv, rc, rn) in enumerate(oref):
+        assert ref[i][0] == rnv and ref[i][1] == rn, f"event {i}"
+        np.testing.assert_array_equal(ref[i][2][:, 0], rv, err_msg=f"event {i}: votes")
+        np.testing.assert_array_equal(ref[i][2][:, 1], rc, err_msg=f"event {i}: cells")
 
     srv = hough.Server(grids, thr, lanes=2, batch_events=[6, 2], batch_hits=[1 << 19, 1 << 17], deadline_ms=2.0)
     hit_off = np.zeros(len(evs) + 1, np.int64)
@@ -109,4 +112,26 @@ def test_close_with_work_pending_does_not_hang():
     ev = synth.gen_config_event(3, 0)
     for k in range(5):
         assert srv.submit(k, 0, ev.x, ev.y)
+    srv.close()
+
+
+def test_batches_past_their_time_limit_fail_instead_of_blocking():
+    """A completion wait that exceeds the server's batch time limit returns the
+    batch's events with HOUGH_EDEVICE rather than blocking the lane: forced here
+    with a 1-microsecond limit on displaced events (each batch runs for much
+    longer; the kernels themselves finish normally).  Shutdown still drains."""
+    _dev()
+    srv = hough.Server([synth.GRID_3D], [5], lanes=1, batch_events=[2], batch_hits=[1 << 17],
+                       batch_timeout_ms=0.001)
+    ev = synth.gen_config_event(3, 0)
+    for k in range(3):
+        assert srv.submit(k, 0, ev.x, ev.y)
+    got = {}
+    import time
+    t_end = time.time() + 60
+    while len(got) < 3 and time.time() < t_end:
+        for r in srv.poll(wait_ms=50):
+            got[r["tag"]] = r
+    assert sorted(got) == [0, 1, 2]
+    assert all(r["status"] == hough.HOUGH_EDEVICE for r in got.values())
     srv.close()
