@@ -333,18 +333,21 @@ hough_status hough_tune_lookup(const char *cache_path, const char *device, const
                                int32_t *threads, int32_t *split);
 
 /* Timing mode (for benchmarks and profiling; results are unchanged).  When
- * enabled, hough_event_batch enqueues its kernels directly on the stream
- * instead of replaying a graph and records HIP events around the whole batch
- * and around its vote kernel.  hough_get_timing waits for the last timed batch
- * and returns the two durations in milliseconds (EINVAL before any timed
- * batch). */
+ * enabled (enable 1 or 2), hough_event_batch enqueues its kernels directly on
+ * the stream instead of replaying a graph and records HIP events around the
+ * whole batch and around its vote kernel; with 2 the vote kernel also counts
+ * the (hit, row) pairs it evaluates (one global atomic per wavefront and tile,
+ * which lengthens the vote: time with 1, count with 2).  hough_get_timing
+ * waits for the last timed batch and returns the two durations in
+ * milliseconds (EINVAL before any timed batch).  EINVAL for enable outside
+ * 0..2. */
 hough_status hough_set_timing(hough_ctx *ctx, int32_t enable);
 hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms);
 /* Work of the last timed batch (measurement only): the (hit, phi0 row) pairs
  * its vote kernel evaluated -- each hit staged into a tile times the rows of
  * that tile, halo rows included.  The culling arcs leave out the rows where a
  * hit cannot vote, so this is less than hits * n_d0 * n_phi.  Waits for the
- * batch.  EINVAL before any timed batch. */
+ * batch.  EINVAL unless the last batch ran in timing mode 2. */
 hough_status hough_get_work(hough_ctx *ctx, uint64_t *evaluated_pairs);
 
 /* ------------------------------------------------------------------------

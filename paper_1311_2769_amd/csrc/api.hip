@@ -41,6 +41,7 @@ struct BatchHeader {
     int32_t n_events;
     int32_t n_items;
     int64_t n_hits;
+    QueueDesc queues;
 };
 
 struct GraphKey {
@@ -110,6 +111,7 @@ struct hough_ctx {
 
     // timing mode: batches run without a graph, with events around the vote
     bool timing = false;
+    bool count_pairs = false;  // timing mode 2: the vote also counts the pairs it evaluates
     bool timed_once = false;
     unsigned long long *pairs = nullptr;   // timing mode: (hit, row) pairs the last timed vote evaluated
     hipEvent_t ev_start = nullptr, ev_vote0 = nullptr, ev_vote1 = nullptr, ev_end = nullptr;
@@ -256,16 +258,31 @@ hough_status stage_descriptors(hough_ctx *ctx, int32_t n_events, const int64_t *
         desc[e].cand_cap = static_cast<int32_t>(co[e + 1] - co[e]);
         desc[e].pad_ = 0;
     }
-    // Largest events first so the persistent workgroups finish together.
+    // Events go whole to the XCD queues, largest first, each to the queue with
+    // the least work so far (a tile's work grows with the event's hits, plus
+    // a fixed part for its clear and peak scan), so the queues drain together
+    // and every tile of an event reads its hits through one L2.
     std::vector<int32_t> order(static_cast<size_t>(n_events));
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return hit_off[a + 1] - hit_off[a] > hit_off[b + 1] - hit_off[b];
     });
+    std::vector<int32_t> queue_of(static_cast<size_t>(n_events));
+    int64_t load[kQueues] = {};
+    for (int32_t e : order) {
+        const int q = static_cast<int>(std::min_element(load, load + kQueues) - load);
+        queue_of[e] = q;
+        load[q] += (hit_off[e + 1] - hit_off[e] + 1024) * tpe;
+    }
     int32_t n_items = 0;
-    for (int32_t e : order)
-        for (int32_t t = 0; t < tpe; ++t)
-            items[n_items++] = WorkItem{e, t};
+    for (int q = 0; q < kQueues; ++q) {
+        hdr->queues.begin[q] = n_items;
+        for (int32_t e : order)
+            if (queue_of[e] == q)
+                for (int32_t t = 0; t < tpe; ++t)
+                    items[n_items++] = WorkItem{e, t};
+        hdr->queues.len[q] = n_items - hdr->queues.begin[q];
+    }
     ctx->last_hit_off.assign(hit_off, hit_off + n);
     ctx->last_cand_off = co;
     ctx->last_fused = fused;
@@ -363,13 +380,14 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
     if (ce == hipSuccess && timed)
         ce = hipEventRecord(ctx->ev_vote0, cs);
     uint32_t *a = (fused || acc_dw) ? acc_dw : ctx->acc_ws;
-    if (ce == hipSuccess && timed)
+    const bool count = timed && ctx->count_pairs;
+    if (ce == hipSuccess && count)
         ce = launch_zero(reinterpret_cast<uint32_t *>(ctx->pairs), 2, cs);
     if (ce == hipSuccess)
         ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, vs, fused), dd.desc,
-                               &dd.hdr->n_items, dd.items, ctx->max_items, ctx->work_counter,
+                               &dd.hdr->queues, dd.items, ctx->max_items, ctx->work_counter,
                                ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs,
-                               timed ? ctx->pairs : nullptr);
+                               count ? ctx->pairs : nullptr);
     if (ce == hipSuccess && timed)
         ce = hipEventRecord(ctx->ev_vote1, cs);
     if (ce == hipSuccess && !fused)
@@ -578,7 +596,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         e = hipMemcpy(c->all_tiles, &all, sizeof(uint2), hipMemcpyHostToDevice);
     }
     e = e ? e : dev_alloc(&c->desc_dev, c->desc_bytes);
-    e = e ? e : dev_alloc(&c->work_counter, 1);
+    e = e ? e : dev_alloc(&c->work_counter, static_cast<size_t>(kQueues) * kCounterStride);
     e = e ? e : dev_alloc(&c->assoc_hist, kAssocBuckets);
     e = e ? e : dev_alloc(&c->pairs, 1);
     if (e == hipSuccess)
@@ -634,7 +652,10 @@ hough_status hough_set_launch(hough_ctx *ctx, int32_t which, int32_t rows, int32
 hough_status hough_set_timing(hough_ctx *ctx, int32_t enable) {
     if (!ctx)
         return HOUGH_EINVAL;
+    if (enable < 0 || enable > 2)
+        return HOUGH_EINVAL;
     ctx->timing = enable != 0;
+    ctx->count_pairs = enable == 2;
     ctx->timed_once = false;
     return HOUGH_OK;
 }
@@ -654,7 +675,7 @@ hough_status hough_get_timing(hough_ctx *ctx, float *vote_ms, float *total_ms) {
 }
 
 hough_status hough_get_work(hough_ctx *ctx, uint64_t *evaluated_pairs) {
-    if (!ctx || !ctx->timed_once || !evaluated_pairs)
+    if (!ctx || !ctx->timed_once || !ctx->count_pairs || !evaluated_pairs)
         return HOUGH_EINVAL;
     HIP_TRY(hipEventSynchronize(ctx->ev_end));
     unsigned long long v = 0;
@@ -776,7 +797,7 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
     auto *nv = reinterpret_cast<unsigned long long *>(n_votes);
     HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, s));
     HIP_TRY(hit_prep(ctx, vs, false, x, y, hit_off[n_events], nullptr, s));
-    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, vs, false), dd.desc, &dd.hdr->n_items,
+    HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, vs, false), dd.desc, &dd.hdr->queues,
                               dd.items, ctx->max_items, ctx->work_counter, ctx->persistent_groups,
                               static_cast<uint32_t *>(acc), nv, nullptr, 0, s));
     return HOUGH_OK;

@@ -62,29 +62,6 @@ struct AssocArgs {
     unsigned long long *n_pairs;
 };
 
-// The hit's kappa bin at (d0 slice l, phi0 row j), or -1 when it casts no vote there.
-__device__ __forceinline__ int hit_bin(const GridArgs &g, float hx, float hy, float hr2, int l, int j) {
-    const float c = g.cos_phi[j];
-    const float s = g.sin_phi[j];
-    if (g.forward) {
-        const float ahead = hx * c + hy * s;
-        if (!(ahead > 0.0f))
-            return -1;
-    }
-    const float u = hy * c - hx * s;
-    float kf;
-    if (g.straight) {
-        kf = (u - g.kappa_min) * g.kappa_scale;
-    } else {
-        const float d = g.d0 ? g.d0[l] : 0.0f;
-        const float num = 2.0f * (u - d);
-        const float den = hr2 - 2.0f * d * u + d * d;
-        const float kappa = num / den;
-        kf = (kappa - g.kappa_min) * g.kappa_scale;
-    }
-    return (kf >= 0.0f && kf < static_cast<float>(g.n_kappa)) ? static_cast<int>(kf) : -1;
-}
-
 // Azimuth bucket of a hit (NaN and the origin go to bucket 0).
 __device__ __forceinline__ int azimuth_bucket(float x, float y) {
     const float a = atan2f(y, x);                      // [-pi, pi]
@@ -143,8 +120,9 @@ __global__ __launch_bounds__(kAssocThreads) void map_kernel(const Cand *cands, c
 }
 
 // R phi0 rows per thread; D3: the grid has a d0 axis (slices l - 1 .. l + 1
-// take part in a window), else one slice.
-template <int R, bool D3>
+// take part in a window), else one slice; STRAIGHT: the straight-line family;
+// FWD: the forward-hemisphere option.
+template <int R, bool D3, bool STRAIGHT, bool FWD>
 __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
     __shared__ int2 staged[kAssocWaves][kAssocBuf];
     const GridArgs &g = a.g;
@@ -179,16 +157,46 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
     const int h = __float_as_int(rec.w);
     const int64_t plane = static_cast<int64_t>(np) * nk;
 
-    // bins of slice ll over ring rows j0 - 1 .. j0 + R (-1: no vote, or a
-    // slice outside the grid)
+    // The run's ring rows j0 - 1 .. j0 + R (cyclic) are the same for every
+    // lane: u = y c - x s per row is computed once and serves every slice.
+    const float kmin = g.kappa_min;
+    const float kscale = g.kappa_scale;
+    const float nkf = static_cast<float>(nk);
+    float u[R + 2];
+    bool votes[R + 2];                  // the hit exists (and, with the option, lies ahead)
+#pragma unroll
+    for (int k = 0; k < R + 2; ++k) {
+        int row = j0 - 1 + k;
+        row += row < 0 ? np : 0;
+        row -= row >= np ? np : 0;
+        const float c = g.cos_phi[row];
+        const float sn = g.sin_phi[row];
+        u[k] = rec.y * c - rec.x * sn;
+        votes[k] = live;
+        if constexpr (FWD) {
+            const float ahead = rec.x * c + rec.y * sn;
+            votes[k] = live && ahead > 0.0f;
+        }
+    }
+    // The hit's kappa bins of slice ll over the ring rows: the vote of hough.h,
+    // operation for operation (-1: no vote, or a slice outside the grid).
     auto fill_slice = [&](int ll, int (&B)[R + 2]) {
-        const bool ok = live && ll >= 0 && ll < n_d0;
+        const bool ok = ll >= 0 && ll < n_d0;
+        const float d = (ok && g.d0) ? g.d0[ll] : 0.0f;     // a one-slice grid may carry a d0 table
+        const float d2 = 2.0f * d;
+        const float dd = d * d;
 #pragma unroll
         for (int k = 0; k < R + 2; ++k) {
-            int row = j0 - 1 + k;
-            row += row < 0 ? np : 0;
-            row -= row >= np ? np : 0;
-            B[k] = ok ? hit_bin(g, rec.x, rec.y, rec.z, ll, row) : -1;
+            float kf;
+            if constexpr (STRAIGHT) {
+                kf = (u[k] - kmin) * kscale;
+            } else {
+                const float num = 2.0f * (u[k] - d);
+                const float den = (rec.z - d2 * u[k]) + dd;
+                const float kappa = num / den;
+                kf = (kappa - kmin) * kscale;
+            }
+            B[k] = (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
         }
     };
     int B0[R + 2], B1[R + 2], B2[R + 2];
@@ -211,9 +219,14 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
         uint32_t cmin[R + 2];
 #pragma unroll
         for (int k = 0; k < R + 2; ++k) {
-            cmax[k] = max(max(B0[k], B1[k]), B2[k]);
-            cmin[k] = min(min(static_cast<uint32_t>(B0[k]), static_cast<uint32_t>(B1[k])),
-                          static_cast<uint32_t>(B2[k]));
+            if constexpr (D3) {
+                cmax[k] = max(max(B0[k], B1[k]), B2[k]);
+                cmin[k] = min(min(static_cast<uint32_t>(B0[k]), static_cast<uint32_t>(B1[k])),
+                              static_cast<uint32_t>(B2[k]));
+            } else {
+                cmax[k] = B1[k];
+                cmin[k] = static_cast<uint32_t>(B1[k]);
+            }
         }
         const uint32_t *brow0 = a.bits + static_cast<int64_t>(l) * np * a.row_words;
 #pragma unroll
@@ -248,9 +261,11 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
                         bool near = false;
 #pragma unroll
                         for (int t = 0; t < 3; ++t) {
-                            near |= B0[r + t] >= 0 && abs(B0[r + t] - kc) <= 1;
                             near |= B1[r + t] >= 0 && abs(B1[r + t] - kc) <= 1;
-                            near |= B2[r + t] >= 0 && abs(B2[r + t] - kc) <= 1;
+                            if constexpr (D3) {
+                                near |= B0[r + t] >= 0 && abs(B0[r + t] - kc) <= 1;
+                                near |= B2[r + t] >= 0 && abs(B2[r + t] - kc) <= 1;
+                            }
                         }
                         if (near) {
                             cand = a.map[l * plane + static_cast<int64_t>(jc) * nk + kc] - 1;
@@ -331,10 +346,13 @@ hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, i
     const bool d3 = g.n_d0 > 1;
     const int R = d3 ? 8 : 16;
     const dim3 grid(static_cast<unsigned>((g.n_phi + R - 1) / R), hb);
+    auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, grid, dim3(kAssocThreads), 0, stream, a); };
     if (d3)
-        hipLaunchKernelGGL((assoc_kernel<8, true>), grid, dim3(kAssocThreads), 0, stream, a);
+        g.forward ? go(assoc_kernel<8, true, false, true>) : go(assoc_kernel<8, true, false, false>);
+    else if (g.straight)
+        g.forward ? go(assoc_kernel<16, false, true, true>) : go(assoc_kernel<16, false, true, false>);
     else
-        hipLaunchKernelGGL((assoc_kernel<16, false>), grid, dim3(kAssocThreads), 0, stream, a);
+        g.forward ? go(assoc_kernel<16, false, false, true>) : go(assoc_kernel<16, false, false, false>);
     return hipGetLastError();
 }
 

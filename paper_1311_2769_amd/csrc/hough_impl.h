@@ -55,6 +55,20 @@ struct WorkItem {
     int32_t tile;         // tile index inside the event (d0 slice major)
 };
 
+// Work queues of a persistent batched vote, one per XCD: workgroups are
+// dispatched to the XCDs in turn (workgroup i on XCD i mod kQueues), so the
+// workgroups of queue q share one L2, and all tiles of an event sit in one
+// queue -- its hit records are fetched into one L2 rather than into every
+// XCD's.  Queue q is items [begin[q], begin[q] + len[q]) of the work list (the
+// queues back to back); a workgroup whose queue is empty takes work from the
+// next queues in turn.
+constexpr int kQueues = 8;
+constexpr int kCounterStride = 32;    // int32s between queue counters: each on a 128-byte line of its own
+struct QueueDesc {
+    int32_t begin[kQueues];
+    int32_t len[kQueues];
+};
+
 // Grid in the form the kernels take it.
 struct GridArgs {
     const float *cos_phi;
@@ -163,6 +177,7 @@ int32_t default_tile_rows(const GridArgs &g);
 hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *n_votes,
                        hipStream_t stream);
 // Batch form: state of all max_events slots, n_votes of the live events, work counter.
+// work_counter: kQueues counters kCounterStride int32s apart, all zeroed.
 hipError_t launch_prep_batch(EventState *state, int32_t max_events, const int32_t *n_events_dev,
                              unsigned long long *n_votes, int32_t *work_counter, hipStream_t stream);
 hipError_t launch_zero(uint32_t *p, int64_t n_dwords, hipStream_t stream);
@@ -193,13 +208,15 @@ hipError_t launch_table_check(const float *cos_phi, const float *sin_phi, int32_
 hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, const VoteInputs &in,
                               int32_t n_hits, uint32_t *acc, unsigned long long *n_votes, hipStream_t stream,
                               unsigned long long *pairs = nullptr);
-// Many events: tile work items over events described by desc; the live item
-// count is read on the device.  With a work counter (reset beforehand) the
-// launch is persistent: persistent_groups workgroups pull items in order.
+// Many events: tile work items over events described by desc; the queues
+// (live item counts) are read on the device.  With work counters (reset
+// beforehand) the launch is persistent: persistent_groups workgroups pull
+// items from their XCD's queue, then from the others; without, workgroup i
+// takes item i of the queues back to back.
 // fused (2D int32 only): tiles also search their interior rows for peaks into
 // the staging lists of *w; acc may then be nullptr.
 hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const VoteShape &s, const VoteInputs &in,
-                             const EventDesc *desc, const int32_t *n_items_dev, const WorkItem *items,
+                             const EventDesc *desc, const QueueDesc *queues, const WorkItem *items,
                              int32_t max_items, int32_t *work_counter, int32_t persistent_groups, uint32_t *acc,
                              unsigned long long *n_votes, const SortWork *w, int32_t threshold,
                              hipStream_t stream, unsigned long long *pairs = nullptr);

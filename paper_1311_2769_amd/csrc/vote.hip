@@ -88,8 +88,8 @@ struct VoteArgs {
     int32_t tile_off;           // 0, or -1 for fused tiles
     const EventDesc *desc;      // batch: per-event hit ranges
     const WorkItem *items;      // batch: tile list, or nullptr for a single event
-    const int32_t *n_items;     // batch: live item count (device)
-    int32_t *work_counter;      // batch, persistent: next item to take
+    const QueueDesc *queues;    // batch: the list's work queues (device)
+    int32_t *work_counter;      // batch, persistent: next item of each queue (kCounterStride apart)
     uint32_t *acc;              // dwords; fused batches may pass nullptr
     unsigned long long *n_votes;
     SortWork w;                 // fused: staging lists
@@ -120,6 +120,7 @@ struct TileScratch {
     unsigned long long red[NT / 64];
     int32_t n_kept[2][2];            // per block parity: staged at the front, at the back
     int32_t next_item;
+    unsigned long long pairs;        // measurement: pairs this workgroup evaluated, added once at its end
 };
 
 __device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v) {
@@ -461,8 +462,11 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     lds_barrier();
     // Every staged hit is evaluated once per row of the tile (halo rows
     // included); rows past the grid take NaN constants and are not counted.
+    // Summed in LDS; the workgroup adds its total to a.pairs when it ends.
     if (a.pairs && lane == 0 && kept_here > 0)
-        atomicAdd(a.pairs, static_cast<unsigned long long>(kept_here) * static_cast<unsigned long long>(len));
+        __hip_atomic_fetch_add(&ts.pairs, static_cast<unsigned long long>(kept_here) *
+                                              static_cast<unsigned long long>(len),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 
     const int rd = g.row_dwords;
     unsigned long long votes = 0;
@@ -644,6 +648,16 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ TileScratch<NT> ts;
     const int T = a.tiles_per_slice;
+    // measurement: the workgroup's evaluated pairs, one global add at its end
+    if (a.pairs && threadIdx.x == 0)
+        ts.pairs = 0ull;
+    auto add_pairs = [&]() {
+        if (a.pairs) {
+            lds_barrier();
+            if (threadIdx.x == 0 && ts.pairs)
+                atomicAdd(a.pairs, ts.pairs);
+        }
+    };
 
     if (a.items == nullptr) {
         const int tile = blockIdx.x;
@@ -654,20 +668,38 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
         const int64_t hb = static_cast<int64_t>(blockIdx.y) * per;
         const int64_t he = min(n, hb + per);
         vote_tile<U16, D3, ROWS, NT, FUSED, FWD>(a, 0, l, t, hb, he, a.acc, a.split > 1, a.n_votes, lds, ts);
+        add_pairs();
         return;
     }
-    const int32_t n_items = *a.n_items;
+    const QueueDesc *qd = a.queues;
     int32_t it = blockIdx.x;
+    int q = blockIdx.x % kQueues;     // this XCD's queue (thread 0 keeps track)
+    int tried = 0;
     for (;;) {
         if (a.work_counter) {
-            if (threadIdx.x == 0)
-                ts.next_item = atomicAdd(a.work_counter, 1);
+            if (threadIdx.x == 0) {
+                int32_t item = -1;
+                while (tried < kQueues) {
+                    const int32_t k = atomicAdd(&a.work_counter[q * kCounterStride], 1);
+                    if (k < qd->len[q]) {
+                        item = qd->begin[q] + k;
+                        break;
+                    }
+                    q = q + 1 < kQueues ? q + 1 : 0;      // empty: the next queue
+                    ++tried;
+                }
+                ts.next_item = item;
+            }
             lds_barrier();
             it = ts.next_item;
             lds_barrier();
+        } else if (it >= qd->begin[kQueues - 1] + qd->len[kQueues - 1]) {
+            it = -1;
         }
-        if (it >= n_items)
+        if (it < 0) {
+            add_pairs();
             return;
+        }
         const WorkItem wi = a.items[it];
         const EventDesc ev = a.desc[wi.event];
         const int l = wi.tile / T;
@@ -675,8 +707,10 @@ __global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
         uint32_t *acc_e = a.acc ? a.acc + static_cast<int64_t>(wi.event) * a.g.acc_dwords : nullptr;
         vote_tile<U16, D3, ROWS, NT, FUSED, FWD>(a, wi.event, l, t, ev.hit_begin, ev.hit_end, acc_e, false,
                                             a.n_votes ? a.n_votes + wi.event : nullptr, lds, ts);
-        if (!a.work_counter)
+        if (!a.work_counter) {
+            add_pairs();
             return;
+        }
     }
 }
 
@@ -989,8 +1023,8 @@ __global__ void prep_batch_kernel(EventState *state, int32_t max_events, const i
         if (n_votes && i < *n_events_dev)
             n_votes[i] = 0ull;
     }
-    if (i == 0 && work_counter)
-        *work_counter = 0;
+    if (i < kQueues && work_counter)
+        work_counter[i * kCounterStride] = 0;
 }
 
 __global__ void zero_kernel(uint32_t *p, int64_t n) {
@@ -1241,7 +1275,7 @@ hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, c
 }
 
 hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const VoteShape &s, const VoteInputs &in,
-                             const EventDesc *desc, const int32_t *n_items_dev, const WorkItem *items,
+                             const EventDesc *desc, const QueueDesc *queues, const WorkItem *items,
                              int32_t max_items, int32_t *work_counter, int32_t persistent_groups, uint32_t *acc,
                              unsigned long long *n_votes, const SortWork *w, int32_t threshold,
                              hipStream_t stream, unsigned long long *pairs) {
@@ -1253,7 +1287,7 @@ hipError_t launch_vote_batch(const GridArgs &g, bool u16, bool fused, const Vote
     set_geometry(a, g, s, fused);
     a.desc = desc;
     a.items = items;
-    a.n_items = n_items_dev;
+    a.queues = queues;
     a.acc = acc;
     a.n_votes = n_votes;
     if (w)

@@ -476,8 +476,11 @@ class HoughContext:
             cache.encode() if cache else None, _stream_handle(stream), ctypes.byref(best)), "hough_autotune")
         return self.get_launch(which) + (best.value,)
 
-    def set_timing(self, enable: bool):
-        _check(self.lib.hough_set_timing(self.handle, 1 if enable else 0), "hough_set_timing")
+    def set_timing(self, enable):
+        """0/False: graphs; 1/True: timed direct launches; 2: timed and counting
+        the vote's evaluated pairs (get_work)."""
+        mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        _check(self.lib.hough_set_timing(self.handle, mode), "hough_set_timing")
 
     def get_timing(self):
         """(vote_ms, total_ms) of the last timed batch (waits for it)."""

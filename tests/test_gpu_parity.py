@@ -589,6 +589,30 @@ def test_timing_mode_gives_the_same_results():
         np.testing.assert_array_equal(timed[e][3], base[e][3])
 
 
+def test_counted_pairs_bound_the_work():
+    """Timing mode 2 counts the (hit, row) pairs the vote evaluates: at least one
+    per vote cast, at most every row of every tile (halo rows included) for every
+    hit, and the culling leaves out a good share; results are unchanged."""
+    b = synth.gen_batch(4, 6)
+    g = synth.GRID_2D
+    ctx = hough.HoughContext(g, max_events=6, max_hits=b.n_hits)
+    base = _batch_results(ctx, b, 7)
+    with pytest.raises(hough.HoughError):
+        ctx.get_work()                      # nothing counted yet
+    ctx.set_timing(2)
+    counted = _batch_results(ctx, b, 7)
+    pairs = ctx.get_work()
+    ctx.set_timing(False)
+    votes = sum(r[0] for r in counted)
+    rows, _, _ = ctx.get_launch(1)
+    tiles = -(-g.n_phi // (rows - 2))      # fused tiles of rows - 2 interior rows, each with two halo rows
+    assert votes <= pairs <= b.n_hits * tiles * rows
+    assert pairs < 0.8 * b.n_hits * g.n_phi
+    for e in range(6):
+        assert counted[e][:2] == base[e][:2]
+        np.testing.assert_array_equal(counted[e][3], base[e][3])
+
+
 def test_division_fast_path_equals_the_operator():
     """The hoisted-reciprocal quotient equals fp32 division bit for bit (device self-test)."""
     _dev()
