@@ -17,17 +17,19 @@
 // Work: hits are first put in azimuth order (a counting sort into the
 // context's hit records), so that the lanes of a wavefront are hits of
 // similar direction, whose votes fall in similar cells.  A thread then takes
-// one hit and a run of R phi0 rows and walks the d0 slices upwards, keeping
-// the hit's kappa bins of three slices (l - 1, l, l + 1) over rows
-// j0 - 1 .. j0 + R in registers: every bin is computed once per thread, one
-// new slice per step.  For a candidate row (l, jc) the hit's nine window bins
-// b_p give the kappa bins it can reach, the union of [b_p - 1, b_p + 1]: the
-// bitmap is read over [min b_p - 1, max b_p + 1], and each candidate found
-// there is kept when some |b_p - kc| <= 1 -- so each (candidate, hit) pair is
-// found once, by the thread that owns the candidate's row.  Each wavefront
-// gathers its pairs in LDS and reserves room in the output with one atomic
-// per kAssocFlush pairs.
+// one hit and a run of R phi0 rows (4 in 3D, 32 in 2D) and walks the d0
+// slices upwards, keeping the hit's kappa bins of three slices (l - 1, l,
+// l + 1) over rows j0 - 1 .. j0 + R in registers: every bin is computed once
+// per thread, one new slice per step.  For a candidate row (l, jc) the hit's
+// nine window bins b_p give the kappa bins it can reach, the union of
+// [b_p - 1, b_p + 1]: the bitmap is read over [min b_p - 1, max b_p + 1], and
+// each candidate found there is kept when some |b_p - kc| <= 1 -- so each
+// (candidate, hit) pair is found once, by the thread that owns the
+// candidate's row.  Each wavefront gathers its pairs in LDS and reserves room
+// in the output with one atomic per kAssocFlush pairs.
 #pragma clang fp contract(off)
+
+#include <algorithm>
 
 #include "assoc.h"
 
@@ -187,16 +189,16 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
         const float dd = d * d;
 #pragma unroll
         for (int k = 0; k < R + 2; ++k) {
-            float kf;
             if constexpr (STRAIGHT) {
-                kf = (u[k] - kmin) * kscale;
+                const float kf = (u[k] - kmin) * kscale;
+                B[k] = (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
             } else {
                 const float num = 2.0f * (u[k] - d);
                 const float den = (rec.z - d2 * u[k]) + dd;
                 const float kappa = num / den;
-                kf = (kappa - kmin) * kscale;
+                const float kf = (kappa - kmin) * kscale;
+                B[k] = (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
             }
-            B[k] = (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
         }
     };
     int B0[R + 2], B1[R + 2], B2[R + 2];
@@ -343,16 +345,17 @@ hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, i
     a.pairs = pairs;
     a.cap = cap;
     a.n_pairs = n_pairs;
+    // rows per thread: measured best on the workload grids (2D 32, 3D 4)
     const bool d3 = g.n_d0 > 1;
-    const int R = d3 ? 8 : 16;
+    const int R = d3 ? 4 : 32;
     const dim3 grid(static_cast<unsigned>((g.n_phi + R - 1) / R), hb);
     auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, grid, dim3(kAssocThreads), 0, stream, a); };
     if (d3)
-        g.forward ? go(assoc_kernel<8, true, false, true>) : go(assoc_kernel<8, true, false, false>);
+        g.forward ? go(assoc_kernel<4, true, false, true>) : go(assoc_kernel<4, true, false, false>);
     else if (g.straight)
-        g.forward ? go(assoc_kernel<16, false, true, true>) : go(assoc_kernel<16, false, true, false>);
+        g.forward ? go(assoc_kernel<32, false, true, true>) : go(assoc_kernel<32, false, true, false>);
     else
-        g.forward ? go(assoc_kernel<16, false, false, true>) : go(assoc_kernel<16, false, false, false>);
+        g.forward ? go(assoc_kernel<32, false, false, true>) : go(assoc_kernel<32, false, false, false>);
     return hipGetLastError();
 }
 
