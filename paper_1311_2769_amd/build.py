@@ -67,7 +67,9 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as pool:
         list(pool.map(lambda c: _run(c, verbose), cmds))
     out_tmp = LIB + ".tmp"
-    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs], verbose)
+    # the server marks its phases as roctx ranges (seen by rocprofv3 --marker-trace)
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs, "-L/opt/rocm/lib",
+          "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"], verbose)
     os.replace(out_tmp, LIB)
     return LIB
 

@@ -16,9 +16,14 @@
 //     other lane of that grid is busy; otherwise it waits until the oldest
 //     has waited `deadline_ms` or the waiting hits fill half a pool, so small
 //     batches do not starve large ones;
-//   * completion: one thread per lane waits for its batch, copies each event's
-//     candidates (exactly n_found of them) to the host and publishes the
-//     results with their submit, launch and completion times.
+//   * lanes: one worker thread per lane stages its batch's hits in pinned
+//     memory, launches it, waits for it, copies each event's candidates
+//     (exactly n_found of them) to the host and publishes the results with
+//     their submit, launch and completion times; the dispatcher thread only
+//     picks batches.
+//
+// The worker marks its phases as roctx ranges, so a rocprofv3 run with
+// --marker-trace shows staging, waiting and the copy back per lane.
 //
 // Every result is the one hough_vote + hough_peaks give for that event alone:
 // batching never changes an integer.
@@ -35,6 +40,8 @@
 #include <new>
 #include <thread>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "dispatch.h"
 #include "hough.h"
@@ -75,13 +82,12 @@ struct Lane {
     hough_cand *c_h = nullptr;
     int32_t *nf_h = nullptr;
     uint64_t *nv_h = nullptr;
-    // the batch in flight (owned by the dispatcher until handed to the completion thread)
+    // the batch in flight (filled by the dispatcher, then owned by the lane's worker)
     std::vector<std::unique_ptr<Event>> batch;
     std::vector<int64_t> hit_off, cand_off;
     double t_launch = 0.0;
-    hipError_t launch_err = hipSuccess;
     bool busy = false;               // guarded by the server mutex
-    bool handed = false;             // a batch waits for the completion thread
+    bool handed = false;             // a batch waits for the lane's worker
     std::thread worker;
 };
 
@@ -188,7 +194,9 @@ int64_t grid_bound(const hough_grid &g) {
     return std::max<int64_t>(1, a * b * c);
 }
 
-// Launch the lane's batch (dispatcher thread, lane not busy, mutex not held).
+// Stage and launch the lane's batch (the lane's worker, mutex not held): each
+// lane copies its own events into pinned memory, so a large batch of one lane
+// delays neither the dispatcher nor the other lanes.
 hipError_t launch_batch(hough_server *s, Lane *l) {
     const int32_t n = static_cast<int32_t>(l->batch.size());
     l->hit_off.assign(n + 1, 0);
@@ -274,12 +282,6 @@ void dispatcher_main(hough_server *s) {
             }
             continue;
         }
-        lk.unlock();
-        const hipError_t e = launch_batch(s, pick);
-        pick->launch_err = e;
-        if (e != hipSuccess)
-            set_error(s, "server batch launch", e);
-        lk.lock();
         pick->handed = true;
         s->cv_lane.notify_all();
     }
@@ -294,9 +296,16 @@ void lane_main(hough_server *s, Lane *l) {
             break;
         lk.unlock();
         const int32_t n = static_cast<int32_t>(l->batch.size());
-        hipError_t e = l->launch_err;
+        roctxRangePushA("hough_server: stage and launch a batch");
+        hipError_t e = launch_batch(s, l);
+        roctxRangePop();
+        if (e != hipSuccess)
+            set_error(s, "server batch launch", e);
+        roctxRangePushA("hough_server: wait for a batch");
         if (e == hipSuccess)
             e = wait_event(l->done, s->wait_limit_s);
+        roctxRangePop();
+        roctxRangePushA("hough_server: candidates to the host");
         // The lists are packed: event k's min(n_found, cap) candidates follow
         // event k-1's, so one copy brings the whole batch's lists back.
         std::vector<int64_t> start(static_cast<size_t>(n) + 1, 0);
@@ -324,6 +333,7 @@ void lane_main(hough_server *s, Lane *l) {
             const int64_t m = (e == hipSuccess && s->keep_candidates) ? start[k + 1] - start[k] : 0;
             r.cands.assign(l->c_h + start[k], l->c_h + start[k] + m);
         }
+        roctxRangePop();
         if (e != hipSuccess)
             set_error(s, "server batch completion", e);
         lk.lock();
