@@ -326,6 +326,7 @@ DevDesc device_descriptors(const hough_ctx *ctx) {
 // captured graphs -- the exact count is read on the device -- so a context
 // needs at most a few graphs whatever its batches hold.
 constexpr int64_t kHitBucket = 1 << 16;
+constexpr size_t kMaxGraphs = 32;         // executable graphs kept per context
 
 // Sort-key digits that can differ within the events of a batch.  A key is
 // 0x7fffffff - votes, which is 0x7fffffff XOR votes for 0 <= votes, so two
@@ -834,10 +835,18 @@ hough_status event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_of
     const int64_t bucket = hit_bucket(hit_off[n_events]);
     const uint32_t key_mask = batch_key_mask(ctx, n_events, hit_off);
     GraphKey key{x, y, acc, cands, n_found, n_votes, cand_start, threshold, bucket, key_mask};
+    // Executable graphs are kept per key, least recently used evicted first: a
+    // served lane sees batches of many sizes (hit buckets, sort passes), and
+    // a capture costs far more than the replay it saves.
     hipGraphExec_t exec = nullptr;
-    for (auto &ge : ctx->graphs)
-        if (ge.key == key)
-            exec = ge.exec;
+    for (size_t k = 0; k < ctx->graphs.size(); ++k)
+        if (ctx->graphs[k].key == key) {
+            const GraphEntry hit = ctx->graphs[k];
+            ctx->graphs.erase(ctx->graphs.begin() + static_cast<std::ptrdiff_t>(k));
+            ctx->graphs.push_back(hit);
+            exec = hit.exec;
+            break;
+        }
     if (ctx->timing) {
         // Direct launches with events around the vote (no graph).
         if (changed)
@@ -871,7 +880,7 @@ hough_status event_batch(hough_ctx *ctx, int32_t n_events, const int64_t *hit_of
         (void)hipGraphDestroy(graph);
         if (ie != hipSuccess)
             return device_error(ie, "hipGraphInstantiate");
-        if (ctx->graphs.size() >= 8) {
+        if (ctx->graphs.size() >= kMaxGraphs) {
             (void)hipGraphExecDestroy(ctx->graphs.front().exec);
             ctx->graphs.erase(ctx->graphs.begin());
         }

@@ -19,13 +19,15 @@
 //
 // Hits.  hit_prep_kernel writes one record per hit (x, y and the hit's
 // denominator terms) and, per d0 slice, the two cyclic ranges of tiles
-// outside which the hit cannot vote.  A tile streams the event's records
-// through LDS in blocks of kHitBlock: each thread loads its share of the next
-// block while the current one is evaluated, and only the hits whose ranges
-// hold the tile are staged.  Lane groups read staged hits one iteration ahead
-// of their votes; the fewer than 4G hits left over after whole iterations are
-// carried into the next block, so only the last block of a tile has a
-// partial iteration.
+// outside which the hit cannot vote.  The wavefronts of a tile take the
+// event's records in chunks of 64, round robin, each on its own: a lane loads
+// one record of the wavefront's next chunk while the current one is
+// evaluated, and only the hits whose ranges hold the tile are staged, in the
+// wavefront's own LDS region.  Lane groups read staged hits one iteration
+// ahead of their votes; the fewer than 4G hits left over after whole
+// iterations are carried into the wavefront's next chunk, so only its last
+// chunk has a partial iteration.  The workgroup meets at a barrier only when
+// the tile is zeroed and when its votes are in.
 //
 // Culling.  A hit can only vote in the phi0 rows where its curvature lies in
 // the kappa range: two arcs of phi0 per d0 slice.  hit_prep_kernel computes
@@ -97,28 +99,24 @@ struct VoteArgs {
     unsigned long long *pairs;  // measurement: (hit, row) pairs evaluated, added per tile, or nullptr
 };
 
-constexpr int kHitBlock = 512;   // hit records examined per block
-
-// Staged hits of a block: fast ones from the front (a carried remainder of
-// fewer than 4G, then up to kHitBlock new ones), slow ones downwards from
-// slow_end, and 4G slots of slack after that for the reads a lane group
-// issues past the end of a list (values that are never used).  G, the lane
-// groups of a workgroup, is at most twice its wavefronts.
-template <int NT>
-constexpr int max_groups() { return 2 * (NT / 64); }
-template <int NT>
-constexpr int slow_end() { return kHitBlock + 4 * max_groups<NT>(); }
-template <int NT>
-constexpr int hit_slots() { return slow_end<NT>() + 4 * max_groups<NT>(); }
+// Each wavefront stages the hit records of its own chunks (chunk c of a
+// tile's hit range belongs to wavefront c mod NW, one record per lane) in a
+// region of its own: fast hits from the front, after a carried remainder of
+// fewer than kCarryMax, slow ones downwards from kRegionSlow, and kCarryMax
+// slots of slack after that for the reads a lane group issues past the end of
+// a list (values that are never used).
+constexpr int kChunk = 64;
+constexpr int kCarryMax = 8;                       // 4 x (hits per wavefront instruction)
+constexpr int kRegionSlow = kChunk + kCarryMax;
+constexpr int kRegion = kRegionSlow + kCarryMax;
 
 template <int NT>
 struct TileScratch {
-    float4 hits[hit_slots<NT>()];
+    float4 hits[NT / 64][kRegion];   // each wavefront's staged hits
     CompactScratch<NT> sc;
     int32_t cnt[NT];                 // fused peak search: candidates per (row, kappa segment)
     int32_t wave_tot[NT / 64];
     unsigned long long red[NT / 64];
-    int32_t n_kept[2][2];            // per block parity: staged at the front, at the back
     int32_t next_item;
     unsigned long long pairs;        // measurement: pairs this workgroup evaluated, added once at its end
 };
@@ -137,10 +135,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     constexpr int HPW = 64 / RL;                // hits per wavefront instruction
     constexpr int RPT = ROWS / RL;              // rows per lane
     constexpr int NW = NT / 64;
-    constexpr int G = NW * HPW;                 // lane groups
-    constexpr int SLOW_END = slow_end<NT>();
+    constexpr int G = HPW;                      // lane groups of a wavefront
     constexpr int stride = ROWS;                // dwords per LDS kappa column
-    static_assert(G <= max_groups<NT>(), "staging slack");
+    static_assert(4 * G <= kCarryMax, "staging slack");
     const GridArgs &g = a.g;
     const int tid = threadIdx.x;
     const int n_phi = g.n_phi;
@@ -162,8 +159,6 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         for (int i = tid; i < kDigits; i += NT)
             ts.sc.hist[i] = 0u;
     }
-    if (tid < 4)
-        ts.n_kept[tid >> 1][tid & 1] = 0;
 
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -347,17 +342,17 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             vote(kb[i], i);
         }
     };
-    // Staged hits [lo, hi) (lo, hi wave-uniform).  An iteration covers 2G
-    // consecutive hits: lane group lg = wave*HPW + hsub takes hits it + lg and
-    // it + G + lg.  Two iterations per trip, the next pair read before the
-    // current votes are cast (two register sets, no copies), so waiting for a
-    // read never waits for atomics still in flight.  Whole trips need no
-    // per-lane checks; a tail of fewer than 4G hits checks.
-    const int lg = wave * HPW + hsub;
+    // Staged hits [lo, hi) of this wavefront's region (lo, hi wave-uniform).
+    // An iteration covers 2G consecutive hits: lane group hsub takes hits
+    // it + hsub and it + G + hsub.  Two iterations per trip, the next pair
+    // read before the current votes are cast (two register sets, no copies),
+    // so waiting for a read never waits for atomics still in flight.  Whole
+    // trips need no per-lane checks; a tail of fewer than 4G hits checks.
+    float4 *region = ts.hits[wave];
     auto sweep_with = [&](int lo, int hi, auto fast, auto bits, auto fwd) {
         if (lo >= hi)
             return;
-        const float4 *hp = ts.hits + lg;
+        const float4 *hp = region + hsub;
         int it = lo;
         float4 a0 = hp[it], b0 = hp[it + G];
         for (; it + 4 * G <= hi; it += 4 * G) {
@@ -369,9 +364,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         }
         if (it < hi) {
             const float4 a1 = hp[it + 2 * G], b1 = hp[it + 3 * G];
-            eval2(a0, b0, it + lg < hi, it + G + lg < hi, fast, bits, fwd);
+            eval2(a0, b0, it + hsub < hi, it + G + hsub < hi, fast, bits, fwd);
             if (it + 2 * G < hi)
-                eval2(a1, b1, it + 2 * G + lg < hi, it + 3 * G + lg < hi, fast, bits, fwd);
+                eval2(a1, b1, it + 2 * G + hsub < hi, it + 3 * G + hsub < hi, fast, bits, fwd);
         }
     };
     // (the forward option is a kernel of its own: its variants inlined here
@@ -390,74 +385,57 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         return dt < static_cast<int>((r >> 16) & 0x7fffu);
     };
 
-    // Hit blocks: every thread loads kHitBlock/NT records of the next block
-    // (loads issued unconditionally, index clamped) while the current block is
-    // evaluated; whether a hit is kept is decided when it is staged.
-    constexpr int PER = kHitBlock / NT > 0 ? kHitBlock / NT : 1;
-    constexpr int STAGERS = kHitBlock / PER;    // threads that stage
-    float4 ph[PER];
-    uint2 pr[PER];
+    // Chunks: this wavefront's lanes load the records (and tile masks) of its
+    // next chunk while the current one is evaluated, test them against this
+    // tile, stage the kept ones in the wavefront's region and evaluate them.
+    // LDS operations of one wavefront complete in order, so no barrier is
+    // needed until the tile is done; fast hits short of a whole trip are
+    // carried into the next chunk, so only the last chunk has a partial trip.
+    const int64_t cstep = static_cast<int64_t>(NW) * kChunk;
+    int64_t c0 = h_begin + static_cast<int64_t>(wave) * kChunk;
+    float4 ph = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint2 pr = make_uint2(0u, 0u);
     // (always inlined, through a local: otherwise the 2D kernels kept the
     // prefetched records in a stack slot and waited for each load at once)
-    auto fetch = [&](int64_t b0) __attribute__((always_inline)) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int64_t h = min(b0 + q * STAGERS + tid, h_end - 1);
-            pr[q] = rrow[h & rmask];
-            const float4 v = hrec[h];
-            ph[q] = v;
-        }
+    auto fetch = [&](int64_t b) __attribute__((always_inline)) {
+        const int64_t h = min(b + lane, h_end - 1);
+        pr = rrow[h & rmask];
+        ph = hrec[h];
     };
-    if (h_begin < h_end)
-        fetch(h_begin);
-    int parity = 0;
+    if (c0 < h_end)
+        fetch(c0);
     int kept_here = 0;                           // hits this wavefront staged (pair counting only)
-    int carry = 0;                               // fast hits carried into this block
-    float4 carry_v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // this thread's carried hit (tid < carry)
-    for (int64_t b0 = h_begin; b0 < h_end; b0 += kHitBlock, parity ^= 1) {
-        lds_barrier();                         // the previous block is fully evaluated
-        if (tid < carry)
-            ts.hits[tid] = carry_v;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const bool mine = tid < STAGERS;
-            const bool hit_tile = mask_mode ? ((t < 32 ? pr[q].x >> t : pr[q].y >> (t - 32)) & 1u) != 0u
-                                            : (in_range(pr[q].x) || in_range(pr[q].y));
-            const bool keep = mine && b0 + q * STAGERS + tid < h_end && hit_tile;
-            const bool fast = D3 ? (pr[q].y & kFastDiv) != 0u : ph[q].w != 0.0f;
-            const uint64_t mf = __ballot(keep && fast);
-            const uint64_t ms = __ballot(keep && !fast);
-            kept_here += __popcll(mf | ms);
-            int bf = 0, bs = 0;
-            if (lane == 0 && mf)
-                bf = atomicAdd(&ts.n_kept[parity][0], __popcll(mf));
-            if (lane == 0 && ms)
-                bs = atomicAdd(&ts.n_kept[parity][1], __popcll(ms));
-            // every lane is active here, so the first lane is lane 0
-            bf = __builtin_amdgcn_readfirstlane(bf);
-            bs = __builtin_amdgcn_readfirstlane(bs);
-            const int slot = fast ? bf + rank_below(mf) : SLOW_END - 1 - (bs + rank_below(ms));
-            if (keep)
-                ts.hits[slot] = ph[q];
-        }
-        lds_barrier();
-        const int n_fast = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][0]);   // with the carried hits
-        const int n_slow = __builtin_amdgcn_readfirstlane(ts.n_kept[parity][1]);
-        const bool last = b0 + kHitBlock >= h_end;
+    int carry = 0;                               // fast hits carried into this chunk
+    lds_barrier();                               // the tile is zeroed
+    for (; c0 < h_end; c0 += cstep) {
+        const bool hit_tile = mask_mode ? ((t < 32 ? pr.x >> t : pr.y >> (t - 32)) & 1u) != 0u
+                                        : (in_range(pr.x) || in_range(pr.y));
+        const bool keep = c0 + lane < h_end && hit_tile;
+        const bool fast = D3 ? (pr.y & kFastDiv) != 0u : ph.w != 0.0f;
+        const uint64_t mf = __ballot(keep && fast);
+        const uint64_t ms = __ballot(keep && !fast);
+        kept_here += __popcll(mf | ms);
+        const int slot = fast ? carry + rank_below(mf) : kRegionSlow - 1 - rank_below(ms);
+        if (keep)
+            region[slot] = ph;
+        const int n_fast = carry + __popcll(mf);
+        const int n_slow = __popcll(ms);
+        const bool last = c0 + cstep >= h_end;
         const int whole = last ? n_fast : n_fast - n_fast % (4 * G);
-        const int carry_next = n_fast - whole;
-        if (tid < 2)
-            ts.n_kept[parity ^ 1][tid] = tid == 0 ? carry_next : 0;   // every thread passed the last barrier
-        if (tid < carry_next)
-            carry_v = ts.hits[whole + tid];      // nothing writes the staged hits until the next barrier
         if (!last)
-            fetch(b0 + kHitBlock);
+            fetch(c0 + cstep);
         if (near_band > 0.0f)
             sweep(0, whole, std::integral_constant<int, 2>{});
         else
             sweep(0, whole, std::true_type{});
-        sweep(SLOW_END - n_slow, SLOW_END, std::false_type{});
-        carry = carry_next;
+        sweep(kRegionSlow - n_slow, kRegionSlow, std::false_type{});
+        carry = n_fast - whole;
+        // the carried hits to the front (whole is 0 or at least 4G > carry:
+        // the two ranges do not overlap)
+        if (whole > 0 && lane < carry) {
+            const float4 v = region[whole + lane];
+            region[lane] = v;
+        }
     }
     lds_barrier();
     // Every staged hit is evaluated once per row of the tile (halo rows
