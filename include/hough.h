@@ -108,7 +108,7 @@ typedef struct {
 /* Context sizing.  Zero fields take the defaults noted. */
 typedef struct {
     int32_t max_events;      /* largest n_events of hough_event_batch (default 1) */
-    int64_t max_hits;        /* largest total hit count of one call (default 1<<20) */
+    int64_t max_hits;        /* largest total hit count of one call (default 1<<20, at most 1<<30) */
     const char *tune_cache;  /* JSON file of tuned launch shapes, or NULL */
 } hough_ctx_opts;
 
@@ -117,7 +117,8 @@ typedef struct hough_ctx hough_ctx;
 /* Create a context for one grid on the current HIP device.  The bin tables
  * must stay valid for the context's lifetime.  Allocates all workspace.
  * EINVAL: null pointers, n_phi < 3, n_kappa < 1, n_d0 < 1, n_d0 > 1 without a
- * d0 table, u16 with odd n_kappa, more than 2^31 - 1 cells. */
+ * d0 table, u16 with odd n_kappa, more than 2^31 - 1 cells, max_hits < 0 or
+ * above 2^30. */
 hough_status hough_ctx_create(hough_ctx **ctx, const hough_grid *grid, const hough_ctx_opts *opts);
 void hough_ctx_destroy(hough_ctx *ctx);
 
@@ -271,7 +272,7 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
  *             aligned, overwritten (the peak search reads it back).
  *   out:      [dev][cap] sorted candidates (NULL when cap == 0); n_found: [dev]
  *             int32 full count; n_votes: [dev] uint64 (8-byte aligned) or NULL.
- * Scratch (hit records, tile masks or ranges, per-event state, sort buffers)
+ * Scratch (hit records, tile words or ranges, per-event state, sort buffers)
  * is one fixed device array of HOUGH_NOALLOC_SCRATCH_BYTES inside the library,
  * held on every device it runs on until the process ends; the call allocates
  * and frees nothing.  It needs about 16 + 8*n_d0 bytes per hit plus 16 bytes

@@ -148,7 +148,7 @@ int32_t batch_tiles_per_event(const hough_ctx *c, const VoteShape &s, bool fused
     return c->g.n_d0 * vote_tiles_per_slice(c->g, s, fused);
 }
 
-// Tile masks instead of ranges when culling is on and a slice has few enough tiles.
+// Tile words instead of ranges when culling is on and a slice has few enough tiles.
 bool use_masks(const hough_ctx *c, const VoteShape &s, bool fused) {
     return c->cull_ok && vote_tile_geom(c->g, s, fused).tiles <= kMaskTiles;
 }
@@ -157,18 +157,19 @@ VoteInputs vote_inputs(const hough_ctx *c, const VoteShape &s, bool fused) {
     VoteInputs in{};
     in.hits = c->hits;
     in.ranges = c->cull_ok ? c->ranges : c->all_tiles;
-    in.range_stride = c->cull_ok ? c->max_hits : 0;
-    in.range_step = c->cull_ok ? 1 : 0;
     in.mask_mode = use_masks(c, s, fused) ? 1 : 0;
+    in.range_stride = !c->cull_ok ? 0 : in.mask_mode ? tile_word_stride(c->max_hits) : c->max_hits;
+    in.range_step = c->cull_ok ? 1 : 0;
     return in;
 }
 
-// Hit records (and tile ranges or masks) for a vote launch of shape s.
+// Hit records (and tile ranges or words) for a vote launch of shape s.
 hipError_t hit_prep(const hough_ctx *c, const VoteShape &s, bool fused, const float *x, const float *y,
                     int64_t n_hits, const int64_t *n_hits_dev, hipStream_t stream) {
+    const bool words = use_masks(c, s, fused);
     return launch_hit_prep(c->g, vote_tile_geom(c->g, s, fused), x, y, n_hits, n_hits_dev, c->hits,
-                           c->cull_ok ? c->ranges : nullptr, c->max_hits, c->cull_ok, use_masks(c, s, fused),
-                           nullptr, stream);
+                           c->cull_ok ? c->ranges : nullptr, words ? tile_word_stride(c->max_hits) : c->max_hits,
+                           c->cull_ok, words, nullptr, stream);
 }
 
 SortWork sort_work(const hough_ctx *c, bool fused_layout) {
@@ -354,7 +355,7 @@ int64_t hit_bucket(int64_t hits) {
 
 
 // The launch sequence of one batch (after the descriptor upload): reset,
-// tile masks, vote (fused with the peak search for 2D int32), sort.  With
+// tile words, vote (fused with the peak search for 2D int32), sort.  With
 // `timed`, events bracket the whole sequence and the vote kernel.
 hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const float *y, int32_t threshold,
                          void *acc, hough_cand *cands, int32_t *n_found, uint64_t *n_votes, int64_t *cand_start,
@@ -502,6 +503,8 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         o.max_events = 1;
     if (o.max_hits == 0)
         o.max_hits = 1 << 20;
+    if (o.max_hits > (int64_t{1} << 30))
+        return HOUGH_EINVAL;     // the vote kernels index hit records with 32 bits
 
     hough_ctx *c = new (std::nothrow) hough_ctx();
     if (!c)
@@ -587,7 +590,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     e = e ? e : dev_alloc(&c->acc_ws, E * static_cast<size_t>(g.acc_dwords));
     e = e ? e : dev_alloc(&c->hits, static_cast<size_t>(c->max_hits));
     if (c->cull_ok)
-        e = e ? e : dev_alloc(&c->ranges, static_cast<size_t>(g.n_d0) * static_cast<size_t>(c->max_hits));
+        e = e ? e : dev_alloc(&c->ranges, static_cast<size_t>(g.n_d0) * static_cast<size_t>(ranges_entries(c->max_hits)));
     e = e ? e : dev_alloc(&c->all_tiles, 1);
     e = e ? e : dev_alloc(&c->cell_map, static_cast<size_t>(g.cells));
     e = e ? e : dev_alloc(&c->cell_bits, static_cast<size_t>(g.n_d0) * static_cast<size_t>(g.n_phi) *

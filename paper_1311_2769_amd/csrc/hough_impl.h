@@ -124,7 +124,7 @@ struct VoteInputs {
     const uint2 *ranges;       // [n_d0][range_stride] tile ranges per hit, or one all-tiles entry
     int64_t range_stride;      // 0 with the all-tiles entry
     int32_t range_step;        // 1 with ranges, 0 with the all-tiles entry
-    int32_t mask_mode;         // per-hit entries are 64-bit tile masks (culling on, at most kMaskTiles tiles)
+    int32_t mask_mode;         // ranges holds transposed tile words (culling on, at most kMaskTiles tiles)
 };
 
 // A tile range packs first | count << 16 (tile indices of one d0 slice,
@@ -132,11 +132,16 @@ struct VoteInputs {
 // Bit 31 of a hit's second range is kFastDiv: every phi0 row of that (hit,
 // d0 slice) has its 3D quotient operands in the range of vote_math.h.
 constexpr uint32_t kAllTiles = 0x7fffu << 16;
-// With at most kMaskTiles tiles per slice a hit's entry is instead the 64-bit
-// mask of the tiles it can vote in (bit t: tile t; low dword first), and bit
-// 63 -- bit 31 of the high dword, where kFastDiv sits -- keeps that flag.
+// With at most kMaskTiles tiles T per slice the buffer holds instead, per d0
+// slice and 64-hit chunk of the record array, T + 1 transposed 64-bit words:
+// word t has bit k set when hit 64 chunk + k can vote in tile t, word T when
+// that (hit, slice) has the kFastDiv property.  Word (l, t, chunk) sits at
+// (l (T + 1) + t) tile_word_stride + chunk, 8 bytes like a range pair, so a
+// buffer of ranges_entries(max_hits) entries per slice holds either form.
 constexpr int32_t kMaskTiles = 63;
 constexpr uint32_t kFastDiv = 1u << 31;
+inline int64_t tile_word_stride(int64_t max_hits) { return (max_hits + 63) / 64; }
+inline int64_t ranges_entries(int64_t max_hits) { return max_hits + 64; }
 
 // Tile geometry of a vote launch: tile t of a slice owns phi0 rows
 // [t*stride, min((t+1)*stride, n_phi)); with halo it also votes the row

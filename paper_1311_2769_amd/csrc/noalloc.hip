@@ -1,6 +1,6 @@
 // hough_event_noalloc: one event's vote, peak search and sort without a
 // context and without allocating device memory.  The scratch the kernels need
-// (hit records, tile masks or ranges, the table flag, the per-event state and
+// (hit records, tile words or ranges, the table flag, the per-event state and
 // the sort buffers) lives in one file-scope device array of fixed size; the
 // caller passes the inputs and the outputs.  The kernels are the ones of
 // hough_vote and hough_peaks.
@@ -72,7 +72,7 @@ Layout layout(const GridArgs &g, int64_t n_hits) {
     L.flag = take(sizeof(int32_t));
     L.state = take(sizeof(EventState));
     L.hits = take(static_cast<size_t>(n_hits) * sizeof(float4));
-    L.ranges = take(static_cast<size_t>(g.n_d0) * static_cast<size_t>(n_hits) * sizeof(uint2));
+    L.ranges = take(static_cast<size_t>(g.n_d0) * static_cast<size_t>(ranges_entries(n_hits)) * sizeof(uint2));
     L.stage = take(static_cast<size_t>(L.bound) * sizeof(Cand));
     L.cnt0 = take(static_cast<size_t>(pb) * sizeof(int32_t));
     L.hist = take(static_cast<size_t>(L.hist_chunks) * kDigits * sizeof(uint32_t));
@@ -137,7 +137,7 @@ extern "C" hough_status hough_event_noalloc(const hough_grid *grid, const float 
     VoteInputs in{};
     in.hits = hits;
     in.ranges = ranges;
-    in.range_stride = n_hits;
+    in.range_stride = masks ? tile_word_stride(n_hits) : n_hits;
     in.range_step = 1;
     in.mask_mode = masks ? 1 : 0;
 
@@ -174,7 +174,7 @@ extern "C" hough_status hough_event_noalloc(const hough_grid *grid, const float 
     if (e == hipSuccess)
         e = launch_prep(state, 1, nv, s);
     if (e == hipSuccess)
-        e = launch_hit_prep(g, tg, x, y, n_hits, nullptr, hits, ranges, n_hits, true, masks, flag, s);
+        e = launch_hit_prep(g, tg, x, y, n_hits, nullptr, hits, ranges, in.range_stride, true, masks, flag, s);
     if (e == hipSuccess)
         e = launch_vote_single(g, u16, vs, in, n_hits, static_cast<uint32_t *>(acc), nv, s);
     if (e == hipSuccess)

@@ -82,7 +82,7 @@ struct VoteArgs {
     const uint2 *ranges;        // [n_d0][range_stride] tile ranges per hit; or one all-tiles entry (step 0)
     int64_t range_stride;
     int32_t range_step;         // 1 with ranges, 0 without
-    int32_t mask_mode;          // entries are 64-bit tile masks
+    int32_t mask_mode;          // ranges holds the transposed tile words (see hit_prep_kernel)
     int32_t n_hits;             // single event
     int32_t split;              // single event: hit chunks per tile
     int32_t tiles_per_slice;
@@ -385,57 +385,108 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         return dt < static_cast<int>((r >> 16) & 0x7fffu);
     };
 
-    // Chunks: this wavefront's lanes load the records (and tile masks) of its
-    // next chunk while the current one is evaluated, test them against this
-    // tile, stage the kept ones in the wavefront's region and evaluate them.
-    // LDS operations of one wavefront complete in order, so no barrier is
-    // needed until the tile is done; fast hits short of a whole trip are
-    // carried into the next chunk, so only the last chunk has a partial trip.
-    const int64_t cstep = static_cast<int64_t>(NW) * kChunk;
-    int64_t c0 = h_begin + static_cast<int64_t>(wave) * kChunk;
-    float4 ph = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    uint2 pr = make_uint2(0u, 0u);
-    // (always inlined, through a local: otherwise the 2D kernels kept the
-    // prefetched records in a stack slot and waited for each load at once)
-    auto fetch = [&](int64_t b) __attribute__((always_inline)) {
-        const int64_t h = min(b + lane, h_end - 1);
-        pr = rrow[h & rmask];
-        ph = hrec[h];
-    };
-    if (c0 < h_end)
-        fetch(c0);
+    // Chunks: 64 hits at a multiple of 64 of the record array (the first and
+    // last chunks of the range may hold other events' hits, which the range
+    // mask drops); chunk g0 + wave + k NW belongs to this wavefront.  Its
+    // lanes load the records of its next chunk (and the tile's word of it,
+    // or the per-hit ranges) while the current one is evaluated; the kept
+    // hits are staged in the wavefront's region and evaluated.  LDS
+    // operations of one wavefront complete in order, so no barrier is needed
+    // until the tile is done; fast hits short of a whole trip are carried
+    // into the next chunk, so only the last chunk has a partial trip.
+    // Record indices fit 32 bits (contexts hold at most 2^30 hits).
+    const int hb = static_cast<int>(h_begin);
+    const int he = static_cast<int>(h_end);
+    const int g_stop = (he + 63) >> 6;
+    const uint64_t *__restrict__ words = reinterpret_cast<const uint64_t *>(a.ranges);
+    const int64_t ws = a.range_stride;
     int kept_here = 0;                           // hits this wavefront staged (pair counting only)
-    int carry = 0;                               // fast hits carried into this chunk
     lds_barrier();                               // the tile is zeroed
-    for (; c0 < h_end; c0 += cstep) {
-        const bool hit_tile = mask_mode ? ((t < 32 ? pr.x >> t : pr.y >> (t - 32)) & 1u) != 0u
-                                        : (in_range(pr.x) || in_range(pr.y));
-        const bool keep = c0 + lane < h_end && hit_tile;
-        const bool fast = D3 ? (pr.y & kFastDiv) != 0u : ph.w != 0.0f;
-        const uint64_t mf = __ballot(keep && fast);
-        const uint64_t ms = __ballot(keep && !fast);
-        kept_here += __popcll(mf | ms);
-        const int slot = fast ? carry + rank_below(mf) : kRegionSlow - 1 - rank_below(ms);
-        if (keep)
-            region[slot] = ph;
-        const int n_fast = carry + __popcll(mf);
-        const int n_slow = __popcll(ms);
-        const bool last = c0 + cstep >= h_end;
-        const int whole = last ? n_fast : n_fast - n_fast % (4 * G);
-        if (!last)
-            fetch(c0 + cstep);
-        if (near_band > 0.0f)
-            sweep(0, whole, std::integral_constant<int, 2>{});
-        else
-            sweep(0, whole, std::true_type{});
-        sweep(kRegionSlow - n_slow, kRegionSlow, std::false_type{});
-        carry = n_fast - whole;
-        // the carried hits to the front (whole is 0 or at least 4G > carry:
-        // the two ranges do not overlap)
-        if (whole > 0 && lane < carry) {
-            const float4 v = region[whole + lane];
-            region[lane] = v;
+    auto chunks = [&](auto by_words) __attribute__((always_inline)) {
+        constexpr bool W = decltype(by_words)::value;
+        // With words, the word of a chunk is the same for every lane: loaded
+        // as a vector value (through zero_v, a zero the compiler cannot see
+        // through) and made scalar only where used, since a scalar copy right
+        // after the load would wait for it -- and the records -- at once.
+        int zero_v;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(zero_v));
+        const uint2 *__restrict__ wtile =
+            reinterpret_cast<const uint2 *>(words + (static_cast<int64_t>(l) * (T + 1) + t) * ws) + zero_v;
+        const uint2 *__restrict__ wflag =
+            reinterpret_cast<const uint2 *>(words + (static_cast<int64_t>(l) * (T + 1) + T) * ws) + zero_v;
+        float4 ph = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        uint2 pr = make_uint2(0u, 0u);           // the tile's word of the chunk, or the hit's ranges
+        uint2 pf = make_uint2(0u, 0u);           // 3D with words: the chunk's kFastDiv word
+        // (always inlined, through a local: otherwise the 2D kernels kept the
+        // prefetched records in a stack slot and waited for each load at once)
+        auto fetch = [&](int gg) __attribute__((always_inline)) {
+            const int h = min(max((gg << 6) + lane, hb), he - 1);
+            ph = hrec[h];
+            if constexpr (W) {
+                pr = wtile[gg];
+                if constexpr (D3)
+                    pf = wflag[gg];
+            } else {
+                pr = rrow[h & rmask];
+            }
+        };
+        auto uniform64 = [](uint2 v) {
+            const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v.x)));
+            const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v.y)));
+            return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+        };
+        int gc = (hb >> 6) + wave;
+        if (gc < g_stop)
+            fetch(gc);
+        int carry = 0;                           // fast hits carried into this chunk
+        for (; gc < g_stop; gc += NW) {
+            // lanes of the chunk inside [h_begin, h_end)
+            const int lo = hb - (gc << 6);
+            const int hi = he - (gc << 6);
+            uint64_t inside = hi >= 64 ? ~0ull : (1ull << hi) - 1ull;
+            if (lo > 0)
+                inside &= ~((1ull << lo) - 1ull);
+            uint64_t K, F;
+            if constexpr (W) {
+                K = uniform64(pr) & inside;
+                F = D3 ? uniform64(pf) : __ballot(ph.w != 0.0f);
+            } else {
+                K = __ballot(in_range(pr.x) || in_range(pr.y)) & inside;
+                F = __ballot(D3 ? (pr.y & kFastDiv) != 0u : ph.w != 0.0f);
+            }
+            const uint64_t mf = K & F;
+            const uint64_t ms = K & ~F;
+            kept_here += __popcll(K);
+            const bool keep = ((K >> lane) & 1ull) != 0ull;
+            const bool fast = ((F >> lane) & 1ull) != 0ull;
+            const int slot = fast ? carry + rank_below(mf) : kRegionSlow - 1 - rank_below(ms);
+            if (keep)
+                region[slot] = ph;
+            const int n_fast = carry + __popcll(mf);
+            const int n_slow = __popcll(ms);
+            const bool last = gc + NW >= g_stop;
+            const int whole = last ? n_fast : n_fast - n_fast % (4 * G);
+            if (!last)
+                fetch(gc + NW);
+            if (near_band > 0.0f)
+                sweep(0, whole, std::integral_constant<int, 2>{});
+            else
+                sweep(0, whole, std::true_type{});
+            sweep(kRegionSlow - n_slow, kRegionSlow, std::false_type{});
+            carry = n_fast - whole;
+            // the carried hits to the front (whole is 0 or at least 4G > carry:
+            // the two ranges do not overlap)
+            if (whole > 0 && lane < carry) {
+                const float4 v = region[whole + lane];
+                region[lane] = v;
+            }
         }
+    };
+    if (hb < he) {
+        if (mask_mode)
+            chunks(std::true_type{});
+        else
+            chunks(std::false_type{});
     }
     lds_barrier();
     // Every staged hit is evaluated once per row of the tile (halo rows
@@ -760,7 +811,7 @@ struct PrepArgs {
     int32_t straight;           // straight-line family: records (x, y, 1, 1), arcs from the d0 range
     int32_t forward;            // forward-hemisphere option: the first arc only
     float dlo, dhi;             // straight: the d0 range, rounded outwards
-    int32_t mask_mode;          // write 64-bit tile masks instead of ranges (tiles <= kMaskTiles)
+    int32_t mask_mode;          // write transposed tile words instead of ranges (tiles <= kMaskTiles)
     const int32_t *table_ok;    // device flag: the phi0 table holds the bin centres (else no arcs and no
                                 // fast division), or nullptr when the host has checked the table
 };
@@ -776,14 +827,6 @@ __device__ __forceinline__ uint64_t range_bits(uint32_t r, int T) {
     if (first + cnt <= T)
         return ((1ull << cnt) - 1ull) << first;
     return (((1ull << (T - first)) - 1ull) << first) | ((1ull << (first + cnt - T)) - 1ull);
-}
-
-// A hit's entry: the two ranges (and the kFastDiv flag), or their tile mask.
-__device__ __forceinline__ uint2 hit_entry(uint2 ranges, const PrepArgs &p) {
-    if (!p.mask_mode)
-        return ranges;
-    const uint64_t m = range_bits(ranges.x, p.tiles) | range_bits(ranges.y & ~kFastDiv, p.tiles);
-    return make_uint2(static_cast<uint32_t>(m), static_cast<uint32_t>(m >> 32) | (ranges.y & kFastDiv));
 }
 
 // 3D quotient range (every phi0 row of one hit and d0 slice): with a phi0
@@ -853,19 +896,24 @@ __device__ __forceinline__ uint32_t tile_range(uint32_t arc, const PrepArgs &p) 
 
 constexpr int kPrepSlices = 8;   // d0 slices per hit_prep thread (per-hit terms computed once)
 
-__global__ void hit_prep_kernel(PrepArgs p) {
+__global__ __launch_bounds__(256) void hit_prep_kernel(PrepArgs p) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = p.n_hits_dev ? *p.n_hits_dev : p.n_hits;
-    if (i >= n)
+    // With tile words every lane of a wavefront takes part in the ballots,
+    // live or not; dead lanes read nothing and set no bit.
+    const bool live = i < n;
+    if (!p.mask_mode && !live)
         return;
-    const float xf = p.x[i];
-    const float yf = p.y[i];
+    if (p.mask_mode && __ballot(live) == 0ull)
+        return;                              // no word of this wavefront's chunk exists
+    const float xf = live ? p.x[i] : 0.0f;
+    const float yf = live ? p.y[i] : 0.0f;
     const float r2 = xf * xf + yf * yf;
     const int l_begin = blockIdx.y * kPrepSlices;
     // Arcs and the fast division rest on a table of bin centres; without one
     // every (hit, slice) takes every tile and the division operator.
     const bool table = p.table_ok == nullptr || *p.table_ok != 0;
-    if (l_begin == 0) {
+    if (l_begin == 0 && live) {
         float4 rec = make_float4(xf, yf, r2, 0.0f);
         if (p.straight) {
             // the 2D fast path then computes kappa = quot_apply(u, 1, 1) = u
@@ -882,10 +930,32 @@ __global__ void hit_prep_kernel(PrepArgs p) {
     }
     if (!p.ranges)
         return;
+    // The (hit, slice) entry: per-hit ranges, or (mask_mode) the hit's bit in
+    // the transposed words of its 64-hit chunk g = i / 64 -- word t of slice l
+    // has bit k set when hit 64 g + k can vote in tile t, word T (the tile
+    // count) when its 3D quotients take the fast division.  Lane t < T writes
+    // tile t's word, lane T the flags.
+    const int lane = threadIdx.x & 63;
+    auto emit = [&](int l, uint2 out) {
+        if (!p.mask_mode) {
+            p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = out;
+            return;
+        }
+        const int T = p.tiles;
+        const uint64_t m = live ? (range_bits(out.x, T) | range_bits(out.y & ~kFastDiv, T)) : 0ull;
+        uint64_t mine = __ballot(live && (out.y & kFastDiv) != 0u);
+        for (int tt = 0; tt < T; ++tt) {
+            const uint64_t w = __ballot(((m >> tt) & 1ull) != 0ull);
+            mine = lane == tt ? w : mine;
+        }
+        uint64_t *words = reinterpret_cast<uint64_t *>(p.ranges);
+        if (lane <= T)
+            words[(static_cast<int64_t>(l) * (T + 1) + lane) * p.range_stride + (i >> 6)] = mine;
+    };
     if (!table) {
         const int l_stop = p.straight ? 1 : min(l_begin + kPrepSlices, p.d0 ? p.n_d0 : 1);
         for (int l = l_begin; l < l_stop; ++l)
-            p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = hit_entry(make_uint2(kAllTiles, 0u), p);
+            emit(l, make_uint2(kAllTiles, 0u));
         return;
     }
     const float r = sqrtf(r2);
@@ -928,7 +998,7 @@ __global__ void hit_prep_kernel(PrepArgs p) {
             const float m = 1e-5f + 0x1.0p-18f * (2.0f * fabsf(p.dlo) + 2.0f * fabsf(p.dhi)) * inv_r;
             out = arcs(p.dlo * inv_r - m, p.dhi * inv_r + m);
         }
-        p.ranges[i] = hit_entry(out, p);
+        emit(0, out);
         return;
     }
     for (int l = l_begin; l < l_end; ++l) {
@@ -948,7 +1018,7 @@ __global__ void hit_prep_kernel(PrepArgs p) {
         }
         if (p.d0 && p.div_fast && fast_div_3d(r, d, ad))
             out.y |= kFastDiv;
-        p.ranges[static_cast<int64_t>(l) * p.range_stride + i] = hit_entry(out, p);
+        emit(l, out);
     }
 }
 
@@ -1113,7 +1183,9 @@ bool vote_near_band(const GridArgs &g, float *band, float *off) {
     //   exact kf:  |kf - kf_r| <= u |P| (the quotient) + 2u |kf_r| (two roundings after it);
     //   kf1:       |kf1 - (kf_r + E)| <= 3u |P| (the reciprocal's 1 ulp, the product's
     //              rounding) + u (E + M) (off) + u |kf1| (the FMA), |kf1| <= K + 1;
-    // second-order terms fit in the factor 1 + 2^-20.  E is twice the sum.
+    // second-order terms fit in the factor 1 + 2^-20.  A lane outside the band
+    // [k, k + 2E) decides alike whenever E exceeds the sum (|kf1 - (kf + E)|
+    // < E, vote_math.h); E is the sum plus a quarter of margin.
     // Beyond the band (|kf_r| > K) the same relative bounds keep kf and kf1 out
     // of [0, n_kappa) while K + M <= 2^20.  kappa_scale in [2^-60, 2^60] keeps
     // the 2D hit constant w = RN(y kappa_scale) normal and finite.
@@ -1127,7 +1199,7 @@ bool vote_near_band(const GridArgs &g, float *band, float *off) {
         return false;
     const double u = 0x1.0p-24;
     const double ekf = (4.0 * u * (K + M) + 2.0 * u * K + u * (1.0 + M) + u * (K + 1.0)) * (1.0 + 0x1.0p-20);
-    const double E = 2.0 * ekf;
+    const double E = 1.25 * ekf;
     if (!(E <= 1.0 / 64.0))
         return false;
     float b = static_cast<float>(2.0 * E);

@@ -613,6 +613,35 @@ def test_counted_pairs_bound_the_work():
         np.testing.assert_array_equal(counted[e][3], base[e][3])
 
 
+def test_counted_pairs_are_the_culled_tiles():
+    """The pairs timing mode 2 counts are the kept (hit, tile) pairs times the
+    tile's voted rows, where a hit is kept by the tiles whose rows meet its
+    culling arcs -- redone on the CPU (tests/test_culling_cpu.py's binary32
+    emulation with correctly rounded angle functions; the device's are within
+    1e-6 rad, so a few boundary rows may differ).  Catches staging that keeps
+    hits a tile's arcs do not reach, which no result would show."""
+    from test_culling_cpu import arc_rows
+    b = synth.gen_batch(4, 2)
+    g = synth.GRID_2D
+    ctx = hough.HoughContext(g, max_events=2, max_hits=b.n_hits)
+    ctx.set_timing(2)
+    _batch_results(ctx, b, 7)
+    pairs = ctx.get_work()
+    ctx.set_timing(False)
+    rows, _, _ = ctx.get_launch(1)
+    S = rows - 2                                 # interior rows of a fused tile
+    T = -(-g.n_phi // S)
+    voted = []
+    for t in range(T):
+        s_here = min(S, g.n_phi - t * S)
+        voted.append({(t * S - 1 + k) % g.n_phi for k in range(s_here + 2)})
+    expect = 0
+    for xi, yi in zip(b.x, b.y):
+        R = arc_rows(xi, yi, g)[0]
+        expect += sum(len(v) for v in voted if not v.isdisjoint(R))
+    assert abs(pairs - expect) <= 2e-3 * expect, (pairs, expect)
+
+
 def test_division_fast_path_equals_the_operator():
     """The hoisted-reciprocal quotient equals fp32 division bit for bit (device self-test)."""
     _dev()
