@@ -72,6 +72,11 @@ def test_null_context_is_rejected_without_touching_the_device(lib):
     assert lib.hough_ctx_create(ctypes.byref(out), ctypes.byref(g), None) == EINVAL
     g = _Grid(1, 8, 8, -1.0, 4.0, 1, 1, None, 0, 0, 2)      # forward option is 0 or 1
     assert lib.hough_ctx_create(ctypes.byref(out), ctypes.byref(g), None) == EINVAL
+    from paper_1311_2769_amd.hough import _Opts
+    tab = (ctypes.c_float * 8)()
+    g = _Grid(1, 8, 8, -1.0, 4.0, ctypes.addressof(tab), ctypes.addressof(tab), None, 0)
+    for o in (_Opts(1, -1, None), _Opts(-1, 10, None), _Opts(1, (1 << 30) + 1, None)):
+        assert lib.hough_ctx_create(ctypes.byref(out), ctypes.byref(g), ctypes.byref(o)) == EINVAL
 
 
 def test_product_package_does_not_import_the_oracle():
