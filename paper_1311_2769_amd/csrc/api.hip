@@ -758,7 +758,7 @@ hough_status hough_associate(hough_ctx *ctx, const float *x, const float *y, int
         return HOUGH_EINVAL;
     HIP_TRY(launch_associate(ctx->g, x, y, n_hits, reinterpret_cast<const Cand *>(cands), n_cands, cands_cap,
                              min_votes, ctx->cell_map, ctx->cell_bits, ctx->hits, ctx->assoc_hist, pairs, cap,
-                             reinterpret_cast<unsigned long long *>(n_pairs),
+                             reinterpret_cast<unsigned long long *>(n_pairs), ctx->cull_ok,
                              static_cast<hipStream_t>(stream)));
     return HOUGH_OK;
 }

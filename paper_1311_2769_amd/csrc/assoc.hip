@@ -4,10 +4,13 @@
 // of C's window (lc + dl, jc + dj, kc + dk), dl, dj, dk in {-1, 0, 1}: phi0
 // modulo n_phi, d0 and kappa inside the grid -- the window of the peak rule.
 //
-// The vote is recomputed here in its plain binary32 form, operation for
-// operation the definition in hough.h (this file is compiled with
-// -ffp-contract=off; the division is the correctly rounded operator, the
-// range test the compare form), with the grid's family and forward option.
+// The vote is recomputed here with the grid's family and forward option: in
+// its plain binary32 form, operation for operation the definition in hough.h
+// (this file is compiled with -ffp-contract=off; the division is the
+// correctly rounded operator, the range test the compare form), or -- for
+// prompt 2D grids with a phi0 table of bin centres -- as the vote kernels do
+// it, an approximate bin from one FMA and that exact form wherever the
+// estimate cannot decide (vote_math.h), which gives the same bins.
 //
 // Layout: the context's cell map holds, per cell, 1 + the index of the
 // candidate there (0: none), and a bitmap of the cells that hold one: per
@@ -32,6 +35,7 @@
 #include <algorithm>
 
 #include "assoc.h"
+#include "vote_math.h"
 
 namespace hough {
 namespace {
@@ -62,6 +66,7 @@ struct AssocArgs {
     int32_t *pairs;                // [cap][2] (candidate, hit)
     int64_t cap;
     unsigned long long *n_pairs;
+    int32_t approx;                // approximate bins with exact redos (phi0 table of bin centres, near_band > 0)
 };
 
 // Azimuth bucket of a hit (NaN and the origin go to bucket 0).
@@ -182,41 +187,84 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
     }
     // The hit's kappa bins of slice ll over the ring rows: the vote of hough.h,
     // operation for operation (-1: no vote, or a slice outside the grid).
+    auto exact_bin = [&](int k, bool ok, float d, float d2, float dd) {
+        if constexpr (STRAIGHT) {
+            const float kf = (u[k] - kmin) * kscale;
+            return (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
+        } else {
+            const float num = 2.0f * (u[k] - d);
+            const float den = (rec.z - d2 * u[k]) + dd;
+            const float kappa = num / den;
+            const float kf = (kappa - kmin) * kscale;
+            return (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
+        }
+    };
+    // The bins are kept biased: b + 1 for a vote in bin b, kNoBin for none.
+    // Then kc is within one of b exactly when (b + 1) - kc, as unsigned, is at
+    // most 2 -- kNoBin, far below zero, never is.
+    constexpr int kNoBin = -(1 << 20);
+    auto biased = [](int b) { return b >= 0 ? b + 1 : kNoBin; };
+    // 2D: approximate bins with exact redos, as in the vote (vote_math.h):
+    // kf1 = RN(u w + off) with the hit constant w = RN(y kappa_scale), y the
+    // refined reciprocal of r2/2 (in the range of quot_den_ok), and the exact
+    // bin only where kf1 lies within the band above an integer (the redo
+    // divides with the operator).  The displaced grid keeps the exact form:
+    // with u hoisted per row its quotient is not the larger part of a bin,
+    // and the estimate measured slower there (4.03 against 3.85 ms on the
+    // displaced event).
+    const bool approx = !D3 && !STRAIGHT && a.approx != 0 && g.d0 == nullptr;
+    const float band = g.near_band;
+    const float kf_off = g.kf_off;
+    const uint32_t lim_bits = __float_as_uint(nkf + 0.5f);
+    const float half = 0.5f * rec.z;
+    const bool fast2d = approx && quot_den_ok(half);
+    const float w2d = fast2d ? quot_recip(half) * kscale : 0.0f;
     auto fill_slice = [&](int ll, int (&B)[R + 2]) {
         const bool ok = ll >= 0 && ll < n_d0;
         const float d = (ok && g.d0) ? g.d0[ll] : 0.0f;     // a one-slice grid may carry a d0 table
         const float d2 = 2.0f * d;
         const float dd = d * d;
+        if (!approx) {
+#pragma unroll
+            for (int k = 0; k < R + 2; ++k)
+                B[k] = biased(exact_bin(k, ok, d, d2, dd));
+            return;
+        }
+        bool redo[R + 2];
+        bool any = false;
 #pragma unroll
         for (int k = 0; k < R + 2; ++k) {
-            if constexpr (STRAIGHT) {
-                const float kf = (u[k] - kmin) * kscale;
-                B[k] = (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
-            } else {
-                const float num = 2.0f * (u[k] - d);
-                const float den = (rec.z - d2 * u[k]) + dd;
-                const float kappa = num / den;
-                const float kf = (kappa - kmin) * kscale;
-                B[k] = (ok && votes[k] && kf >= 0.0f && kf < nkf) ? static_cast<int>(kf) : -1;
-            }
+            const float kf1 = kf_offset_2d(u[k], w2d, kf_off);
+            const bool live = ok && votes[k];
+            const float v = kf_clamp(live ? kf1 : __builtin_nanf(""), lim_bits);
+            const int b = static_cast<int>(v);
+            B[k] = b < nk ? b + 1 : kNoBin;
+            redo[k] = live && (!fast2d || kf_in_band(v, band));
+            any |= redo[k];
+        }
+        if (__ballot(any)) {
+#pragma unroll
+            for (int k = 0; k < R + 2; ++k)
+                if (redo[k])
+                    B[k] = biased(exact_bin(k, ok, d, d2, dd));
         }
     };
     int B0[R + 2], B1[R + 2], B2[R + 2];
 #pragma unroll
     for (int k = 0; k < R + 2; ++k)
-        B0[k] = -1;
+        B0[k] = kNoBin;
     fill_slice(0, B1);
     if constexpr (D3)
         fill_slice(1, B2);
     else
 #pragma unroll
         for (int k = 0; k < R + 2; ++k)
-            B2[k] = -1;
+            B2[k] = kNoBin;
 
     for (int l = 0; l < n_d0; ++l) {
-        // column extremes over the three slices: the largest bin (invalid -1
-        // never wins) and, as unsigned, the smallest valid one (-1 is the
-        // largest unsigned value)
+        // column extremes over the three slices: the largest biased bin (kNoBin
+        // never wins) and, as unsigned, the smallest valid one (kNoBin is
+        // larger than any as unsigned)
         int cmax[R + 2];
         uint32_t cmin[R + 2];
 #pragma unroll
@@ -237,9 +285,10 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
             const int vmax = max(max(cmax[r], cmax[r + 1]), cmax[r + 2]);
             const uint32_t vmin_u = min(min(cmin[r], cmin[r + 1]), cmin[r + 2]);
             const bool any = jc < np && vmax >= 0;
-            // candidates of row (l, jc) in [vmin - 1, vmax + 1], 32 bins at a time
-            const int k_lo = any ? max(static_cast<int>(vmin_u) - 1, 0) : 0;
-            const int k_hi = any ? min(vmax + 1, nk - 1) : -1;
+            // candidates of row (l, jc) in [min b - 1, max b + 1] (b the
+            // unbiased bins), 32 bins at a time
+            const int k_lo = any ? max(static_cast<int>(vmin_u) - 2, 0) : 0;
+            const int k_hi = any ? min(vmax, nk - 1) : -1;
             const uint32_t *brow = brow0 + static_cast<int64_t>(any ? jc : 0) * a.row_words;
             for (int base = k_lo; __ballot(base <= k_hi); base += 32) {
                 uint32_t pend = 0u;
@@ -263,10 +312,10 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
                         bool near = false;
 #pragma unroll
                         for (int t = 0; t < 3; ++t) {
-                            near |= B1[r + t] >= 0 && abs(B1[r + t] - kc) <= 1;
+                            near |= static_cast<uint32_t>(B1[r + t] - kc) <= 2u;
                             if constexpr (D3) {
-                                near |= B0[r + t] >= 0 && abs(B0[r + t] - kc) <= 1;
-                                near |= B2[r + t] >= 0 && abs(B2[r + t] - kc) <= 1;
+                                near |= static_cast<uint32_t>(B0[r + t] - kc) <= 2u;
+                                near |= static_cast<uint32_t>(B2[r + t] - kc) <= 2u;
                             }
                         }
                         if (near) {
@@ -302,7 +351,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
 hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, int32_t n_hits, const Cand *cands,
                             const int32_t *n_found, int32_t cands_cap, int32_t min_votes, int32_t *map, uint32_t *bits,
                             float4 *sorted, int32_t *hist, int32_t *pairs, int64_t cap,
-                            unsigned long long *n_pairs, hipStream_t stream) {
+                            unsigned long long *n_pairs, bool approx, hipStream_t stream) {
     const int64_t row_words = assoc_row_words(g.n_kappa);
     hipError_t e = launch_zero(reinterpret_cast<uint32_t *>(map), g.cells, stream);
     if (e != hipSuccess)
@@ -345,6 +394,7 @@ hipError_t launch_associate(const GridArgs &g, const float *x, const float *y, i
     a.pairs = pairs;
     a.cap = cap;
     a.n_pairs = n_pairs;
+    a.approx = approx && g.near_band > 0.0f ? 1 : 0;
     // rows per thread: measured best on the workload grids (2D 32, 3D 4)
     const bool d3 = g.n_d0 > 1;
     const int R = d3 ? 4 : 32;

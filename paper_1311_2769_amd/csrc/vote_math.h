@@ -60,6 +60,26 @@ __device__ __forceinline__ float quot_apply(float a, float b, float y) {
     return __builtin_fmaf(r1, y, q1);
 }
 
+// 3D quotient range (every phi0 row of one hit and d0 slice): with a phi0
+// table of bin centres, r in [2^-8, 2^10], d = 0 or |d| in [2^-20, 2^10] and
+// |r - |d|| >= 0.03 (r + |d|):
+//   den = |h - P0|^2 up to fp32 rounding (2^-21 (r + |d|)^2 absolute) lies in
+//   [(r - |d|)^2, (r + |d|)^2] widened by that, i.e. within
+//   [0.0009 (r + |d|)^2 (1 - 2^-10), 2^22 (1 + 2^-20)], a subset of
+//   [2^-27, 2^23] and so of [2^-30, 2^30];
+//   num = 2 (u - d) with |u| <= r (1 + 1e-6): |num| <= 2^12; a nonzero u - d
+//   is at least 2^-45 (d = 0: u >= 2^-54 as in the 2D case; |d| >= 2^-20:
+//   either |u| < |d| / 2 and |u - d| > 2^-21, or both magnitudes are at
+//   least 2^-21 and the difference is a nonzero multiple of 2^-45), so every
+//   nonzero numerator is in [2^-60, 2^30]; a zero numerator moves no vote.
+// The test takes the fp32 r (within 3 2^-24 relative of the real one) with
+// bounds pulled in by 2^-20 and the stricter 0.0301, so it implies the above.
+__device__ __forceinline__ bool fast_div_3d(float r, float d, float ad) {
+    const bool r_ok = r >= 0x1.00001p-8f && r <= 0x1.ffffep9f;
+    const bool d_ok = d == 0.0f || (ad >= 0x1.0p-20f && ad <= 0x1.0p10f);
+    return r_ok && d_ok && fabsf(r - ad) >= 0.0301f * (r + ad);
+}
+
 // Approximate bins with exact redos.  The exact fractional bin is
 //   2D: kf = RN(RN(q - kappa_min) kappa_scale),     q = RN(u / h),
 //   3D: kf = RN(RN(2 q - kappa_min) kappa_scale),   q = RN(num / den),
