@@ -136,7 +136,8 @@ constexpr uint32_t kAllTiles = 0x7fffu << 16;
 // slice and 64-hit chunk of the record array, T + 1 transposed 64-bit words:
 // word t has bit k set when hit 64 chunk + k can vote in tile t, word T when
 // that (hit, slice) has the kFastDiv property.  Word (l, t, chunk) sits at
-// (l (T + 1) + t) tile_word_stride + chunk, 8 bytes like a range pair, so a
+// (l tile_word_stride + chunk) (T + 1) + t -- the words of one chunk side by
+// side, so hit_prep stores them at once -- 8 bytes like a range pair, so a
 // buffer of ranges_entries(max_hits) entries per slice holds either form.
 constexpr int32_t kMaskTiles = 63;
 constexpr uint32_t kFastDiv = 1u << 31;

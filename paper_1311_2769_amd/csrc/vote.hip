@@ -410,10 +410,11 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         // after the load would wait for it -- and the records -- at once.
         int zero_v;
         asm volatile("v_mov_b32 %0, 0" : "=v"(zero_v));
+        const int wstep = T + 1;                 // words of one chunk
         const uint2 *__restrict__ wtile =
-            reinterpret_cast<const uint2 *>(words + (static_cast<int64_t>(l) * (T + 1) + t) * ws) + zero_v;
+            reinterpret_cast<const uint2 *>(words + static_cast<int64_t>(l) * ws * wstep + t) + zero_v;
         const uint2 *__restrict__ wflag =
-            reinterpret_cast<const uint2 *>(words + (static_cast<int64_t>(l) * (T + 1) + T) * ws) + zero_v;
+            reinterpret_cast<const uint2 *>(words + static_cast<int64_t>(l) * ws * wstep + T) + zero_v;
         float4 ph = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         uint2 pr = make_uint2(0u, 0u);           // the tile's word of the chunk, or the hit's ranges
         uint2 pf = make_uint2(0u, 0u);           // 3D with words: the chunk's kFastDiv word
@@ -423,9 +424,9 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             const int h = min(max((gg << 6) + lane, hb), he - 1);
             ph = hrec[h];
             if constexpr (W) {
-                pr = wtile[gg];
+                pr = wtile[gg * wstep];
                 if constexpr (D3)
-                    pf = wflag[gg];
+                    pf = wflag[gg * wstep];
             } else {
                 pr = rrow[h & rmask];
             }
@@ -930,7 +931,7 @@ __global__ __launch_bounds__(256) void hit_prep_kernel(PrepArgs p) {
         }
         uint64_t *words = reinterpret_cast<uint64_t *>(p.ranges);
         if (lane <= T)
-            words[(static_cast<int64_t>(l) * (T + 1) + lane) * p.range_stride + (i >> 6)] = mine;
+            words[(static_cast<int64_t>(l) * p.range_stride + (i >> 6)) * (T + 1) + lane] = mine;
     };
     if (!table) {
         const int l_stop = p.straight ? 1 : min(l_begin + kPrepSlices, p.d0 ? p.n_d0 : 1);
