@@ -94,10 +94,11 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def counter_fields():
-    """Per-dispatch counters of the vote kernel from the committed summary:
-    (HBM bytes per launch, VALU wave-instructions per launch), each None when
-    missing or taken from other kernel sources."""
+def counter_fields(rows, threads):
+    """Per-dispatch counters of the vote kernel at launch shape rows x threads
+    from the committed summary: (HBM bytes per launch, VALU wave-instructions
+    per launch), each None when missing, taken at another shape or from other
+    kernel sources.  Fields carry the shape as a suffix (`_64x1024`)."""
     try:
         with open(COUNTERS) as f:
             fields = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
@@ -106,15 +107,16 @@ def counter_fields():
     fields = {k.strip().strip("-* `"): v.strip().strip("` ") for k, v in fields.items()}
     if fields.get("kernel_source_sha256") != kernel_digest():
         return None, None
+    sfx = f"_{rows}x{threads}"
     traffic = valu = None
     try:
-        fetch = float(fields["fetch_kib_per_dispatch"]) * float(fields["fetch_scale"])
-        write = float(fields["write_kib_per_dispatch"]) * float(fields["write_scale"])
+        fetch = float(fields["fetch_kib_per_dispatch" + sfx]) * float(fields["fetch_scale"])
+        write = float(fields["write_kib_per_dispatch" + sfx]) * float(fields["write_scale"])
         traffic = 1024.0 * (fetch + write)
     except (KeyError, ValueError):
         pass
     try:
-        valu = float(fields["valu_insts_per_dispatch"])
+        valu = float(fields["valu_insts_per_dispatch" + sfx])
     except (KeyError, ValueError):
         pass
     return traffic, valu
@@ -704,7 +706,7 @@ def main():
     achieved = pairs * VALU_PER_PAIR_2D / t_vote
     log("throughput probes")
     lds_peak_meas, valu_peak_meas = hough.diag_rates()
-    traffic, valu_insts = counter_fields()
+    traffic, valu_insts = counter_fields(rows, threads)
     vote_rate = votes / t_vote
     roofline = {"bound": "alu", "kernel": "vote_kernel (batched, persistent, fused peak search)",
                 "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "T VALU-ops/s",
