@@ -575,6 +575,38 @@ def test_batch_tile_shapes_agree():
     np.testing.assert_array_equal(base[2][3], rc)
 
 
+@pytest.mark.parametrize("grid_name,shape", [("2d", (32, 512)), ("2d", (64, 1024)), ("3d", (64, 512))])
+def test_batch_events_straddling_hit_chunks(grid_name, shape):
+    """Events of 0, 1, 63, 64, 65, 127, 129 ... hits packed back to back: the
+    vote stages hits in chunks at multiples of 64 of the record array, so
+    most events start and end inside a chunk shared with their neighbours,
+    and tile words of other events' hits must not leak into them."""
+    print(f"[parity] straddling events {grid_name} {shape}", flush=True)
+    d3 = grid_name == "3d"
+    src = synth.gen_config_event(3 if d3 else 2)
+    rng = np.random.default_rng(64)
+    sizes = [0, 1, 65, 129, 500, 63] if d3 else [0, 1, 63, 64, 65, 127, 129, 700, 0, 2000, 31, 3]
+    events = []
+    for n in sizes:
+        pick = rng.choice(src.n_hits, size=n, replace=False)
+        events.append((src.x[pick], src.y[pick]))
+    hit_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.concatenate([e[0] for e in events]).astype(np.float32)
+    y = np.concatenate([e[1] for e in events]).astype(np.float32)
+    g = synth.GRID_3D if d3 else synth.GRID_2D
+    thr = 5 if d3 else 2
+    b = dataclasses.make_dataclass("B", ["x", "y", "hit_off", "n_events"])(x, y, hit_off, len(sizes))
+    ctx = hough.HoughContext(g, max_events=len(sizes), max_hits=max(int(hit_off[-1]), 1))
+    ctx.set_launch(1, shape[0], shape[1], 1)
+    res = _batch_results(ctx, b, thr)
+    for e, (ex, ey) in enumerate(events):
+        ra, rnv, rv, rc, rn = oracle.find(ex, ey, g, thr)
+        nv, nf, v, c = res[e]
+        assert (nv, nf) == (rnv, rn), (e, sizes[e])
+        np.testing.assert_array_equal(c, rc[:len(c)])
+        np.testing.assert_array_equal(v, rv[:len(v)])
+
+
 def test_timing_mode_gives_the_same_results():
     b = synth.gen_batch(4, 5)
     ctx = hough.HoughContext(synth.GRID_2D, max_events=5, max_hits=b.n_hits)
