@@ -145,7 +145,7 @@ void free_ctx(hough_ctx *c) {
 }
 
 int32_t batch_tiles_per_event(const hough_ctx *c, const VoteShape &s, bool fused) {
-    return c->g.n_d0 * vote_tiles_per_slice(c->g, s, fused);
+    return vote_slice_units(c->g, c->u16) * vote_tiles_per_slice(c->g, s, fused);
 }
 
 // Tile words instead of ranges when culling is on and a slice has few enough tiles.
@@ -577,7 +577,8 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     const size_t E = static_cast<size_t>(c->max_events);
     int32_t max_tpe = 0;
     for (int32_t rows : kBatchRows)
-        max_tpe = std::max(max_tpe, g.n_d0 * vote_tiles_per_slice(g, VoteShape{rows, 256, 1}, c->fused_batch));
+        max_tpe = std::max(max_tpe, vote_slice_units(g, c->u16) *
+                                        vote_tiles_per_slice(g, VoteShape{rows, 256, 1}, c->fused_batch));
     c->max_items = static_cast<int32_t>(E) * max_tpe;
     c->desc_bytes = sizeof(BatchHeader) + E * sizeof(EventDesc) + static_cast<size_t>(c->max_items) * sizeof(WorkItem);
 

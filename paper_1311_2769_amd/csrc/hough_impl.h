@@ -171,6 +171,12 @@ size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa);
 // when the grid is outside the range the bound covers.
 bool vote_near_band(const GridArgs &g, float *band, float *off);
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
+// Slice units of a vote launch: uint16 grids with a d0 axis take their d0
+// slices in pairs (one LDS tile counts the cells of both), others one at a
+// time.  A launch has units x tiles_per_slice tiles per event.
+inline int32_t vote_slice_units(const GridArgs &g, bool u16) {
+    return (u16 && g.d0) ? (g.n_d0 + 1) / 2 : g.n_d0;
+}
 TileGeom vote_tile_geom(const GridArgs &g, const VoteShape &s, bool fused);
 int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);
 

@@ -125,8 +125,17 @@ __device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Vote hits [h_begin, h_end) of event e into tile t of d0 slice l, then either
-// flush it (unfused) or search its interior rows for peaks (fused).
+// Vote hits [h_begin, h_end) of event e into tile t of slice unit l, then
+// either flush it (unfused) or search its interior rows for peaks (fused).
+// A slice unit is one d0 slice, or with uint16 cells on a d0 grid two
+// (slice pairs: slices 2l and 2l + 1, the second absent past the grid).
+//
+// Slice pairs.  A uint16 event holds at most 65535 hits and a cell takes at
+// most one vote per hit, so an LDS dword can count the cell (kappa, row) of
+// both slices: the first in its low half, the second in its high half (adds
+// of 1 and of 0x10000 never carry into each other).  The tile then covers
+// two slices in the LDS of one, every staged hit serves both, and u =
+// y c - x s of a (hit, row) is computed once for the two bins.
 template <bool U16, bool D3, int ROWS, int NT, bool FUSED, bool FWD>
 __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begin, int64_t h_end,
                           uint32_t *__restrict__ acc_event, bool atomic_flush, unsigned long long *n_votes,
@@ -183,12 +192,19 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         s[i] = live ? g.sin_phi[j] : __builtin_nanf("");
         rowoff[i] = r;
     }
-    const float d = D3 ? g.d0[l] : 0.0f;
+    constexpr bool SP = U16 && D3;               // slice pairs
+    const int l0 = SP ? 2 * l : l;               // the (first) d0 slice
+    const bool has1 = SP && l0 + 1 < g.n_d0;     // the pair's second slice exists
+    const float d = D3 ? g.d0[l0] : 0.0f;
+    // an absent second slice takes d = NaN: every bin of it misses
+    const float d_1 = has1 ? g.d0[l0 + 1] : __builtin_nanf("");
     // Let the row constants land now: the memory counter is in order, so a
     // first use inside the hit loop would also wait for the hit prefetches.
     __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
     const float d2 = 2.0f * d;
     const float dd = d * d;
+    const float d2_1 = 2.0f * d_1;
+    const float dd_1 = d_1 * d_1;
     const float kmin = g.kappa_min;
     const float kscale = g.kappa_scale;
     const int trash = nk_cols;                                 // bin index of the spare column
@@ -196,7 +212,8 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     int trash_v;
     asm volatile("v_mov_b32 %0, %1" : "=v"(trash_v) : "s"(trash));
     const float4 *__restrict__ hrec = a.hits;
-    const uint2 *__restrict__ rrow = a.ranges + static_cast<int64_t>(l) * a.range_stride;
+    const uint2 *__restrict__ rrow = a.ranges + static_cast<int64_t>(l0) * a.range_stride;
+    const uint2 *__restrict__ rrow1 = has1 ? rrow + a.range_stride : rrow;
     const int64_t rmask = a.range_step ? -1 : 0;   // per-hit ranges, or the one all-tiles entry
     const bool mask_mode = a.mask_mode != 0;
 
@@ -236,11 +253,22 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             return valid;
         }
     };
-    auto bin = [&](const float4 &h, int i, bool valid, auto fast, auto bits, auto fwd) -> int {
+    // Slice constants (d, 2d, d*d) of the unit's first or second slice.
+    auto sconst = [&](auto sl) {
+        if constexpr (decltype(sl)::value)
+            return make_float3(d_1, d2_1, dd_1);
+        else
+            return make_float3(d, d2, dd);
+    };
+    using S0 = std::false_type;
+    using S1 = std::true_type;
+    auto bin = [&](const float4 &h, int i, bool valid, auto fast, auto bits, auto fwd, auto sl) -> int {
         valid = ahead(h, i, valid, fwd);
         const float u = h.y * c[i] - h.x * s[i];
         float kappa;
         if constexpr (D3) {
+            const float3 sc = sconst(sl);
+            const float d = sc.x, d2 = sc.y, dd = sc.z;
             const float den = (h.z - d2 * u) + dd;
             if constexpr (decltype(fast)::value) {
                 // In range, 2(u - d) / den = 2 ((u - d) / den) exactly (scaling a
@@ -275,11 +303,13 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         asm volatile("v_mov_b32 %0, %1" : "=v"(kf_off) : "s"(g.kf_off));
     }
     auto bin_approx = [&](const float4 &h, int i, bool valid, auto bits, auto fwd, float &num, float &den,
-                          bool &near) -> int {
+                          bool &near, auto sl) -> int {
         valid = ahead(h, i, valid, fwd);
         const float u = h.y * c[i] - h.x * s[i];
         float kf1;
         if constexpr (D3) {
+            const float3 sc = sconst(sl);
+            const float d = sc.x, d2 = sc.y, dd = sc.z;
             num = u - d;
             den = (h.z - d2 * u) + dd;
             kf1 = kf_offset_3d(num, den, kscale2, kf_off);
@@ -294,25 +324,32 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     auto bin_exact = [&](float num, float den, int i, bool valid, auto bits) -> int {
         return bin_of(D3 ? kf_exact_3d(num, den, kmin, kscale) : kf_exact_2d(num, den, kmin, kscale), i, valid, bits);
     };
-    auto vote = [&](int kk, int i) { lds_add(&lds[kk * stride + rowoff[i]], 1u); };
-    // Evaluate and vote two hits of this lane group (valid: the hit exists).
-    // fast: 0 the division operator, 1 the hoisted exact quotient, 2 the
-    // approximate bins with exact redos.
+    auto vote = [&](int kk, int i, uint32_t one) { lds_add(&lds[kk * stride + rowoff[i]], one); };
+    // Evaluate and vote two hits of this lane group (valid: the hit exists):
+    // fast 0 the division operator, 1 the hoisted exact quotient, 2 the
+    // approximate bins with exact redos.  With slice pairs each (hit, row)
+    // takes a bin in both slices; u is computed once for the two (the same
+    // operations on the same operands), and one wave-uniform branch redoes
+    // the lanes of either slice.
     auto eval2 = [&](const float4 &ha, const float4 &hb, bool va, bool vb, auto fast, auto bits, auto fwd) {
-        int ka[RPT], kb[RPT];
+        int ka[RPT], kb[RPT], ka1[RPT], kb1[RPT];
         if constexpr (decltype(fast)::value == 2) {
-            float na[RPT], da[RPT], nb[RPT], db[RPT];
-            bool fa[RPT], fb[RPT];
-            bool any_a = false, any_b = false;
+            float na[RPT], da[RPT], nb[RPT], db[RPT], na1[RPT], da1[RPT], nb1[RPT], db1[RPT];
+            bool fa[RPT], fb[RPT], fa1[RPT], fb1[RPT];
+            bool any = false;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                ka[i] = bin_approx(ha, i, va, bits, fwd, na[i], da[i], fa[i]);
-                kb[i] = bin_approx(hb, i, vb, bits, fwd, nb[i], db[i], fb[i]);
-                any_a |= fa[i];
-                any_b |= fb[i];
+                ka[i] = bin_approx(ha, i, va, bits, fwd, na[i], da[i], fa[i], S0{});
+                kb[i] = bin_approx(hb, i, vb, bits, fwd, nb[i], db[i], fb[i], S0{});
+                any |= fa[i] || fb[i];
+                if constexpr (SP) {
+                    ka1[i] = bin_approx(ha, i, va, bits, fwd, na1[i], da1[i], fa1[i], S1{});
+                    kb1[i] = bin_approx(hb, i, vb, bits, fwd, nb1[i], db1[i], fb1[i], S1{});
+                    any |= fa1[i] || fb1[i];
+                }
             }
             // one wave-uniform branch for both hits, so their chains interleave
-            if (__ballot(any_a || any_b)) {
+            if (__ballot(any)) {
                 if constexpr (!D3) {
                     // the 2D denominator r2/2 is the hit's own
 #pragma unroll
@@ -327,19 +364,33 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
                         ka[i] = bin_exact(na[i], da[i], i, va, bits);
                     if (fb[i])
                         kb[i] = bin_exact(nb[i], db[i], i, vb, bits);
+                    if constexpr (SP) {
+                        if (fa1[i])
+                            ka1[i] = bin_exact(na1[i], da1[i], i, va, bits);
+                        if (fb1[i])
+                            kb1[i] = bin_exact(nb1[i], db1[i], i, vb, bits);
+                    }
                 }
             }
         } else {
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                ka[i] = bin(ha, i, va, fast, bits, fwd);
-                kb[i] = bin(hb, i, vb, fast, bits, fwd);
+                ka[i] = bin(ha, i, va, fast, bits, fwd, S0{});
+                kb[i] = bin(hb, i, vb, fast, bits, fwd, S0{});
+                if constexpr (SP) {
+                    ka1[i] = bin(ha, i, va, fast, bits, fwd, S1{});
+                    kb1[i] = bin(hb, i, vb, fast, bits, fwd, S1{});
+                }
             }
         }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            vote(ka[i], i);
-            vote(kb[i], i);
+            vote(ka[i], i, 1u);
+            vote(kb[i], i, 1u);
+            if constexpr (SP) {
+                vote(ka1[i], i, 0x10000u);
+                vote(kb1[i], i, 0x10000u);
+            }
         }
     };
     // Staged hits [lo, hi) of this wavefront's region (lo, hi wave-uniform).
@@ -411,13 +462,16 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         int zero_v;
         asm volatile("v_mov_b32 %0, 0" : "=v"(zero_v));
         const int wstep = T + 1;                 // words of one chunk
-        const uint2 *__restrict__ wtile =
-            reinterpret_cast<const uint2 *>(words + static_cast<int64_t>(l) * ws * wstep + t) + zero_v;
-        const uint2 *__restrict__ wflag =
-            reinterpret_cast<const uint2 *>(words + static_cast<int64_t>(l) * ws * wstep + T) + zero_v;
+        const int64_t w0 = static_cast<int64_t>(l0) * ws * wstep;
+        const int64_t w1 = has1 ? w0 + ws * wstep : w0;   // a slice pair's second slice
+        const uint2 *__restrict__ wtile = reinterpret_cast<const uint2 *>(words + w0 + t) + zero_v;
+        const uint2 *__restrict__ wflag = reinterpret_cast<const uint2 *>(words + w0 + T) + zero_v;
+        const uint2 *__restrict__ wtile1 = reinterpret_cast<const uint2 *>(words + w1 + t) + zero_v;
+        const uint2 *__restrict__ wflag1 = reinterpret_cast<const uint2 *>(words + w1 + T) + zero_v;
         float4 ph = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         uint2 pr = make_uint2(0u, 0u);           // the tile's word of the chunk, or the hit's ranges
         uint2 pf = make_uint2(0u, 0u);           // 3D with words: the chunk's kFastDiv word
+        uint2 pr1 = make_uint2(0u, 0u), pf1 = make_uint2(0u, 0u);   // the same of a pair's second slice
         // (always inlined, through a local: otherwise the 2D kernels kept the
         // prefetched records in a stack slot and waited for each load at once)
         auto fetch = [&](int gg) __attribute__((always_inline)) {
@@ -427,8 +481,14 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
                 pr = wtile[gg * wstep];
                 if constexpr (D3)
                     pf = wflag[gg * wstep];
+                if constexpr (SP) {
+                    pr1 = wtile1[gg * wstep];
+                    pf1 = wflag1[gg * wstep];
+                }
             } else {
                 pr = rrow[h & rmask];
+                if constexpr (SP)
+                    pr1 = rrow1[h & rmask];
             }
         };
         auto uniform64 = [](uint2 v) {
@@ -447,13 +507,26 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
             uint64_t inside = hi >= 64 ? ~0ull : (1ull << hi) - 1ull;
             if (lo > 0)
                 inside &= ~((1ull << lo) - 1ull);
+            // kept: the hit can vote in this tile (of either slice of a pair);
+            // fast: its quotients take the fast form (in both slices)
             uint64_t K, F;
             if constexpr (W) {
-                K = uniform64(pr) & inside;
+                K = uniform64(pr);
                 F = D3 ? uniform64(pf) : __ballot(ph.w != 0.0f);
+                if constexpr (SP) {
+                    K |= uniform64(pr1);
+                    F &= uniform64(pf1);
+                }
+                K &= inside;
             } else {
-                K = __ballot(in_range(pr.x) || in_range(pr.y)) & inside;
-                F = __ballot(D3 ? (pr.y & kFastDiv) != 0u : ph.w != 0.0f);
+                bool in = in_range(pr.x) || in_range(pr.y);
+                bool fst = D3 ? (pr.y & kFastDiv) != 0u : ph.w != 0.0f;
+                if constexpr (SP) {
+                    in = in || in_range(pr1.x) || in_range(pr1.y);
+                    fst = fst && (pr1.y & kFastDiv) != 0u;
+                }
+                K = __ballot(in) & inside;
+                F = __ballot(fst);
             }
             const uint64_t mf = K & F;
             const uint64_t ms = K & ~F;
@@ -495,7 +568,7 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     // Summed in LDS; the workgroup adds its total to a.pairs when it ends.
     if (a.pairs && lane == 0 && kept_here > 0)
         __hip_atomic_fetch_add(&ts.pairs, static_cast<unsigned long long>(kept_here) *
-                                              static_cast<unsigned long long>(len),
+                                              static_cast<unsigned long long>(has1 ? 2 * len : len),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 
     const int rd = g.row_dwords;
@@ -637,7 +710,29 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
         const int kseg = (rd + SEGS - 1) / SEGS;
         const int w_lo = min(rd, seg * kseg);
         const int w_hi = min(rd, w_lo + kseg);
-        if (rr < len) {
+        if (SP && rr < len) {
+            // slice pairs: each LDS dword holds the cell of both slices; the
+            // uint16 rows of the two slices pair kappa bins 2wd and 2wd + 1
+            uint32_t *dst0 = acc_event + (static_cast<int64_t>(l0) * n_phi + first + rr) * rd;
+            uint32_t *dst1 = dst0 + static_cast<int64_t>(n_phi) * rd;
+            for (int wd = w_lo; wd < w_hi; ++wd) {
+                const uint32_t lo = lds[(2 * wd) * stride + rr];
+                const uint32_t hi = lds[(2 * wd + 1) * stride + rr];
+                votes += (lo & 0xffffu) + (lo >> 16) + (hi & 0xffffu) + (hi >> 16);
+                const uint32_t v0 = (lo & 0xffffu) | (hi << 16);
+                const uint32_t v1 = (lo >> 16) | (hi & 0xffff0000u);
+                if (!atomic_flush) {
+                    dst0[wd] = v0;
+                    if (has1)
+                        dst1[wd] = v1;
+                } else {
+                    if (v0)
+                        atomicAdd(&dst0[wd], v0);
+                    if (has1 && v1)
+                        atomicAdd(&dst1[wd], v1);
+                }
+            }
+        } else if (rr < len) {
             uint32_t *dst = acc_event + (static_cast<int64_t>(l) * n_phi + first + rr) * rd;
             for (int wd = w_lo; wd < w_hi; ++wd) {
                 uint32_t v;
@@ -1301,7 +1396,7 @@ hipError_t launch_vote_single(const GridArgs &g, bool u16, const VoteShape &s, c
         e = launch_zero(acc, g.acc_dwords, stream);
     if (e != hipSuccess)
         return e;
-    dim3 grid(static_cast<unsigned>(a.tiles_per_slice * g.n_d0), static_cast<unsigned>(s.split));
+    dim3 grid(static_cast<unsigned>(a.tiles_per_slice * vote_slice_units(g, u16)), static_cast<unsigned>(s.split));
     return launch_vote(a, u16, false, s, grid, stream);
 }
 
