@@ -77,7 +77,7 @@ struct hough_ctx {
     int device;
     VoteShape shape_single;
     VoteShape shape_batch;
-    int32_t persistent_groups;
+    int32_t cus;                  // compute units of the device (persistent launches)
 
     // sort workspace
     int64_t bound;             // max candidates per event (any first-pass layout)
@@ -388,7 +388,8 @@ hipError_t enqueue_batch(hough_ctx *ctx, hipStream_t cs, const float *x, const f
     if (ce == hipSuccess)
         ce = launch_vote_batch(ctx->g, ctx->u16, fused, vs, vote_inputs(ctx, vs, fused), dd.desc,
                                &dd.hdr->queues, dd.items, ctx->max_items, ctx->work_counter,
-                               ctx->persistent_groups, a, nv, fused ? &w : nullptr, threshold, cs,
+                               ctx->cus * vote_groups_per_cu(vs, ctx->g.n_kappa), a, nv, fused ? &w : nullptr,
+                               threshold, cs,
                                count ? ctx->pairs : nullptr);
     if (ce == hipSuccess && timed)
         ce = hipEventRecord(ctx->ev_vote1, cs);
@@ -458,10 +459,14 @@ hough_status grid_setup(const hough_grid *grid, GridArgs *out) {
     return HOUGH_OK;
 }
 
-int32_t default_tile_rows(const GridArgs &g) {
-    // 64 rows while two such workgroups still fit a CU's LDS (n_kappa <= 256:
-    // each hit is staged half as often; the displaced batch votes 6 % faster),
-    // else 32.  The forward kernels come in 32-row tiles.
+int32_t default_tile_rows(const GridArgs &g, bool u16) {
+    // Slice pairs (uint16 with a d0 axis): 32 rows, three workgroups per CU
+    // (the displaced batch votes 4 % faster than with 64).  Otherwise 64 rows
+    // while two such workgroups still fit a CU's LDS (n_kappa <= 256: each hit
+    // is staged half as often), else 32.  The forward kernels come in 32-row
+    // tiles.
+    if (u16 && g.d0)
+        return 32;
     return (g.n_kappa <= 256 && g.forward == 0) ? 64 : 32;
 }
 
@@ -525,7 +530,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
     hipDeviceProp_t prop{};
     (void)hipGetDeviceProperties(&prop, c->device);
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    const int32_t rows = default_tile_rows(g);
+    const int32_t rows = default_tile_rows(g, u16);
     c->shape_single = VoteShape{rows, 512, u16 ? 1 : 4};
     c->shape_batch = VoteShape{rows, 512, 1};
     if (!vote_shape_supported(c->shape_single, u16, g.n_kappa, g.forward != 0) ||
@@ -533,7 +538,7 @@ hough_status hough_ctx_create(hough_ctx **out, const hough_grid *grid, const hou
         delete c;
         return HOUGH_EINVAL;   // a kappa row too long for an LDS tile
     }
-    c->persistent_groups = cus * 2;
+    c->cus = cus;
     // Tuned shapes for this device, grid and size, if the cache has them.
     if (const char *cache = tune_cache_path(o.tune_cache)) {
         TuneEntry key;
@@ -803,7 +808,7 @@ hough_status hough_vote_batch(hough_ctx *ctx, int32_t n_events, const int64_t *h
     HIP_TRY(launch_prep_batch(ctx->state, ctx->max_events, &dd.hdr->n_events, nv, ctx->work_counter, s));
     HIP_TRY(hit_prep(ctx, vs, false, x, y, hit_off[n_events], nullptr, s));
     HIP_TRY(launch_vote_batch(ctx->g, ctx->u16, false, vs, vote_inputs(ctx, vs, false), dd.desc, &dd.hdr->queues,
-                              dd.items, ctx->max_items, ctx->work_counter, ctx->persistent_groups,
+                              dd.items, ctx->max_items, ctx->work_counter, ctx->cus * vote_groups_per_cu(vs, ctx->g.n_kappa),
                               static_cast<uint32_t *>(acc), nv, nullptr, 0, s));
     return HOUGH_OK;
 }

@@ -171,6 +171,9 @@ size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa);
 // when the grid is outside the range the bound covers.
 bool vote_near_band(const GridArgs &g, float *band, float *off);
 int32_t vote_tiles_per_slice(const GridArgs &g, const VoteShape &s, bool fused);
+// Workgroups of launch shape s that fit one CU at once (LDS and wavefronts):
+// the persistent batch launches that many per CU.
+int32_t vote_groups_per_cu(const VoteShape &s, int32_t n_kappa);
 // Slice units of a vote launch: uint16 grids with a d0 axis take their d0
 // slices in pairs (one LDS tile counts the cells of both), others one at a
 // time.  A launch has units x tiles_per_slice tiles per event.
@@ -184,7 +187,7 @@ int32_t fused_chunk_cap(const GridArgs &g, const VoteShape &s);
 // the grid is rejected).  api.hip.
 hough_status grid_setup(const hough_grid *grid, GridArgs *out);
 // Default tile height of a grid's vote kernels.
-int32_t default_tile_rows(const GridArgs &g);
+int32_t default_tile_rows(const GridArgs &g, bool u16);
 
 hipError_t launch_prep(EventState *state, int32_t n_events, unsigned long long *n_votes,
                        hipStream_t stream);

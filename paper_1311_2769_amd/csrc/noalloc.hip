@@ -109,7 +109,7 @@ extern "C" hough_status hough_event_noalloc(const hough_grid *grid, const float 
     const bool u16 = grid->acc_type == HOUGH_ACC_U16;
     if (u16 && n_hits > 65535)
         return fail(HOUGH_EINVAL, "hough_event_noalloc: uint16 cells hold events of at most 65535 hits");
-    const VoteShape vs{default_tile_rows(g), 512, u16 ? 1 : 4};
+    const VoteShape vs{default_tile_rows(g, u16), 512, u16 ? 1 : 4};
     if (!vote_shape_supported(vs, u16, g.n_kappa, g.forward != 0))
         return fail(HOUGH_EINVAL, "hough_event_noalloc: kappa rows too long for an LDS tile");
     const Layout L = layout(g, n_hits);

@@ -1243,6 +1243,17 @@ size_t vote_lds_bytes(const VoteShape &s, int32_t n_kappa) {
     return (static_cast<size_t>(n_kappa) + 1) * static_cast<size_t>(s.rows) * sizeof(uint32_t);
 }
 
+int32_t vote_groups_per_cu(const VoteShape &s, int32_t n_kappa) {
+    // workgroups of shape s resident on one CU: LDS (in 1 KiB granules, the
+    // dynamic tile plus the static scratch) and 32 wavefronts per CU
+    const size_t st = s.threads <= 256 ? sizeof(TileScratch<256>)
+                      : s.threads <= 512 ? sizeof(TileScratch<512>) : sizeof(TileScratch<1024>);
+    const size_t lds = (vote_lds_bytes(s, n_kappa) + st + 1023) / 1024 * 1024;
+    const int by_lds = static_cast<int>((160u * 1024u) / lds);
+    const int by_waves = 32 / std::max(1, s.threads / 64);
+    return std::max(1, std::min(by_lds, by_waves));
+}
+
 bool vote_shape_supported(const VoteShape &s, bool u16, int32_t n_kappa, bool forward) {
     if (!pick_vote(u16, false, false, forward, s.rows, s.threads))
         return false;
