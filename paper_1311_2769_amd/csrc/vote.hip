@@ -6,12 +6,14 @@
 //
 // Layout.  The accumulator of one d0 slice is cut into tiles of 32, 64 or 128
 // consecutive phi0 rows.  A workgroup owns one tile as a private LDS
-// accumulator.  Each lane owns one phi0 row (two for 128-row tiles) and keeps
-// that row's cos/sin and the slice's d0 in registers; a wavefront evaluates
-// 64 rows of one hit, or 32 rows of two hits, per instruction.  The LDS tile
-// is kappa-major (dword (kappa, row) at kappa*rows + row): lanes are rows, so
-// the LDS atomics of one instruction fall in distinct banks whatever kappa
-// bins the hit produces.  Every lane adds on every evaluation: a lane whose
+// accumulator.  A lane keeps the cos/sin of its phi0 rows and the slice's d0
+// in registers.  2D: 16 lanes span the rows of a 32- or 64-row tile (32 of a
+// 128-row one), each lane taking every hit for 2-4 rows, so a wavefront
+// evaluates four hits (two) per instruction and each staged record read
+// serves several rows.  3D: a lane owns one row, 64 rows of one hit or 32
+// rows of two hits per instruction.  The LDS tile is kappa-major (dword
+// (kappa, row) at kappa*rows + row): the lanes of one hit are distinct rows,
+// so its LDS atomics fall in distinct banks whatever kappa bins it produces.  Every lane adds on every evaluation: a lane whose
 // hit casts no vote in its row adds into one spare kappa column past the
 // grid, which keeps the loop free of branches.  The finished tile is flushed
 // to HBM, lanes again across rows -- no global atomics on the accumulator --
@@ -106,7 +108,7 @@ struct VoteArgs {
 // slots of slack after that for the reads a lane group issues past the end of
 // a list (values that are never used).
 constexpr int kChunk = 64;
-constexpr int kCarryMax = 8;                       // 4 x (hits per wavefront instruction)
+constexpr int kCarryMax = 16;                      // 4 x (hits per wavefront instruction, at most 4)
 constexpr int kRegionSlow = kChunk + kCarryMax;
 constexpr int kRegion = kRegionSlow + kCarryMax;
 
@@ -140,7 +142,10 @@ template <bool U16, bool D3, int ROWS, int NT, bool FUSED, bool FWD>
 __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begin, int64_t h_end,
                           uint32_t *__restrict__ acc_event, bool atomic_flush, unsigned long long *n_votes,
                           uint32_t *lds, TileScratch<NT> &ts) {
-    constexpr int RL = ROWS < 64 ? ROWS : 64;   // lanes across rows
+    // Lanes across rows.  2D: 16 (32 for 128-row tiles), so that a lane
+    // takes every staged hit for 2-4 rows and one record read serves them
+    // all; 3D: one row per lane (slice pairs measured slower with several).
+    constexpr int RL = D3 ? (ROWS < 64 ? ROWS : 64) : (ROWS / 4 < 16 ? 16 : ROWS / 4);
     constexpr int HPW = 64 / RL;                // hits per wavefront instruction
     constexpr int RPT = ROWS / RL;              // rows per lane
     constexpr int NW = NT / 64;
