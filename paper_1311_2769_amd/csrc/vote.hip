@@ -1024,9 +1024,16 @@ __global__ __launch_bounds__(256) void hit_prep_kernel(PrepArgs p) {
         }
         const int T = p.tiles;
         const uint64_t m = live ? (range_bits(out.x, T) | range_bits(out.y & ~kFastDiv, T)) : 0ull;
+        const uint32_t m_lo = static_cast<uint32_t>(m), m_hi = static_cast<uint32_t>(m >> 32);
+        // lane tt keeps tile tt's ballot (32-bit halves: no 64-bit shifts)
         uint64_t mine = __ballot(live && (out.y & kFastDiv) != 0u);
-        for (int tt = 0; tt < T; ++tt) {
-            const uint64_t w = __ballot(((m >> tt) & 1ull) != 0ull);
+        const int t_lo = min(T, 32);
+        for (int tt = 0; tt < t_lo; ++tt) {
+            const uint64_t w = __ballot(((m_lo >> tt) & 1u) != 0u);
+            mine = lane == tt ? w : mine;
+        }
+        for (int tt = 32; tt < T; ++tt) {
+            const uint64_t w = __ballot(((m_hi >> (tt - 32)) & 1u) != 0u);
             mine = lane == tt ? w : mine;
         }
         uint64_t *words = reinterpret_cast<uint64_t *>(p.ranges);
@@ -1078,6 +1085,24 @@ __global__ __launch_bounds__(256) void hit_prep_kernel(PrepArgs p) {
         if (r_ok) {
             const float m = 1e-5f + 0x1.0p-18f * (2.0f * fabsf(p.dlo) + 2.0f * fabsf(p.dhi)) * inv_r;
             out = arcs(p.dlo * inv_r - m, p.dhi * inv_r + m);
+        }
+        emit(0, out);
+        return;
+    }
+    if (!p.d0) {
+        // 2D (d = 0): the interval below is [-s - m, s + m], s = K r2 / (2r),
+        // so one arcsine serves both ends (asin(-v) = -asin(v) up to its
+        // error, which the arc widening covers)
+        uint2 out = make_uint2(kAllTiles, 0u);
+        if (r_ok) {
+            const float a = K * r2;
+            const float shi = a * half_inv_r + (1e-5f + 0x1.0p-18f * a * inv_r);
+            if (isfinite(shi) && (fwd || shi < 1.0f)) {
+                const float ahi = arc_asin(fminf(shi, 1.0f));
+                const float pm = ph - pi;
+                out = make_uint2(tile_range(pack_arc(ph - ahi, ph + ahi, p.n_phi, sc), p),
+                                 fwd ? 0u : tile_range(pack_arc(pm - ahi, pm + ahi, p.n_phi, sc), p));
+            }
         }
         emit(0, out);
         return;
