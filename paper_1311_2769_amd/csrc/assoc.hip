@@ -28,8 +28,9 @@
 // [b_p - 1, b_p + 1]: the bitmap is read over [min b_p - 1, max b_p + 1], and
 // each candidate found there is kept when some |b_p - kc| <= 1 -- so each
 // (candidate, hit) pair is found once, by the thread that owns the
-// candidate's row.  Each wavefront gathers its pairs in LDS and reserves room
-// in the output with one atomic per kAssocFlush pairs.
+// candidate's row.  Each wavefront gathers its pairs (cell, hit) in LDS and
+// reserves room in the output with one atomic per kAssocFlush pairs, looking
+// up the candidate index of each cell as it writes them out.
 #pragma clang fp contract(off)
 
 #include <algorithm>
@@ -136,7 +137,11 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
     const int lane = threadIdx.x & 63;
     int2 *buf = staged[threadIdx.x >> 6];
     int fill = 0;                      // wave-uniform
-    // move the staged pairs to the output: one reservation for all of them
+    // move the staged pairs to the output: one reservation for all of them.
+    // A staged pair holds the candidate's cell; its index comes from the
+    // cell map here, one lookup per lane, so that the scan loop below never
+    // waits on a load.  (A cell whose bitmap bit is set is a candidate's: the
+    // map holds its index + 1 there.)
     auto flush = [&]() {
         __builtin_amdgcn_wave_barrier();
         unsigned long long base = 0;
@@ -147,7 +152,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
             const int64_t slot = static_cast<int64_t>(base) + i;
             if (slot < a.cap) {
                 const int2 p = buf[i];
-                a.pairs[2 * slot] = p.x;
+                a.pairs[2 * slot] = a.map[p.x] - 1;
                 a.pairs[2 * slot + 1] = p.y;
             }
         }
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
                 }
                 while (__ballot(pend != 0u)) {
                     bool emit = false;
-                    int cand = 0;
+                    int cell = 0;
                     if (pend != 0u) {
                         const int kc = base + (__ffs(pend) - 1);
                         pend &= pend - 1u;
@@ -318,14 +323,12 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
                                 near |= static_cast<uint32_t>(B2[r + t] - kc) <= 2u;
                             }
                         }
-                        if (near) {
-                            cand = a.map[l * plane + static_cast<int64_t>(jc) * nk + kc] - 1;
-                            emit = cand >= 0;
-                        }
+                        emit = near;
+                        cell = static_cast<int>(l * plane + static_cast<int64_t>(jc) * nk + kc);
                     }
                     const uint64_t m = __ballot(emit);
                     if (emit)
-                        buf[fill + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cand, h);
+                        buf[fill + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cell, h);
                     fill += __popcll(m);
                     if (fill > kAssocFlush)
                         flush();
