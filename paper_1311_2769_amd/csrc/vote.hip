@@ -917,6 +917,45 @@ struct PrepArgs {
                                 // fast division), or nullptr when the host has checked the table
 };
 
+// Transpose of the 64 x 64 bit matrix whose row L is lane L's m: lane t
+// gets bit L set exactly when bit t of lane L's m is set.  Butterfly steps
+// j = 32, 16, .., 1 swap the off-diagonal j x j blocks of every 2j x 2j
+// block: a lane with bit j clear keeps its columns with bit j clear and takes
+// its partner's (lane ^ j) as the columns above; a lane with bit j set keeps
+// the columns with bit j set and takes its partner's from below.
+template <int J>
+__device__ __forceinline__ void transpose_step(uint32_t &lo, uint32_t &hi, int lane) {
+    // ds_swizzle in bit mode: lane ^ J within each 32-lane half
+    constexpr int kPattern = 0x1f | (J << 10);
+    // the columns with bit J clear, within each 32-bit word
+    constexpr uint32_t kKeep = J == 16 ? 0x0000ffffu : J == 8 ? 0x00ff00ffu : J == 4 ? 0x0f0f0f0fu
+                               : J == 2 ? 0x33333333u : 0x55555555u;
+    const uint32_t ylo = static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(static_cast<int>(lo), kPattern));
+    const uint32_t yhi = static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(static_cast<int>(hi), kPattern));
+    const bool up = (lane & J) != 0;
+    const uint32_t keep = up ? ~kKeep : kKeep;
+    const uint32_t slo = up ? ylo >> J : ylo << J;
+    const uint32_t shi = up ? yhi >> J : yhi << J;
+    lo = (lo & keep) | (slo & ~keep);
+    hi = (hi & keep) | (shi & ~keep);
+}
+
+__device__ __forceinline__ uint64_t lane_transpose(uint64_t m, int lane) {
+    uint32_t lo = static_cast<uint32_t>(m), hi = static_cast<uint32_t>(m >> 32);
+    const uint32_t plo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(lo), 32));
+    const uint32_t phi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), 32));
+    if (lane & 32)
+        lo = phi;
+    else
+        hi = plo;
+    transpose_step<16>(lo, hi, lane);
+    transpose_step<8>(lo, hi, lane);
+    transpose_step<4>(lo, hi, lane);
+    transpose_step<2>(lo, hi, lane);
+    transpose_step<1>(lo, hi, lane);
+    return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+}
+
 // The tiles of a cyclic range as bits of a mask (T <= kMaskTiles).
 __device__ __forceinline__ uint64_t range_bits(uint32_t r, int T) {
     const int cnt = static_cast<int>((r >> 16) & 0x7fffu);
@@ -1024,18 +1063,10 @@ __global__ __launch_bounds__(256) void hit_prep_kernel(PrepArgs p) {
         }
         const int T = p.tiles;
         const uint64_t m = live ? (range_bits(out.x, T) | range_bits(out.y & ~kFastDiv, T)) : 0ull;
-        const uint32_t m_lo = static_cast<uint32_t>(m), m_hi = static_cast<uint32_t>(m >> 32);
-        // lane tt keeps tile tt's ballot (32-bit halves: no 64-bit shifts)
-        uint64_t mine = __ballot(live && (out.y & kFastDiv) != 0u);
-        const int t_lo = min(T, 32);
-        for (int tt = 0; tt < t_lo; ++tt) {
-            const uint64_t w = __ballot(((m_lo >> tt) & 1u) != 0u);
-            mine = lane == tt ? w : mine;
-        }
-        for (int tt = 32; tt < T; ++tt) {
-            const uint64_t w = __ballot(((m_hi >> (tt - 32)) & 1u) != 0u);
-            mine = lane == tt ? w : mine;
-        }
+        // lane t < T takes tile t's word (the transposed masks), lane T the flags
+        const uint64_t flags = __ballot(live && (out.y & kFastDiv) != 0u);
+        const uint64_t tw = lane_transpose(m, lane);
+        const uint64_t mine = lane == T ? flags : tw;
         uint64_t *words = reinterpret_cast<uint64_t *>(p.ranges);
         if (lane <= T)
             words[(static_cast<int64_t>(l) * p.range_stride + (i >> 6)) * (T + 1) + lane] = mine;
