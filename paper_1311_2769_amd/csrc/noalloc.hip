@@ -109,7 +109,12 @@ extern "C" hough_status hough_event_noalloc(const hough_grid *grid, const float 
     const bool u16 = grid->acc_type == HOUGH_ACC_U16;
     if (u16 && n_hits > 65535)
         return fail(HOUGH_EINVAL, "hough_event_noalloc: uint16 cells hold events of at most 65535 hits");
-    const VoteShape vs{default_tile_rows(g, u16), 512, u16 ? 1 : 4};
+    // A 32-row d0-grid tile of at most 512 threads is compiled for three
+    // workgroups per CU and keeps a few loop-invariant values in scratch,
+    // which the runtime may have to grow on its first launch: this entry
+    // point takes 1,024 threads there, whose kernel needs no scratch.
+    const int32_t rows = default_tile_rows(g, u16);
+    const VoteShape vs{rows, (g.d0 && rows <= 32) ? 1024 : 512, u16 ? 1 : 4};
     if (!vote_shape_supported(vs, u16, g.n_kappa, g.forward != 0))
         return fail(HOUGH_EINVAL, "hough_event_noalloc: kappa rows too long for an LDS tile");
     const Layout L = layout(g, n_hits);

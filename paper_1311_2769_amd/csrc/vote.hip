@@ -329,6 +329,14 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     auto bin_exact = [&](float num, float den, int i, bool valid, auto bits) -> int {
         return bin_of(D3 ? kf_exact_3d(num, den, kmin, kscale) : kf_exact_2d(num, den, kmin, kscale), i, valid, bits);
     };
+    // 3D redo: num and den formed again from the record with bin_approx's
+    // operations (the same fp32 values), so that they need not stay live
+    // across the approximate bins of both hits and slices
+    auto bin_exact_3d = [&](const float4 &h, int i, bool valid, auto bits, auto sl) -> int {
+        const float u = h.y * c[i] - h.x * s[i];
+        const float3 sc = sconst(sl);
+        return bin_exact(u - sc.x, (h.z - sc.y * u) + sc.z, i, valid, bits);
+    };
     auto vote = [&](int kk, int i, uint32_t one) { lds_add(&lds[kk * stride + rowoff[i]], one); };
     // Evaluate and vote two hits of this lane group (valid: the hit exists):
     // fast 0 the division operator, 1 the hoisted exact quotient, 2 the
@@ -365,15 +373,22 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
                 }
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                    if (fa[i])
-                        ka[i] = bin_exact(na[i], da[i], i, va, bits);
-                    if (fb[i])
-                        kb[i] = bin_exact(nb[i], db[i], i, vb, bits);
-                    if constexpr (SP) {
-                        if (fa1[i])
-                            ka1[i] = bin_exact(na1[i], da1[i], i, va, bits);
-                        if (fb1[i])
-                            kb1[i] = bin_exact(nb1[i], db1[i], i, vb, bits);
+                    if constexpr (D3) {
+                        if (fa[i])
+                            ka[i] = bin_exact_3d(ha, i, va, bits, S0{});
+                        if (fb[i])
+                            kb[i] = bin_exact_3d(hb, i, vb, bits, S0{});
+                        if constexpr (SP) {
+                            if (fa1[i])
+                                ka1[i] = bin_exact_3d(ha, i, va, bits, S1{});
+                            if (fb1[i])
+                                kb1[i] = bin_exact_3d(hb, i, vb, bits, S1{});
+                        }
+                    } else {
+                        if (fa[i])
+                            ka[i] = bin_exact(na[i], da[i], i, va, bits);
+                        if (fb[i])
+                            kb[i] = bin_exact(nb[i], db[i], i, vb, bits);
                     }
                 }
             }
@@ -773,8 +788,19 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
     lds_barrier();   // the LDS tile and scratch are reused by the next item
 }
 
+// Waves per SIMD the compiler must leave room for.  The 32-row d0-grid tiles
+// take about 48 KiB of LDS, so three workgroups of 512 threads (six waves
+// per SIMD) fit a CU when the kernel keeps to 80 VGPRs; left alone it took
+// 114 and two fitted (the displaced batch's vote 2.15 -> 2.02 ms with
+// three).  Other shapes are bound by LDS first and keep the default.
+template <bool D3, int ROWS, int NT>
+constexpr int vote_min_waves() {
+    return (D3 && ROWS <= 32 && NT <= 512) ? 6 : 1;
+}
+
 template <bool U16, bool D3, int ROWS, int NT, bool FUSED, bool FWD>
-__global__ __launch_bounds__(NT) void vote_kernel(VoteArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vote_min_waves<D3, ROWS, NT>(), 8)))
+void vote_kernel(VoteArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ TileScratch<NT> ts;
     const int T = a.tiles_per_slice;
