@@ -792,10 +792,15 @@ __device__ void vote_tile(const VoteArgs &a, int e, int l, int t, int64_t h_begi
 // take about 48 KiB of LDS, so three workgroups of 512 threads (six waves
 // per SIMD) fit a CU when the kernel keeps to 80 VGPRs; left alone it took
 // 114 and two fitted (the displaced batch's vote 2.15 -> 2.02 ms with
-// three).  Other shapes are bound by LDS first and keep the default.
+// three).  A 2D workgroup of 1,024 threads holds its CU's LDS alone; kept to
+// 96 VGPRs (five waves per SIMD, 127 left alone, no spills) it leaves room
+// for the waves of the kernels that run between two votes -- the next
+// batch's hit_prep, the sort passes -- which then start while its last
+// items finish (batched 2D step 1.289 -> 1.270 ms).  Other shapes keep the
+// default.
 template <bool D3, int ROWS, int NT>
 constexpr int vote_min_waves() {
-    return (D3 && ROWS <= 32 && NT <= 512) ? 6 : 1;
+    return (D3 && ROWS <= 32 && NT <= 512) ? 6 : (!D3 && NT == 1024) ? 5 : 1;
 }
 
 template <bool U16, bool D3, int ROWS, int NT, bool FUSED, bool FWD>
