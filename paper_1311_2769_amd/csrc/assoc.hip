@@ -290,11 +290,6 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
             const int vmax = max(max(cmax[r], cmax[r + 1]), cmax[r + 2]);
             const uint32_t vmin_u = min(min(cmin[r], cmin[r + 1]), cmin[r + 2]);
             const bool any = jc < np && vmax >= 0;
-            // When the window's bins span at most 3, the intervals [b - 1,
-            // b + 1] overlap or touch and their union is the whole scan
-            // range [min b - 1, max b + 1]: every candidate found is near
-            // and the test below is skipped.
-            const bool dense = any && vmax - static_cast<int>(vmin_u) <= 3;
             // candidates of row (l, jc) in [min b - 1, max b + 1] (b the
             // unbiased bins), 32 bins at a time
             const int k_lo = any ? max(static_cast<int>(vmin_u) - 2, 0) : 0;
@@ -319,15 +314,13 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(AssocArgs a) {
                         const int kc = base + (__ffs(pend) - 1);
                         pend &= pend - 1u;
                         // kept when a window bin is within one of kc
-                        bool near = dense;
-                        if (!near) {
+                        bool near = false;
 #pragma unroll
-                            for (int t = 0; t < 3; ++t) {
-                                near |= static_cast<uint32_t>(B1[r + t] - kc) <= 2u;
-                                if constexpr (D3) {
-                                    near |= static_cast<uint32_t>(B0[r + t] - kc) <= 2u;
-                                    near |= static_cast<uint32_t>(B2[r + t] - kc) <= 2u;
-                                }
+                        for (int t = 0; t < 3; ++t) {
+                            near |= static_cast<uint32_t>(B1[r + t] - kc) <= 2u;
+                            if constexpr (D3) {
+                                near |= static_cast<uint32_t>(B0[r + t] - kc) <= 2u;
+                                near |= static_cast<uint32_t>(B2[r + t] - kc) <= 2u;
                             }
                         }
                         emit = near;
