@@ -54,10 +54,12 @@
 // no-ops when every operand is in the range of vote_math.h (rcp, two
 // refinement FMAs, then quot_apply): 8 instead of 11 operations.
 //
-// uint16 accumulators count in int32 LDS cells like int32 ones and are packed
-// two cells per dword (even kappa bin in the low half) when the tile is
-// flushed; counts fit because a cell receives at most one vote per hit and
-// u16 events hold at most 65535 hits.
+// uint16 accumulators of a 2D grid count in int32 LDS cells like int32 ones
+// and are packed two cells per dword (even kappa bin in the low half) when
+// the tile is flushed; on a d0 grid one LDS dword counts the same cell of two
+// slices (slice pairs, below) and the flush repacks them the same way.
+// Counts fit because a cell receives at most one vote per hit and u16 events
+// hold at most 65535 hits.
 //
 // Fused peak search (2D int32 batches).  Tiles then overlap by two rows: a
 // tile votes S interior rows plus one halo row on each side, finds the local
