@@ -89,12 +89,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_digest():
+def code_text(src):
+    """Source text without comments and blank lines: an edit of a comment
+    leaves the compiled kernel, and so this text, unchanged.  None of the
+    kernel sources holds a string literal with a comment marker in it."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
+def kernel_digest(read=None):
+    """SHA-256 of the vote kernel's sources, comments removed (code_text);
+    read(name) gives a source's text (default: the file in csrc/)."""
     import hashlib
+    if read is None:
+        def read(name):
+            with open(os.path.join(ROOT, "paper_1311_2769_amd", "csrc", name)) as f:
+                return f.read()
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1311_2769_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        h.update(code_text(read(name)).encode())
     return h.hexdigest()
 
 
